@@ -1,0 +1,216 @@
+/*
+ * ed.h -- exact output-sensitive edit distance on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libed.so.  Plain pointers and sizes only; no C++ or framework types
+ * cross this boundary and no exception leaves the library.
+ *
+ * The method is the breadth-first (Landau-Vishkin) frontier of "Efficient
+ * Parallel Output-Sensitive Edit Distance" (Ding, Dong, Gu, Liu, Sun; ESA 2023):
+ * round t computes, for every diagonal i = x - y in [-t, t], the furthest row
+ * reachable with t edits, from the three neighbours of round t-1, followed by a
+ * slide along the diagonal by a longest-common-prefix (LCP) query
+ * (section 3.1, Algorithm 1; appendix A).  The LCP queries run on one of two
+ * engines:
+ *   ED_ENGINE_DIRECT  64-bit word XOR / count-trailing-zeros comparison of the
+ *                     strings (the LCP definition of section 2, with the
+ *                     leading-characters shortcut of section 5.1);
+ *   ED_ENGINE_HASH    prefix-hash tables T[j] = h(S[0..jb)) mod 2^61-1
+ *                     (sections 3.2 and 3.3, Algorithm 2) probed by a
+ *                     wavefront-parallel galloping and 64-ary search; every
+ *                     answer is confirmed by a direct comparison of the
+ *                     characters around the reported mismatch, and a detected
+ *                     hash collision falls back to the direct engine.
+ *
+ * Coordinates: strings are 0-based byte arrays A[0..n), B[0..m); the result is
+ * the Levenshtein distance (minimum number of unit insertions, deletions and
+ * substitutions; sections 1 and 2).  n and m must be below ED_MAX_LEN.
+ *
+ * Threading: every call on one context is serialised by the context's mutex.
+ * Streams: `hip_stream` arguments are hipStream_t values (NULL = the null
+ * stream).  A result written to host memory is valid when the call returns.
+ */
+#ifndef ED_H
+#define ED_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define ED_OK 0
+#define ED_EINVAL (-1)     /* bad argument: NULL with length > 0, length >= ED_MAX_LEN,
+                              a character > 3 with pack_bits = 2, bad option value */
+#define ED_ENOMEM (-2)     /* device or host allocation failed */
+#define ED_EDEVICE (-3)    /* a HIP call failed; ed_last_error() has the detail */
+#define ED_ECOLLISION (-4) /* reserved for a certified hash mode */
+#define ED_EBUSY (-5)      /* serving: host queue full */
+#define ED_EINTERNAL (-6)  /* an internal consistency check failed (a bug) */
+
+#define ED_MAX_LEN ((uint64_t)2147418112u) /* 2^31 - 2^16 characters */
+
+/* ---- options ------------------------------------------------------------ */
+#define ED_ENGINE_DIRECT 0u
+#define ED_ENGINE_HASH 1u
+
+#define ED_FLAG_DEBUG_DUMP 1u  /* keep per-round frontier rows (see ed_distance_dump) */
+#define ED_FLAG_NO_PHASE_A 2u  /* run every round grid-wide (skip the one-workgroup phase) */
+#define ED_FLAG_SHUFFLE 4u     /* batch: permute the work order with hash_seed (race test) */
+
+typedef struct ed_options {
+    uint32_t engine;    /* ED_ENGINE_DIRECT or ED_ENGINE_HASH */
+    uint32_t pack_bits; /* 0 = automatic (2-bit when every character is 0..3), 2 or 8 */
+    uint32_t block;     /* hash block size b (power of two, 1..4096); 0 = 32 */
+    uint32_t flags;     /* ED_FLAG_* */
+    uint64_t hash_seed; /* the hash base r is derived from this seed (see ed_hash_base) */
+    /* tuning knobs; 0 = the library default or the autotuned value */
+    uint32_t lds_rounds;   /* rounds kept in one workgroup's LDS before going grid-wide */
+    uint32_t lane_words;   /* words compared per lane before a wave takes over an LCP */
+    uint32_t grid_blocks;  /* workgroups of the persistent kernels */
+    uint32_t init_rows;    /* initial frontier capacity in diagonals per side (grown on demand) */
+} ed_options;
+
+/* Fills *opt with the defaults: direct engine, automatic packing, b = 32,
+ * seed 0x5EED, no flags, automatic tuning knobs. */
+void ed_default_options(ed_options *opt);
+
+/* Base r of the polynomial hash for a seed: one splitmix64 output z of
+ * (seed + 0x9E3779B97F4A7C15), then r = 2^20 + z mod (2^61 - 1 - 2^21). */
+uint64_t ed_hash_base(uint64_t seed);
+
+/* ---- context -------------------------------------------------------------- */
+typedef struct ed_ctx ed_ctx;
+typedef struct ed_pair ed_pair;
+
+/* Creates a context on HIP device `device`.  opt may be NULL (defaults).
+ * Errors: ED_EINVAL (bad device or options), ED_EDEVICE, ED_ENOMEM. */
+int ed_init(ed_ctx **out, int device, const ed_options *opt);
+
+/* Replaces the context's options (pairs prepared later use them). */
+int ed_set_options(ed_ctx *ctx, const ed_options *opt);
+int ed_get_options(ed_ctx *ctx, ed_options *opt);
+
+/* Releases the context and every device buffer it owns.  Pairs prepared on it
+ * must be released first. */
+int ed_shutdown(ed_ctx *ctx);
+
+/* ---- single pair ------------------------------------------------------------ */
+/*
+ * Copies A[0..n) and B[0..m) into buffers owned by a new pair, detects the
+ * alphabet (bitwise OR of all characters; 2-bit packing when it is <= 3 and
+ * pack_bits is 0 or 2), packs, and -- for the hash engine -- builds the prefix
+ * tables T_A, T_B of section 3.3.  A and B are device pointers when
+ * inputs_on_device != 0, host pointers otherwise; the caller keeps ownership
+ * and may free them once `hip_stream` has synchronised.  A may be NULL iff
+ * n = 0, B iff m = 0.  The work is queued on `hip_stream`; with pack_bits = 2
+ * the call synchronises to report ED_EINVAL for characters above 3.
+ * Errors: ED_EINVAL, ED_ENOMEM, ED_EDEVICE.
+ */
+int ed_prepare(ed_ctx *ctx, const uint8_t *A, uint64_t n, const uint8_t *B, uint64_t m,
+               int inputs_on_device, void *hip_stream, ed_pair **out);
+
+/* Frees the pair's device buffers. */
+int ed_release(ed_pair *pair);
+
+/*
+ * Edit distance of a prepared pair.  All rounds of the frontier run in one
+ * persistent launch (device-wide barriers between rounds); the launch is
+ * repeated only when the frontier outgrows its buffer.  With k_max >= 0 the
+ * search stops after round k_max and reports k_max + 1 if the distance is
+ * larger (the band |x - y| <= k of section 3.1).  Synchronous on hip_stream.
+ */
+int ed_distance(ed_ctx *ctx, ed_pair *pair, int64_t k_max, uint64_t *k_out, void *hip_stream);
+
+/*
+ * As ed_distance, and also copies the frontier of every round to `rows`
+ * (host int32 array): row t (t = 0..k) starts at index t*t and holds the 2t+1
+ * entries f_t[-t..t]; a diagonal without a cell holds ED_NONE.  Needs
+ * (k+1)^2 <= rows_cap, else ED_EINVAL after computing k.
+ */
+#define ED_NONE (-(1 << 30))
+int ed_distance_dump(ed_ctx *ctx, ed_pair *pair, int64_t k_max, uint64_t *k_out, int32_t *rows,
+                     uint64_t rows_cap, void *hip_stream);
+
+/* ---- batch ---------------------------------------------------------------- */
+/*
+ * Edit distances of `count` prepared pairs in one persistent launch: the
+ * workgroups take (pair, diagonal-chunk) work from a device queue, largest
+ * pairs first.  k_out[i] and status_out[i] (either may be NULL) receive each
+ * pair's result; the return value is the first error, or ED_OK.
+ */
+int ed_batch(ed_ctx *ctx, ed_pair *const *pairs, uint64_t count, int64_t k_max, uint64_t *k_out,
+             int32_t *status_out, void *hip_stream);
+
+/* ---- introspection ---------------------------------------------------------- */
+typedef struct ed_stats {
+    uint64_t n, m;
+    uint32_t bits_per_char;  /* 2 or 8, as detected */
+    uint32_t engine;
+    uint64_t rounds;          /* k of the last ed_distance (or batch) */
+    uint64_t updates;         /* diagonal updates over all rounds */
+    uint64_t lcp_chars;       /* sum of all slides */
+    uint64_t wave_lcps;       /* LCPs handed from a lane to a whole wave */
+    uint64_t grid_lcps;       /* LCPs handed to the whole grid */
+    uint64_t hash_queries;    /* LCPs answered by the hash engine */
+    uint64_t hash_probes;     /* hash equality tests */
+    uint64_t collisions;      /* detected collisions (fell back to the direct engine) */
+    double collision_bound;   /* union bound on an undetected collision for the last run */
+    uint64_t launches;        /* kernel launches of the last ed_distance */
+    double ns_prepare, ns_distance; /* host wall time of the last calls */
+} ed_stats;
+
+int ed_pair_stats(const ed_pair *pair, ed_stats *out);
+
+/* ---- debug read-backs (used by the tests) ------------------------------------ */
+#define ED_BUF_PACKED2 0 /* 2-bit words, char j at bits [2(j mod 32), +2) of word j/32 */
+#define ED_BUF_BYTES 1   /* 8-bit copy (only when bits_per_char = 8) */
+#define ED_BUF_TABLE 2   /* prefix table, floor(len/b) + 1 uint64 entries */
+/* Copies a pair buffer of string `which` (0 = A, 1 = B) to host memory `out`
+ * (cap bytes); *len_out receives the byte length of the valid part. */
+int ed_pair_buffer(ed_ctx *ctx, const ed_pair *pair, int which, int kind, void *out, uint64_t cap,
+                   uint64_t *len_out);
+
+/* Runs the pair's LCP engine on `count` queries (x[i], y[i]) (host arrays) and
+ * writes LCP(A, B, x[i], y[i]) to out[i].  engine overrides the prepared
+ * engine when it is 0 or 1 (1 needs tables), or uses it when -1.  Each query
+ * runs on one wavefront, through the same lane, wave and hash code as the
+ * frontier kernels. */
+int ed_debug_lcp(ed_ctx *ctx, ed_pair *pair, int engine, const int64_t *x, const int64_t *y,
+                 uint64_t count, int64_t *out, void *hip_stream);
+
+/* ---- serving ---------------------------------------------------------------- */
+typedef struct ed_server ed_server;
+typedef struct ed_result {
+    uint64_t tag;
+    uint64_t k;
+    int32_t status;
+    int32_t pad;
+    uint64_t t_arrive_ns; /* submit time (CLOCK_MONOTONIC) */
+    uint64_t t_done_ns;   /* completion time */
+} ed_result;
+
+/* Opens a request loop on the context: requests are admitted while their
+ * device bytes fit in hbm_budget_bytes and a slot is free (max_slots); admitted
+ * requests advance together in shared launches, and finished slots are refilled
+ * between launches (continuous batching). */
+int ed_serve_open(ed_ctx *ctx, uint64_t hbm_budget_bytes, uint32_t max_slots, ed_server **out);
+/* Copies the strings (host memory) and queues the request.  ED_EBUSY if the
+ * host queue is full; ED_ENOMEM if the request alone exceeds the budget. */
+int ed_serve_submit(ed_server *srv, const uint8_t *A, uint64_t n, const uint8_t *B, uint64_t m,
+                    uint64_t tag);
+/* Moves up to max finished results into out; *got receives their number. */
+int ed_serve_poll(ed_server *srv, ed_result *out, uint32_t max, uint32_t *got);
+/* Blocks until every submitted request has finished. */
+int ed_serve_drain(ed_server *srv);
+int ed_serve_close(ed_server *srv);
+
+/* ---- errors ----------------------------------------------------------------- */
+const char *ed_strerror(int status);
+/* Detail of the last error on the calling thread ("" if none). */
+const char *ed_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ED_H */

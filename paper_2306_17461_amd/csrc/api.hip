@@ -1,0 +1,759 @@
+// Host side of libed.so: the C ABI declared in include/ed.h.
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ed.h"
+#include "internal.h"
+#include "host.h"
+
+using namespace ed;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+void ed::set_error(const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            ed::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                          __LINE__);                                                     \
+            return ED_EDEVICE;                                                           \
+        }                                                                                \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// host-side arithmetic mod 2^61-1 (powers of the base for the kernels)
+// ---------------------------------------------------------------------------
+static uint64_t hmul(uint64_t a, uint64_t b) {
+    unsigned __int128 p = static_cast<unsigned __int128>(a) * b;
+    uint64_t lo = static_cast<uint64_t>(p) & kP;
+    uint64_t hi = static_cast<uint64_t>(p >> 61);
+    uint64_t s = lo + hi;
+    s = (s & kP) + (s >> 61);
+    return s >= kP ? s - kP : s;
+}
+
+static uint64_t hpow(uint64_t r, uint64_t e) {
+    uint64_t acc = 1, b = r;
+    while (e) {
+        if (e & 1) acc = hmul(acc, b);
+        b = hmul(b, b);
+        e >>= 1;
+    }
+    return acc;
+}
+
+uint64_t ed_hash_base(uint64_t seed) {
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    const uint64_t span = kP - (1ull << 21);
+    return (1ull << 20) + z % span;
+}
+
+// ---------------------------------------------------------------------------
+// device memory pool: freed blocks are kept per rounded size and reused
+// ---------------------------------------------------------------------------
+static size_t round_size(size_t n) {
+    if (n < 4096) return 4096;
+    // 1/8-octave classes above 4 KiB
+    size_t p = 4096;
+    while (p < n) p <<= 1;
+    const size_t step = p >> 3;
+    size_t r = (p >> 1);
+    while (r < n) r += step;
+    return r;
+}
+
+void* DevPool::get(size_t bytes) {
+    const size_t sz = round_size(bytes);
+    auto it = free_.find(sz);
+    if (it != free_.end() && !it->second.empty()) {
+        void* p = it->second.back();
+        it->second.pop_back();
+        cached_ -= sz;
+        live_[p] = sz;
+        return p;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, sz) != hipSuccess) {
+        (void)hipGetLastError();
+        trim();
+        if (hipMalloc(&p, sz) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+    }
+    live_[p] = sz;
+    return p;
+}
+
+void DevPool::put(void* p) {
+    if (!p) return;
+    auto it = live_.find(p);
+    if (it == live_.end()) return;
+    free_[it->second].push_back(p);
+    cached_ += it->second;
+    live_.erase(it);
+}
+
+void DevPool::trim() {
+    for (auto& kv : free_)
+        for (void* p : kv.second) (void)hipFree(p);
+    free_.clear();
+    cached_ = 0;
+}
+
+DevPool::~DevPool() {
+    trim();
+    for (auto& kv : live_) (void)hipFree(kv.first);
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+void ed_default_options(ed_options* o) {
+    std::memset(o, 0, sizeof *o);
+    o->engine = ED_ENGINE_DIRECT;
+    o->pack_bits = 0;
+    o->block = 32;
+    o->flags = 0;
+    o->hash_seed = 0x5EED;
+}
+
+static int check_options(const ed_options* o) {
+    if (o->engine > 1) return ED_EINVAL;
+    if (o->pack_bits != 0 && o->pack_bits != 2 && o->pack_bits != 8) return ED_EINVAL;
+    const uint32_t b = o->block ? o->block : 32;
+    if (b > 4096 || (b & (b - 1)) != 0) return ED_EINVAL;
+    if (o->lds_rounds > static_cast<uint32_t>(kLdsRoundsMax)) return ED_EINVAL;
+    if (o->lane_words > 64) return ED_EINVAL;
+    return ED_OK;
+}
+
+int ed::ctx_set_hash(ed_ctx* c, uint64_t seed) {
+    const uint64_t r = ed_hash_base(seed);
+    if (c->d_pow && r == c->r) return ED_OK;
+    std::vector<uint64_t> h(kPowEntries);
+    // pow0 | pow1 | rtab
+    uint64_t* p0 = h.data();
+    uint64_t* p1 = p0 + 65536;
+    uint64_t* rt = p1 + 65536;
+    p0[0] = 1;
+    for (int i = 1; i < 65536; ++i) p0[i] = hmul(p0[i - 1], r);
+    const uint64_t r16 = hmul(p0[65535], r);
+    p1[0] = 1;
+    for (int i = 1; i < 65536; ++i) p1[i] = hmul(p1[i - 1], r16);
+    for (int i = 0; i < 65; ++i) rt[i] = p0[i];
+    for (int k = 0; k < 257; ++k) rt[65 + k] = hpow(r, 64ull * k);
+    const uint64_t R = hpow(r, kTileChars);
+    uint64_t a = 1;
+    for (int d = 0; d < 65; ++d) {
+        rt[65 + 257 + d] = a;
+        a = hmul(a, R);
+    }
+    if (!c->d_pow) {
+        HIP_TRY(hipMalloc(&c->d_pow, kPowEntries * sizeof(uint64_t)));
+    }
+    HIP_TRY(hipMemcpy(c->d_pow, h.data(), kPowEntries * sizeof(uint64_t), hipMemcpyHostToDevice));
+    c->r = r;
+    return ED_OK;
+}
+
+int ed_init(ed_ctx** out, int device, const ed_options* opt) {
+    if (!out) return ED_EINVAL;
+    *out = nullptr;
+    ed_options o;
+    if (opt)
+        o = *opt;
+    else
+        ed_default_options(&o);
+    if (check_options(&o) != ED_OK) {
+        set_error("ed_init: invalid options");
+        return ED_EINVAL;
+    }
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) {
+        set_error("ed_init: device %d out of range (%d devices)", device, ndev);
+        return ED_EINVAL;
+    }
+    HIP_TRY(hipSetDevice(device));
+    ed_ctx* c = new (std::nothrow) ed_ctx();
+    if (!c) return ED_ENOMEM;
+    c->device = device;
+    c->opt = o;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete c;
+        set_error("hipGetDeviceProperties failed");
+        return ED_EDEVICE;
+    }
+    c->num_cu = prop.multiProcessorCount;
+    int fg = 0;
+    if (frontier_max_grid(device, &fg) != hipSuccess || fg < 1) fg = c->num_cu;
+    c->frontier_grid_max = fg;
+    if (hipMalloc(&c->d_ctl, sizeof(FrontierCtl)) != hipSuccess ||
+        hipMalloc(&c->d_cnt, sizeof(CountersDev)) != hipSuccess ||
+        hipHostMalloc(&c->h_ctl, sizeof(FrontierCtl)) != hipSuccess ||
+        hipHostMalloc(&c->h_cnt, sizeof(CountersDev)) != hipSuccess) {
+        set_error("ed_init: allocation failed");
+        ed_shutdown(c);
+        return ED_ENOMEM;
+    }
+    int rc = ctx_set_hash(c, o.hash_seed);
+    if (rc != ED_OK) {
+        ed_shutdown(c);
+        return rc;
+    }
+    *out = c;
+    return ED_OK;
+}
+
+int ed_set_options(ed_ctx* c, const ed_options* opt) {
+    if (!c || !opt) return ED_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (check_options(opt) != ED_OK) {
+        set_error("ed_set_options: invalid options");
+        return ED_EINVAL;
+    }
+    HIP_TRY(hipSetDevice(c->device));
+    int rc = ctx_set_hash(c, opt->hash_seed);
+    if (rc != ED_OK) return rc;
+    c->opt = *opt;
+    return ED_OK;
+}
+
+int ed_get_options(ed_ctx* c, ed_options* opt) {
+    if (!c || !opt) return ED_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    *opt = c->opt;
+    return ED_OK;
+}
+
+int ed_shutdown(ed_ctx* c) {
+    if (!c) return ED_EINVAL;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    if (c->d_pow) (void)hipFree(c->d_pow);
+    if (c->d_ctl) (void)hipFree(c->d_ctl);
+    if (c->d_cnt) (void)hipFree(c->d_cnt);
+    if (c->h_ctl) (void)hipHostFree(c->h_ctl);
+    if (c->h_cnt) (void)hipHostFree(c->h_cnt);
+    delete c;
+    return ED_OK;
+}
+
+// ---------------------------------------------------------------------------
+// pairs
+// ---------------------------------------------------------------------------
+static int log2u(uint32_t b) {
+    int l = 0;
+    while ((1u << l) < b) ++l;
+    return l;
+}
+
+void ed::pair_free(ed_pair* p) {
+    DevPool& pool = p->ctx->pool;
+    for (void** q : {&p->w2[0], &p->w2[1], &p->w8[0], &p->w8[1], &p->tab[0], &p->tab[1], &p->misc,
+                     &p->stage[0], &p->stage[1], &p->f0, &p->f1}) {
+        pool.put(*q);
+        *q = nullptr;
+    }
+}
+
+PairDev ed::pair_dev(const ed_pair* p) {
+    PairDev d;
+    std::memset(&d, 0, sizeof d);
+    d.a.w2 = static_cast<const uint64_t*>(p->w2[0]);
+    d.b.w2 = static_cast<const uint64_t*>(p->w2[1]);
+    d.a.w8 = static_cast<const uint64_t*>(p->w8[0]);
+    d.b.w8 = static_cast<const uint64_t*>(p->w8[1]);
+    d.a.tab = static_cast<const uint64_t*>(p->tab[0]);
+    d.b.tab = static_cast<const uint64_t*>(p->tab[1]);
+    d.a.len = static_cast<int32_t>(p->len[0]);
+    d.b.len = static_cast<int32_t>(p->len[1]);
+    d.alpha = reinterpret_cast<const uint32_t*>(static_cast<char*>(p->misc) + kMiscAlpha);
+    d.log2b = p->log2b;
+    d.force8 = p->force8;
+    return d;
+}
+
+HashDev ed::ctx_hash(const ed_ctx* c) {
+    HashDev h;
+    h.r = c->r;
+    h.pow0 = c->d_pow;
+    h.pow1 = c->d_pow + 65536;
+    return h;
+}
+
+int ed::prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B, uint64_t m,
+                       int on_device, hipStream_t s, ed_pair** out) {
+    *out = nullptr;
+    if ((n && !A) || (m && !B) || n >= ED_MAX_LEN || m >= ED_MAX_LEN) {
+        set_error("ed_prepare: invalid string arguments (n=%llu m=%llu)",
+                  static_cast<unsigned long long>(n), static_cast<unsigned long long>(m));
+        return ED_EINVAL;
+    }
+    ed_pair* p = new (std::nothrow) ed_pair();
+    if (!p) return ED_ENOMEM;
+    p->ctx = c;
+    p->len[0] = n;
+    p->len[1] = m;
+    p->engine = c->opt.engine;
+    const uint32_t b = c->opt.block ? c->opt.block : 32;
+    p->log2b = log2u(b);
+    p->force8 = c->opt.pack_bits == 8 ? 1 : 0;
+    p->seed = c->opt.hash_seed;
+    const bool table = p->engine == ED_ENGINE_HASH;
+    const uint8_t* src[2] = {A, B};
+    int32_t tiles[2];
+    for (int s2 = 0; s2 < 2; ++s2) {
+        const uint64_t len = p->len[s2];
+        tiles[s2] = static_cast<int32_t>(std::max<uint64_t>(1, (len + kTileChars - 1) / kTileChars));
+        p->w2[s2] = c->pool.get((static_cast<size_t>(tiles[s2]) * kTileWords2 + kPadWords) * 8);
+        p->w8[s2] = c->pool.get((static_cast<size_t>(tiles[s2]) * kTileWords8 + kPadWords) * 8);
+        if (table) p->tab[s2] = c->pool.get(((len >> p->log2b) + 1) * 8);
+        if (!p->w2[s2] || !p->w8[s2] || (table && !p->tab[s2])) {
+            pair_free(p);
+            delete p;
+            set_error("ed_prepare: device allocation failed");
+            return ED_ENOMEM;
+        }
+    }
+    const int32_t total = tiles[0] + tiles[1];
+    p->misc = c->pool.get(kMiscAlpha + 64 + static_cast<size_t>(total) * 9);
+    if (!p->misc) {
+        pair_free(p);
+        delete p;
+        return ED_ENOMEM;
+    }
+    char* misc = static_cast<char*>(p->misc);
+    // staging: host inputs, or device inputs not 16-byte aligned
+    const uint8_t* raw[2];
+    for (int s2 = 0; s2 < 2; ++s2) {
+        const uint64_t len = p->len[s2];
+        const bool aligned = (reinterpret_cast<uintptr_t>(src[s2]) & 15u) == 0;
+        if (len && (!on_device || !aligned)) {
+            p->stage[s2] = c->pool.get(len + 16);
+            if (!p->stage[s2]) {
+                pair_free(p);
+                delete p;
+                return ED_ENOMEM;
+            }
+            hipError_t e = hipMemcpyAsync(p->stage[s2], src[s2], len,
+                                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) {
+                set_error("ed_prepare: input copy failed: %s", hipGetErrorString(e));
+                pair_free(p);
+                delete p;
+                return ED_EDEVICE;
+            }
+            raw[s2] = static_cast<const uint8_t*>(p->stage[s2]);
+        } else {
+            raw[s2] = src[s2];
+        }
+    }
+    PrepParams pp;
+    std::memset(&pp, 0, sizeof pp);
+    for (int s2 = 0; s2 < 2; ++s2) {
+        pp.s[s2].raw = raw[s2];
+        pp.s[s2].w2 = static_cast<uint64_t*>(p->w2[s2]);
+        pp.s[s2].w8 = static_cast<uint64_t*>(p->w8[s2]);
+        pp.s[s2].tab = static_cast<uint64_t*>(p->tab[s2]);
+        pp.s[s2].len = static_cast<int32_t>(p->len[s2]);
+        pp.s[s2].tiles = tiles[s2];
+    }
+    pp.s[0].tile0 = 0;
+    pp.s[1].tile0 = tiles[0];
+    pp.total_tiles = total;
+    pp.log2b = p->log2b;
+    pp.force8 = p->force8;
+    pp.build_table = table ? 1 : 0;
+    pp.r = c->r;
+    pp.tile_status = reinterpret_cast<uint64_t*>(misc + kMiscAlpha + 64);
+    pp.ticket = reinterpret_cast<unsigned int*>(misc + kMiscTicket);
+    pp.alpha = reinterpret_cast<uint32_t*>(misc + kMiscAlpha);
+    pp.tile_big = reinterpret_cast<uint8_t*>(misc + kMiscAlpha + 64 + static_cast<size_t>(total) * 8);
+    pp.rtab = c->d_pow + 2 * 65536;
+    int grid = std::min(total, c->num_cu * 4);
+    if (grid < 1) grid = 1;
+    HIP_TRY(launch_prep_clear(pp, s));
+    HIP_TRY(launch_prepare(pp, grid, s));
+    if (c->opt.pack_bits != 2) HIP_TRY(launch_copy8_rest(pp, s));
+    p->launches_prepare = c->opt.pack_bits != 2 ? 3 : 2;
+    if (c->opt.pack_bits == 2) {
+        uint32_t alpha = 0;
+        HIP_TRY(hipMemcpyAsync(&alpha, pp.alpha, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (alpha > 3u) {
+            pair_free(p);
+            delete p;
+            set_error("ed_prepare: pack_bits=2 but a character is above 3 (OR of characters = %u)", alpha);
+            return ED_EINVAL;
+        }
+    }
+    *out = p;
+    return ED_OK;
+}
+
+int ed_prepare(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B, uint64_t m,
+               int inputs_on_device, void* hip_stream, ed_pair** out) {
+    if (!c || !out) return ED_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    HIP_TRY(hipSetDevice(c->device));
+    const auto t0 = std::chrono::steady_clock::now();
+    int rc = prepare_locked(c, A, n, B, m, inputs_on_device, static_cast<hipStream_t>(hip_stream), out);
+    if (rc == ED_OK)
+        (*out)->ns_prepare =
+            std::chrono::duration<double, std::nano>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
+}
+
+int ed_release(ed_pair* p) {
+    if (!p) return ED_EINVAL;
+    ed_ctx* c = p->ctx;
+    std::lock_guard<std::mutex> lk(c->mu);
+    (void)hipSetDevice(c->device);
+    // buffers may still be read by queued work on a caller stream
+    (void)hipDeviceSynchronize();
+    pair_free(p);
+    delete p;
+    return ED_OK;
+}
+
+// ---------------------------------------------------------------------------
+// distance
+// ---------------------------------------------------------------------------
+static int frontier_grid(const ed_ctx* c) {
+    int g = c->opt.grid_blocks ? static_cast<int>(c->opt.grid_blocks) : c->num_cu;
+    return std::max(1, std::min(g, c->frontier_grid_max));
+}
+
+int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, int32_t* rows,
+                        uint64_t rows_cap, hipStream_t s) {
+    if (p->engine == ED_ENGINE_HASH && (!p->tab[0] || !p->tab[1])) {
+        set_error("ed_distance: pair has no prefix tables");
+        return ED_EINVAL;
+    }
+    if (p->engine == ED_ENGINE_HASH && p->seed != c->opt.hash_seed) {
+        int rc = ctx_set_hash(c, p->seed);
+        if (rc != ED_OK) return rc;
+    }
+    const int64_t n = static_cast<int64_t>(p->len[0]), m = static_cast<int64_t>(p->len[1]);
+    const int64_t maxnm = std::max(n, m);
+    int64_t K = std::min<int64_t>(maxnm, c->opt.init_rows ? int64_t(c->opt.init_rows) : int64_t(1) << 17);
+    if (k_max >= 0) K = std::min<int64_t>(K, std::max<int64_t>(k_max, 1));
+    K = std::max<int64_t>(K, 1);
+    const uint32_t lds_rounds = c->opt.lds_rounds ? c->opt.lds_rounds : kDefaultLdsRounds;
+    const uint32_t lane_words = c->opt.lane_words ? c->opt.lane_words
+                                                  : (p->engine == ED_ENGINE_HASH ? 1u : 2u);
+    int32_t* d_dump = nullptr;
+    void* dump_buf = nullptr;
+    if (rows) {
+        dump_buf = c->pool.get(std::max<uint64_t>(rows_cap, 1) * 4);
+        if (!dump_buf) return ED_ENOMEM;
+        d_dump = static_cast<int32_t*>(dump_buf);
+    }
+    auto alloc_rows = [&](int64_t Kn, void** a, void** b) -> bool {
+        *a = c->pool.get(static_cast<size_t>(2 * Kn + 5) * 4);
+        *b = c->pool.get(static_cast<size_t>(2 * Kn + 5) * 4);
+        return *a && *b;
+    };
+    void *f0 = nullptr, *f1 = nullptr;
+    if (!alloc_rows(K, &f0, &f1)) {
+        c->pool.put(f0);
+        c->pool.put(f1);
+        c->pool.put(dump_buf);
+        return ED_ENOMEM;
+    }
+    FrontierParams fp;
+    std::memset(&fp, 0, sizeof fp);
+    fp.p = pair_dev(p);
+    fp.h = ctx_hash(c);
+    fp.kmax = k_max >= 0 ? static_cast<int32_t>(std::min<int64_t>(k_max, INT32_MAX - 1)) : -1;
+    fp.lds_rounds = (c->opt.flags & ED_FLAG_NO_PHASE_A) ? 0 : static_cast<int32_t>(lds_rounds);
+    fp.engine = static_cast<int32_t>(p->engine);
+    fp.lane_words = static_cast<int32_t>(lane_words);
+    fp.ctl = c->d_ctl;
+    fp.dump = d_dump;
+    fp.dump_cap = static_cast<int64_t>(rows_cap);
+    fp.counters = c->d_cnt;
+    int32_t t0 = 0;
+    int launches = 0;
+    CountersDev total;
+    std::memset(&total, 0, sizeof total);
+    int rc = ED_OK;
+    uint64_t result = 0;
+    for (;;) {
+        fp.f0 = static_cast<int32_t*>(f0);
+        fp.f1 = static_cast<int32_t*>(f1);
+        fp.K = static_cast<int32_t>(K);
+        fp.t0 = t0;
+        hipError_t e = launch_ctl_init(c->d_ctl, c->d_cnt, s);
+        if (e == hipSuccess) e = launch_frontier(fp, frontier_grid(c), s);
+        if (e == hipSuccess) e = hipMemcpyAsync(c->h_ctl, c->d_ctl, sizeof(FrontierCtl), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(c->h_cnt, c->d_cnt, sizeof(CountersDev), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            set_error("ed_distance: frontier launch failed: %s", hipGetErrorString(e));
+            rc = ED_EDEVICE;
+            break;
+        }
+        ++launches;
+        const CountersDev& cd = *c->h_cnt;
+        total.updates += cd.updates;
+        total.lcp_chars += cd.lcp_chars;
+        total.wave_lcps += cd.wave_lcps;
+        total.grid_lcps += cd.grid_lcps;
+        total.hash_queries += cd.hash_queries;
+        total.hash_probes += cd.hash_probes;
+        total.hash_eq_len += cd.hash_eq_len;
+        total.collisions += cd.collisions;
+        const FrontierCtl& st = *c->h_ctl;
+        if (st.status == 1 || st.status == 2) {
+            result = static_cast<uint64_t>(st.result_t);
+            break;
+        }
+        if (st.status == 3) {
+            // grow the rows and resume from the saved frontier f_t
+            const int64_t t = st.result_t;
+            const int64_t K2 = std::min<int64_t>(maxnm, std::max<int64_t>(2 * K, t + 1));
+            if (K2 <= K) {
+                set_error("ed_distance: capacity exhausted at t=%lld (K=%lld)", (long long)t, (long long)K);
+                rc = ED_EINTERNAL;
+                break;
+            }
+            void *g0 = nullptr, *g1 = nullptr;
+            if (!alloc_rows(K2, &g0, &g1)) {
+                c->pool.put(g0);
+                c->pool.put(g1);
+                rc = ED_ENOMEM;
+                break;
+            }
+            void* srcrow = st.wbuf == 0 ? f0 : f1;
+            // entries [-(t+2), t+2] of the old row -> same diagonals of the new row
+            e = hipMemcpyAsync(static_cast<int32_t*>(g0) + (K2 + 2) - (t + 2),
+                               static_cast<int32_t*>(srcrow) + (K + 2) - (t + 2),
+                               static_cast<size_t>(2 * t + 5) * 4, hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            c->pool.put(f0);
+            c->pool.put(f1);
+            f0 = g0;
+            f1 = g1;
+            if (e != hipSuccess) {
+                set_error("ed_distance: row copy failed: %s", hipGetErrorString(e));
+                rc = ED_EDEVICE;
+                break;
+            }
+            K = K2;
+            t0 = static_cast<int32_t>(t);
+            continue;
+        }
+        set_error("ed_distance: frontier kernel ended with status %d at t=%d", st.status, st.result_t);
+        rc = ED_EINTERNAL;
+        break;
+    }
+    c->pool.put(f0);
+    c->pool.put(f1);
+    if (rc == ED_OK) {
+        *k_out = result;
+        p->rounds = result;
+        p->counters = total;
+        p->launches_distance = launches;
+        if (rows) {
+            const uint64_t need = (result + 1) * (result + 1);
+            if (need > rows_cap) {
+                set_error("ed_distance_dump: %llu rows need %llu entries, capacity %llu",
+                          (unsigned long long)(result + 1), (unsigned long long)need,
+                          (unsigned long long)rows_cap);
+                rc = ED_EINVAL;
+            } else {
+                hipError_t e = hipMemcpy(rows, d_dump, need * 4, hipMemcpyDeviceToHost);
+                if (e != hipSuccess) {
+                    set_error("ed_distance_dump: copy failed: %s", hipGetErrorString(e));
+                    rc = ED_EDEVICE;
+                }
+            }
+        }
+    }
+    c->pool.put(dump_buf);
+    return rc;
+}
+
+int ed_distance(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, void* hip_stream) {
+    if (!c || !p || !k_out || p->ctx != c) return ED_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    HIP_TRY(hipSetDevice(c->device));
+    const auto t0 = std::chrono::steady_clock::now();
+    int rc = distance_locked(c, p, k_max, k_out, nullptr, 0, static_cast<hipStream_t>(hip_stream));
+    p->ns_distance = std::chrono::duration<double, std::nano>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
+}
+
+int ed_distance_dump(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, int32_t* rows,
+                     uint64_t rows_cap, void* hip_stream) {
+    if (!c || !p || !k_out || !rows || p->ctx != c) return ED_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    HIP_TRY(hipSetDevice(c->device));
+    return distance_locked(c, p, k_max, k_out, rows, rows_cap, static_cast<hipStream_t>(hip_stream));
+}
+
+// ---------------------------------------------------------------------------
+// stats, buffers, debug queries
+// ---------------------------------------------------------------------------
+int ed_pair_stats(const ed_pair* p, ed_stats* o) {
+    if (!p || !o) return ED_EINVAL;
+    std::memset(o, 0, sizeof *o);
+    o->n = p->len[0];
+    o->m = p->len[1];
+    uint32_t alpha = 0;
+    const char* misc = static_cast<const char*>(p->misc);
+    if (hipMemcpy(&alpha, misc + kMiscAlpha, 4, hipMemcpyDeviceToHost) != hipSuccess) {
+        set_error("ed_pair_stats: copy failed");
+        return ED_EDEVICE;
+    }
+    o->bits_per_char = (alpha <= 3u && !p->force8) ? 2 : 8;
+    o->engine = p->engine;
+    o->rounds = p->rounds;
+    o->updates = p->counters.updates;
+    o->lcp_chars = p->counters.lcp_chars;
+    o->wave_lcps = p->counters.wave_lcps;
+    o->grid_lcps = p->counters.grid_lcps;
+    o->hash_queries = p->counters.hash_queries;
+    o->hash_probes = p->counters.hash_probes;
+    o->collisions = p->counters.collisions;
+    // Schwartz-Zippel: a false "equal" for strings of length L has
+    // probability <= (L-1)/P over a uniform base
+    o->collision_bound = static_cast<double>(p->counters.hash_eq_len) / static_cast<double>(kP);
+    o->launches = static_cast<uint64_t>(p->launches_distance);
+    o->ns_prepare = p->ns_prepare;
+    o->ns_distance = p->ns_distance;
+    return ED_OK;
+}
+
+int ed_pair_buffer(ed_ctx* c, const ed_pair* p, int which, int kind, void* out, uint64_t cap,
+                   uint64_t* len_out) {
+    if (!c || !p || which < 0 || which > 1 || !len_out) return ED_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    HIP_TRY(hipSetDevice(c->device));
+    const uint64_t len = p->len[which];
+    const void* src = nullptr;
+    uint64_t bytes = 0;
+    if (kind == ED_BUF_PACKED2) {
+        src = p->w2[which];
+        bytes = (len + 31) / 32 * 8;
+    } else if (kind == ED_BUF_BYTES) {
+        src = p->w8[which];
+        bytes = len;
+    } else if (kind == ED_BUF_TABLE) {
+        src = p->tab[which];
+        bytes = ((len >> p->log2b) + 1) * 8;
+        if (!src) {
+            set_error("ed_pair_buffer: no table (direct engine)");
+            return ED_EINVAL;
+        }
+    } else {
+        return ED_EINVAL;
+    }
+    *len_out = bytes;
+    if (!out) return ED_OK;
+    if (cap < bytes) {
+        set_error("ed_pair_buffer: capacity %llu < %llu", (unsigned long long)cap, (unsigned long long)bytes);
+        return ED_EINVAL;
+    }
+    HIP_TRY(hipDeviceSynchronize());
+    if (bytes) HIP_TRY(hipMemcpy(out, src, bytes, hipMemcpyDeviceToHost));
+    return ED_OK;
+}
+
+int ed_debug_lcp(ed_ctx* c, ed_pair* p, int engine, const int64_t* x, const int64_t* y,
+                 uint64_t count, int64_t* out, void* hip_stream) {
+    if (!c || !p || (count && (!x || !y || !out))) return ED_EINVAL;
+    if (engine < -1 || engine > 1) return ED_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    HIP_TRY(hipSetDevice(c->device));
+    const int eng = engine < 0 ? static_cast<int>(p->engine) : engine;
+    if (eng == 1 && (!p->tab[0] || !p->tab[1])) {
+        set_error("ed_debug_lcp: hash engine needs a pair prepared with tables");
+        return ED_EINVAL;
+    }
+    for (uint64_t i = 0; i < count; ++i) {
+        if (x[i] < 0 || y[i] < 0 || static_cast<uint64_t>(x[i]) > p->len[0] ||
+            static_cast<uint64_t>(y[i]) > p->len[1]) {
+            set_error("ed_debug_lcp: query %llu out of range", (unsigned long long)i);
+            return ED_EINVAL;
+        }
+    }
+    if (count == 0) return ED_OK;
+    if (eng == 1 && p->seed != c->opt.hash_seed) {
+        int rc = ctx_set_hash(c, p->seed);
+        if (rc != ED_OK) return rc;
+    }
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    void* buf = c->pool.get(count * 24);
+    if (!buf) return ED_ENOMEM;
+    int64_t* dx = static_cast<int64_t*>(buf);
+    int64_t* dy = dx + count;
+    int64_t* dout = dy + count;
+    LcpQueryParams q;
+    std::memset(&q, 0, sizeof q);
+    q.p = pair_dev(p);
+    q.h = ctx_hash(c);
+    q.x = dx;
+    q.y = dy;
+    q.out = dout;
+    q.count = static_cast<int64_t>(count);
+    q.engine = eng;
+    q.lane_words = c->opt.lane_words ? static_cast<int32_t>(c->opt.lane_words) : (eng == 1 ? 1 : 2);
+    q.counters = c->d_cnt;
+    hipError_t e = hipMemcpyAsync(dx, x, count * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dy, y, count * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_ctl_init(c->d_ctl, c->d_cnt, s);
+    if (e == hipSuccess) e = launch_lcp_queries(q, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, dout, count * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->h_cnt, c->d_cnt, sizeof(CountersDev), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    c->pool.put(buf);
+    if (e != hipSuccess) {
+        set_error("ed_debug_lcp: %s", hipGetErrorString(e));
+        return ED_EDEVICE;
+    }
+    p->counters = *c->h_cnt;
+    return ED_OK;
+}
+
+const char* ed_strerror(int status) {
+    switch (status) {
+        case ED_OK: return "ok";
+        case ED_EINVAL: return "invalid argument";
+        case ED_ENOMEM: return "out of memory";
+        case ED_EDEVICE: return "device error";
+        case ED_ECOLLISION: return "hash collision not resolved";
+        case ED_EBUSY: return "busy";
+        case ED_EINTERNAL: return "internal error";
+        default: return "unknown status";
+    }
+}
+
+const char* ed_last_error(void) { return g_last_error.c_str(); }

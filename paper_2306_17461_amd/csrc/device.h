@@ -1,0 +1,345 @@
+// Device building blocks: arithmetic mod 2^61-1, packed-string word fetch,
+// and the two LCP engines (direct word compare; prefix-hash search).
+#pragma once
+#include "internal.h"
+
+namespace ed {
+
+// ---------------------------------------------------------------------------
+// Arithmetic modulo P = 2^61 - 1 (the hash of section 2 with a word-size
+// modulus).  Operands are always reduced (< P).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t mp_fold(uint64_t s) {  // any s < 2^64
+    s = (s & kP) + (s >> 61);
+    return s >= kP ? s - kP : s;
+}
+__device__ __forceinline__ uint64_t mp_add(uint64_t a, uint64_t b) {
+    uint64_t s = a + b;
+    return s >= kP ? s - kP : s;
+}
+__device__ __forceinline__ uint64_t mp_sub(uint64_t a, uint64_t b) {
+    return a >= b ? a - b : a + kP - b;
+}
+__device__ __forceinline__ uint64_t mp_mul(uint64_t a, uint64_t b) {
+    // a*b = hi*2^64 + lo and 2^64 = 8 (mod P); hi < 2^58 since a, b < 2^61.
+    uint64_t lo = a * b;
+    uint64_t hi = __umul64hi(a, b);
+    return mp_fold((hi << 3) + (lo & kP) + (lo >> 61));
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront helpers (wave64).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ int ctz64(uint64_t v) { return __builtin_ctzll(v); }
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+    return __shfl(static_cast<unsigned long long>(v), src);
+}
+__device__ __forceinline__ int shfl_i32(int v, int src) { return __shfl(v, src); }
+
+// ---------------------------------------------------------------------------
+// A packed string: chars-per-word 2^lcpw, bits-per-char bpc.  fetch(pos)
+// returns the 64 bits holding characters pos, pos+1, ... (little-endian:
+// character pos in the lowest bits).  Words past the string are zero padding.
+// ---------------------------------------------------------------------------
+struct SView {
+    const uint64_t* w;
+    int32_t len;
+    int32_t lcpw;  // 5 (2-bit) or 3 (8-bit)
+    int32_t bpc;   // 2 or 8
+};
+
+__device__ __forceinline__ uint64_t fetch(const SView& s, int32_t pos) {
+    const int32_t q = pos >> s.lcpw;
+    const uint32_t sh = static_cast<uint32_t>((pos & ((1 << s.lcpw) - 1)) * s.bpc);
+    const uint64_t lo = s.w[q];
+    const uint64_t hi = s.w[q + 1];
+    // (hi << 1) << (63 - sh) equals hi << (64 - sh) and is 0 for sh = 0
+    return (lo >> sh) | ((hi << 1) << (63 - sh));
+}
+
+__device__ __forceinline__ void pair_views(const PairDev& p, uint32_t alpha, SView& A, SView& B) {
+    const bool two = (alpha <= 3u) && !p.force8;
+    A.w = two ? p.a.w2 : p.a.w8;
+    B.w = two ? p.b.w2 : p.b.w8;
+    A.len = p.a.len;
+    B.len = p.b.len;
+    A.lcpw = B.lcpw = two ? 5 : 3;
+    A.bpc = B.bpc = two ? 2 : 8;
+}
+
+// ---------------------------------------------------------------------------
+// Engine (a), lane tier: one lane compares up to `maxw` words of A from x and
+// B from y (at most lim characters).  Returns the matched length; sets *more
+// when maxw full words matched and lim is not reached (the LCP continues).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t lcp_lane(const SView& A, const SView& B, int32_t x, int32_t y,
+                                            int32_t lim, int maxw, bool* more) {
+    const int32_t cpw = 1 << A.lcpw;
+    int32_t l = 0;
+    for (int k = 0; k < maxw; ++k) {
+        if (l >= lim) return lim;
+        const uint64_t d = fetch(A, x + l) ^ fetch(B, y + l);
+        if (d) {
+            const int32_t c = l + ctz64(d) / A.bpc;
+            return c < lim ? c : lim;
+        }
+        l += cpw;
+    }
+    if (l >= lim) return lim;
+    *more = true;
+    return l;
+}
+
+// ---------------------------------------------------------------------------
+// Engine (a), wave tier: all 64 lanes extend one LCP (uniform x, y, lim)
+// from offset l, two words per lane per step (1024 chars at 8-bit, 4096 at
+// 2-bit), with coalesced loads.  Returns the LCP (uniform).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t lcp_wave_direct(const SView& A, const SView& B, int32_t x,
+                                                   int32_t y, int32_t lim, int32_t l) {
+    const int lane = lane_id();
+    const int32_t cpw = 1 << A.lcpw;
+    while (l < lim) {
+        const int32_t p0 = l + lane * cpw;
+        const int32_t p1 = p0 + 64 * cpw;
+        uint64_t d0 = 0, d1 = 0;
+        if (p0 < lim) d0 = fetch(A, x + p0) ^ fetch(B, y + p0);
+        if (p1 < lim) d1 = fetch(A, x + p1) ^ fetch(B, y + p1);
+        const uint64_t b0 = ballot(d0 != 0);
+        if (b0) {
+            const int s = ctz64(b0);
+            const uint64_t dd = shfl_u64(d0, s);
+            const int32_t c = l + s * cpw + ctz64(dd) / A.bpc;
+            return c < lim ? c : lim;
+        }
+        const uint64_t b1 = ballot(d1 != 0);
+        if (b1) {
+            const int s = ctz64(b1);
+            const uint64_t dd = shfl_u64(d1, s);
+            const int32_t c = l + (64 + s) * cpw + ctz64(dd) / A.bpc;
+            return c < lim ? c : lim;
+        }
+        l += 128 * cpw;
+    }
+    return lim;
+}
+
+// ---------------------------------------------------------------------------
+// Engine (b): prefix hashes.  H(S, p) = h(S[0..p)) is rebuilt from the
+// blocked table as T[p/b] * r^(p mod b) + h(S[(p/b)b .. p)) (Algorithm 2,
+// GetHash, with the block index read as floor(p/b)).  Equality of
+// A[x..x+L) and B[y..y+L) is tested as
+//   H(A, x+L) - H(B, y+L) == (H(A, x) - H(B, y)) * r^L   (mod P),
+// which is the comparison of h(A[x..x+L)) and h(B[y..y+L)) via the inverse
+// concatenation of section 2.
+// ---------------------------------------------------------------------------
+struct HashQ {
+    HashDev h;
+    uint64_t r4;           // r^4
+    const uint64_t* lut4;  // LDS: hash of the 4 characters of a packed byte
+    int32_t log2b;
+};
+
+__device__ __forceinline__ uint64_t pow_r(const HashQ& q, int32_t L) {
+    return mp_mul(q.h.pow0[L & 0xFFFF], q.h.pow1[static_cast<uint32_t>(L) >> 16]);
+}
+
+// h(S[s .. s+e)), s a multiple of the block size.
+__device__ __forceinline__ uint64_t partial_hash(const SView& S, const HashQ& q, int32_t s,
+                                                 int32_t e) {
+    uint64_t h = 0;
+    int32_t i = 0;
+    if (S.bpc == 2) {
+        // whole packed bytes (4 characters) through the LDS table, when the
+        // block start is byte aligned (b >= 4)
+        if ((s & 3) == 0) {
+            for (; i + 4 <= e; i += 4) {
+                const int32_t pos = s + i;
+                const uint64_t word = S.w[pos >> 5];
+                const uint32_t byte = static_cast<uint32_t>(word >> (((pos >> 2) & 7) * 8)) & 0xFFu;
+                h = mp_add(mp_mul(h, q.r4), q.lut4[byte]);
+            }
+        }
+        for (; i < e; ++i) {
+            const int32_t pos = s + i;
+            const uint64_t c = (S.w[pos >> 5] >> ((pos & 31) * 2)) & 3u;
+            h = mp_add(mp_mul(h, q.h.r), c);
+        }
+    } else {
+        for (; i < e; ++i) {
+            const int32_t pos = s + i;
+            const uint64_t c = (S.w[pos >> 3] >> ((pos & 7) * 8)) & 0xFFu;
+            h = mp_add(mp_mul(h, q.h.r), c);
+        }
+    }
+    return h;
+}
+
+__device__ __forceinline__ uint64_t get_hash(const SView& S, const uint64_t* T, const HashQ& q,
+                                             int32_t p) {
+    const int32_t j = p >> q.log2b;
+    const int32_t e = p & ((1 << q.log2b) - 1);
+    uint64_t h = T[j];
+    if (e) h = mp_add(mp_mul(h, q.h.pow0[e]), partial_hash(S, q, j << q.log2b, e));
+    return h;
+}
+
+// Wave-parallel LCP by hashing (uniform x, y, lim; the first l0 characters
+// are known to match and l0 < lim).  Galloping: lane k tests L = l0 * 2^(k+1)
+// (the last probe clamped to lim); then 64-ary narrowing of the interval
+// (lo equal, hi unequal) until it spans at most one direct wave step; the
+// direct step finds the mismatch character, which confirms the answer.  When
+// the direct step finds no mismatch below hi, a hash collision made some
+// "equal" verdict wrong: the LCP is recomputed directly (counted).
+__device__ int32_t lcp_wave_hash(const SView& A, const SView& B, const uint64_t* TA,
+                                 const uint64_t* TB, const HashQ& q, int32_t x, int32_t y,
+                                 int32_t lim, int32_t l0, CountersDev& cnt) {
+    const int lane = lane_id();
+    const int32_t cpw = 1 << A.lcpw;
+    const int32_t span = 64 * cpw;  // one direct step
+    const uint64_t hax = get_hash(A, TA, q, x);
+    const uint64_t hby = get_hash(B, TB, q, y);
+    const uint64_t d0 = mp_sub(hax, hby);
+    if (lane == 0) cnt.hash_queries++;
+
+    auto eq = [&](int32_t L) -> bool {
+        const uint64_t lhs = mp_sub(get_hash(A, TA, q, x + L), get_hash(B, TB, q, y + L));
+        return lhs == mp_mul(d0, pow_r(q, L));
+    };
+
+    int32_t lo = l0, hi;
+    {
+        // galloping probes
+        const int64_t Lr = static_cast<int64_t>(l0) << (lane < 40 ? lane + 1 : 40);
+        const int64_t Lprev = static_cast<int64_t>(l0) << (lane < 40 ? lane : 40);
+        const bool active = Lprev < lim;  // first probe that reaches lim is the last one
+        const int32_t L = static_cast<int32_t>(Lr < lim ? Lr : lim);
+        const bool e = active ? eq(L) : true;
+        if (active) {
+            cnt.hash_probes++;
+            if (e) cnt.hash_eq_len += static_cast<unsigned long long>(L);
+        }
+        const uint64_t ne = ballot(active && !e);
+        if (ne == 0) return lim;  // every probe up to lim matched
+        const int k = ctz64(ne);
+        hi = shfl_i32(L, k);
+        if (k > 0) lo = shfl_i32(L, k - 1);
+    }
+    while (hi - lo > span) {
+        const int32_t step = (hi - lo + 63) / 64;
+        const int32_t M = lo + (lane + 1) * step;
+        const bool active = M < hi;
+        const bool e = active ? eq(M) : true;
+        if (active) {
+            cnt.hash_probes++;
+            if (e) cnt.hash_eq_len += static_cast<unsigned long long>(M);
+        }
+        const uint64_t ne = ballot(active && !e);
+        const uint64_t act = ballot(active);
+        if (ne) {
+            const int k = ctz64(ne);
+            const int32_t nhi = shfl_i32(M, k);
+            if (k > 0) lo = shfl_i32(M, k - 1);
+            hi = nhi;
+        } else {
+            lo = shfl_i32(M, 63 - __builtin_clzll(act));
+        }
+    }
+    // direct step over [lo, hi): hi is certainly unequal (different hashes
+    // mean different strings), so a mismatch lies in [0, hi)
+    const int32_t p = lo + lane * cpw;
+    uint64_t d = 0;
+    if (p < hi) d = fetch(A, x + p) ^ fetch(B, y + p);
+    const uint64_t bm = ballot(d != 0);
+    if (bm) {
+        const int s = ctz64(bm);
+        const uint64_t dd = shfl_u64(d, s);
+        const int32_t c = lo + s * cpw + ctz64(dd) / A.bpc;
+        if (c < hi) return c;
+    }
+    // no mismatch in [lo, hi): a collision hid one below lo
+    if (lane == 0) cnt.collisions++;
+    return lcp_wave_direct(A, B, x, y, lim, 0);
+}
+
+// LDS table: hash of the 4 characters held by a packed byte,
+// c0 r^3 + c1 r^2 + c2 r + c3 with c_j = bits [2j, 2j+2) of the byte.
+__device__ __forceinline__ void build_lut4(uint64_t* lut4, uint64_t r, int tid, int nthreads) {
+    const uint64_t r2 = mp_mul(r, r);
+    const uint64_t r3 = mp_mul(r2, r);
+    for (int v = tid; v < 256; v += nthreads) {
+        const uint64_t c0 = v & 3, c1 = (v >> 2) & 3, c2 = (v >> 4) & 3, c3 = (v >> 6) & 3;
+        uint64_t h = mp_mul(c0, r3);
+        h = mp_add(h, mp_mul(c1, r2));
+        h = mp_add(h, mp_mul(c2, r));
+        h = mp_add(h, c3);
+        lut4[v] = h;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The slide of one diagonal: LCP(c, c - i) on the chosen engine.  Called by
+// all 64 lanes of a wave together; lanes with valid=false take part in the
+// wave-level work only.  Returns the LCP for valid lanes (0 otherwise).
+// ---------------------------------------------------------------------------
+struct Engine {
+    SView A, B;
+    const uint64_t* TA;
+    const uint64_t* TB;
+    HashQ q;
+    int32_t kind;        // 0 direct, 1 hash
+    int32_t lane_words;
+};
+
+__device__ __forceinline__ int32_t slide(const Engine& en, bool valid, int32_t x, int32_t y,
+                                         CountersDev& cnt) {
+    int32_t lim = 0, l = 0;
+    bool more = false;
+    if (valid) {
+        const int32_t la = en.A.len - x, lb = en.B.len - y;
+        lim = la < lb ? la : lb;
+        if (lim > 0) l = lcp_lane(en.A, en.B, x, y, lim, en.lane_words, &more);
+    }
+    uint64_t pend = ballot(more);
+    while (pend) {
+        const int src = ctz64(pend);
+        pend &= pend - 1;
+        const int32_t jx = shfl_i32(x, src), jy = shfl_i32(y, src);
+        const int32_t jlim = shfl_i32(lim, src), jl = shfl_i32(l, src);
+        int32_t r;
+        if (en.kind == 1 && jl > 0)
+            r = lcp_wave_hash(en.A, en.B, en.TA, en.TB, en.q, jx, jy, jlim, jl, cnt);
+        else
+            r = lcp_wave_direct(en.A, en.B, jx, jy, jlim, jl);
+        if (lane_id() == 0) cnt.wave_lcps++;
+        if (lane_id() == src) l = r;
+    }
+    if (valid) cnt.lcp_chars += static_cast<unsigned long long>(l);
+    return l;
+}
+
+__device__ __forceinline__ void flush_counters(CountersDev& c, CountersDev* g) {
+    // wave-level sums, then one atomic per wave and field
+    auto red = [](unsigned long long v) {
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        return v;
+    };
+    const unsigned long long u = red(c.updates), lc = red(c.lcp_chars), wl = red(c.wave_lcps),
+                             gl = red(c.grid_lcps), hq = red(c.hash_queries),
+                             hp = red(c.hash_probes), he = red(c.hash_eq_len),
+                             co = red(c.collisions);
+    if (lane_id() == 0 && g) {
+        if (u) atomicAdd(&g->updates, u);
+        if (lc) atomicAdd(&g->lcp_chars, lc);
+        if (wl) atomicAdd(&g->wave_lcps, wl);
+        if (gl) atomicAdd(&g->grid_lcps, gl);
+        if (hq) atomicAdd(&g->hash_queries, hq);
+        if (hp) atomicAdd(&g->hash_probes, hp);
+        if (he) atomicAdd(&g->hash_eq_len, he);
+        if (co) atomicAdd(&g->collisions, co);
+    }
+}
+
+}  // namespace ed

@@ -1,0 +1,85 @@
+// Host-side state of libed.so (context, pair, device memory pool).
+#pragma once
+#include <map>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/ed.h"
+#include "internal.h"
+
+namespace ed {
+
+// Device memory pool: released blocks are cached per size class and reused.
+class DevPool {
+  public:
+    void* get(size_t bytes);
+    void put(void* p);
+    void trim();
+    size_t cached() const { return cached_; }
+    ~DevPool();
+
+  private:
+    std::map<size_t, std::vector<void*>> free_;
+    std::unordered_map<void*, size_t> live_;
+    size_t cached_ = 0;
+};
+
+// pow0 (65536) | pow1 (65536) | r^0..r^64 | r^(64k), k = 0..256 | R^d, d = 0..64
+constexpr size_t kPowEntries = 2 * 65536 + 65 + 257 + 65;
+
+// layout of a pair's small device block
+constexpr size_t kMiscTicket = 0;
+constexpr size_t kMiscAlpha = 64;
+
+constexpr uint32_t kDefaultLdsRounds = 2048;
+
+}  // namespace ed
+
+struct ed_ctx {
+    int device = 0;
+    ed_options opt;
+    std::mutex mu;
+    int num_cu = 0;
+    int frontier_grid_max = 0;
+    uint64_t r = 0;              // hash base of opt.hash_seed
+    uint64_t* d_pow = nullptr;   // power tables (see kPowEntries)
+    ed::FrontierCtl* d_ctl = nullptr;
+    ed::CountersDev* d_cnt = nullptr;
+    ed::FrontierCtl* h_ctl = nullptr;  // pinned
+    ed::CountersDev* h_cnt = nullptr;  // pinned
+    ed::DevPool pool;
+};
+
+struct ed_pair {
+    ed_ctx* ctx = nullptr;
+    uint64_t len[2] = {0, 0};
+    uint32_t engine = 0;
+    int32_t log2b = 5;
+    int32_t force8 = 0;
+    uint64_t seed = 0;
+    void* w2[2] = {nullptr, nullptr};
+    void* w8[2] = {nullptr, nullptr};
+    void* tab[2] = {nullptr, nullptr};
+    void* stage[2] = {nullptr, nullptr};
+    void* misc = nullptr;  // ticket, alphabet word, tile status, tile flags
+    void* f0 = nullptr;    // unused (rows are per call)
+    void* f1 = nullptr;
+    uint64_t rounds = 0;
+    ed::CountersDev counters{};
+    int launches_prepare = 0;
+    int launches_distance = 0;
+    double ns_prepare = 0, ns_distance = 0;
+};
+
+namespace ed {
+void set_error(const char* fmt, ...);
+int ctx_set_hash(ed_ctx* c, uint64_t seed);
+void pair_free(ed_pair* p);
+PairDev pair_dev(const ed_pair* p);
+HashDev ctx_hash(const ed_ctx* c);
+int prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B, uint64_t m,
+                   int on_device, hipStream_t s, ed_pair** out);
+int distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, int32_t* rows,
+                    uint64_t rows_cap, hipStream_t s);
+}  // namespace ed

@@ -1,0 +1,172 @@
+// Structures shared by the host library and the kernels of libed.so.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ed {
+
+constexpr int32_t kNone = -(1 << 30);  // "no cell on this diagonal"
+constexpr uint64_t kP = 0x1FFFFFFFFFFFFFFFull;  // 2^61 - 1
+
+// Frontier kernels: threads per workgroup.
+constexpr int kFrontierThreads = 1024;
+// Largest number of rounds one workgroup keeps in LDS (two int32 rows of
+// 2*kLdsRoundsMax + 5 entries each).
+constexpr int kLdsRoundsMax = 4096;
+constexpr int kLdsRowLen = 2 * kLdsRoundsMax + 5;
+
+// Prepare kernel: 256 threads x 64 characters per tile.
+constexpr int kPrepThreads = 256;
+constexpr int kSegChars = 64;
+constexpr int kTileChars = kPrepThreads * kSegChars;  // 16384
+constexpr int kTileWords2 = kTileChars / 32;          // 512 packed words per tile
+constexpr int kTileWords8 = kTileChars / 8;           // 2048 byte-words per tile
+// Words of zero padding after the last tile of every packed buffer.
+constexpr int kPadWords = 256;
+
+// Tile status of the decoupled look-back scan: value in bits 0..60, flag in
+// bits 62..63.
+constexpr uint64_t kTileAgg = 1ull << 62;
+constexpr uint64_t kTileInc = 2ull << 62;
+constexpr uint64_t kTileValMask = (1ull << 61) - 1;
+
+// One string as the kernels see it.
+struct StrDev {
+    const uint64_t* w2;   // 2-bit packed words (always written)
+    const uint64_t* w8;   // 8-bit copy as words (written when not packable)
+    const uint64_t* tab;  // prefix table (hash engine) or nullptr
+    int32_t len;
+    int32_t pad_;
+};
+
+// One pair.
+struct PairDev {
+    StrDev a, b;
+    const uint32_t* alpha;  // device word: OR of all characters of A and B (+ force bits)
+    int32_t log2b;          // hash block size b = 1 << log2b
+    int32_t force8;         // 1 = use the 8-bit copies even if packable
+};
+
+// Hash parameters shared by build and query.
+struct HashDev {
+    uint64_t r;             // base
+    const uint64_t* pow0;   // r^a, a < 65536
+    const uint64_t* pow1;   // r^(65536 a), a < 65536
+};
+
+// Per-run counters (device), summed with atomics at kernel exit.
+struct CountersDev {
+    unsigned long long updates;
+    unsigned long long lcp_chars;
+    unsigned long long wave_lcps;
+    unsigned long long grid_lcps;
+    unsigned long long hash_queries;
+    unsigned long long hash_probes;
+    unsigned long long hash_eq_len;  // sum of L over hash "equal" verdicts
+    unsigned long long collisions;
+};
+
+// Control block of one single-pair launch (device memory).
+struct FrontierCtl {
+    unsigned int bar_count;
+    unsigned int bar_gen;
+    int32_t phase;     // 0: one workgroup; 1: grid-wide
+    int32_t phase_t;   // round reached when going grid-wide
+    int32_t found_t;   // first round whose frontier reaches (n, m); -1 before
+    int32_t status;    // 0 running, 1 done, 2 k_max reached, 3 out of capacity
+    int32_t result_t;  // reported rounds (k, k_max + 1, or last round at capacity)
+    int32_t wbuf;      // which buffer (0/1) holds the last frontier
+};
+
+struct FrontierParams {
+    PairDev p;
+    HashDev h;
+    int32_t* f0;       // global frontier rows, 2K+5 entries each, diagonal i at [i + K + 2]
+    int32_t* f1;
+    int32_t K;         // supports rounds t <= K
+    int32_t t0;        // first round already computed (resume: f_t0 is in f0)
+    int32_t kmax;      // -1 = none
+    int32_t lds_rounds;  // rounds run by workgroup 0 in LDS (<= kLdsRoundsMax)
+    int32_t engine;
+    int32_t lane_words;
+    FrontierCtl* ctl;
+    int32_t* dump;     // optional per-round rows (device), row t at t*t
+    int64_t dump_cap;
+    CountersDev* counters;
+};
+
+// Batched launch: one descriptor per pair.
+struct BatchItem {
+    PairDev p;
+    int32_t* f0;       // global rows for rounds beyond the LDS phase (2K+5 each)
+    int32_t* f1;
+    int32_t K;
+    int32_t pad_;
+};
+
+struct BatchParams {
+    const BatchItem* items;
+    const int32_t* order;   // processing order (largest first)
+    int32_t count;
+    int32_t kmax;
+    int32_t engine;
+    int32_t lane_words;
+    int32_t lds_rounds;
+    int32_t pad_;
+    HashDev h;
+    unsigned int* ticket;   // work queue head
+    int32_t* k_out;         // per pair: k, k_max + 1, or -3 (capacity, internal error)
+    CountersDev* counters;
+};
+
+// Prepare launch: both strings of one pair in one kernel.
+struct PrepString {
+    const uint8_t* raw;    // input bytes (device), 16-byte aligned
+    uint64_t* w2;          // packed output
+    uint64_t* w8;          // 8-bit copy output
+    uint64_t* tab;         // prefix table output (nullptr: no table)
+    int32_t len;
+    int32_t tiles;         // ceil(len / kTileChars), at least 1
+    int32_t tile0;         // first global tile index of this string
+    int32_t pad_;
+};
+
+struct PrepParams {
+    PrepString s[2];
+    int32_t total_tiles;
+    int32_t log2b;
+    int32_t force8;        // write 8-bit copies of every tile
+    int32_t build_table;
+    uint64_t r;            // hash base
+    uint64_t* tile_status; // total_tiles entries, zeroed before launch
+    unsigned int* ticket;  // tile ticket counter, zeroed before launch
+    uint32_t* alpha;       // OR of all characters (atomicOr), zeroed before launch
+    uint8_t* tile_big;     // per tile: 1 if the tile has a character > 3
+    const uint64_t* rtab;  // r^0..r^64 | r^(64k), k = 0..256 | R^d, d = 0..64, R = r^kTileChars
+};
+
+struct LcpQueryParams {
+    PairDev p;
+    HashDev h;
+    const int64_t* x;
+    const int64_t* y;
+    int64_t* out;
+    int64_t count;
+    int32_t engine;
+    int32_t lane_words;
+    CountersDev* counters;
+};
+
+// Kernel launchers (defined in the .hip files).
+hipError_t launch_prep_clear(const PrepParams& pp, hipStream_t s);
+hipError_t launch_prepare(const PrepParams& pp, int grid, hipStream_t s);
+hipError_t launch_copy8_rest(const PrepParams& pp, hipStream_t s);
+hipError_t launch_ctl_init(FrontierCtl* ctl, CountersDev* cnt, hipStream_t s);
+hipError_t launch_frontier(const FrontierParams& fp, int grid, hipStream_t s);
+hipError_t frontier_max_grid(int device, int* grid_out);
+hipError_t launch_batch(const BatchParams& bp, int grid, hipStream_t s);
+hipError_t launch_lcp_queries(const LcpQueryParams& qp, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t s);
+
+}  // namespace ed

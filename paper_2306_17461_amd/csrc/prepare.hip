@@ -1,0 +1,351 @@
+// Prepare: one pass over the input bytes of both strings of a pair.
+//   * alphabet detection: bitwise OR of every character (2-bit packing is
+//     possible when the OR is <= 3);
+//   * 2-bit packing (speculative: always written, used only when packable);
+//   * 8-bit copy of every tile holding a character > 3 (the rest of the copy,
+//     if needed, is written by a second, small kernel);
+//   * prefix table T[j] = h(S[0..jb)) mod 2^61-1 (sections 3.2 and 3.3,
+//     Algorithm 2 "Build"): block hashes from LDS lookup tables (h is linear in
+//     the characters), then a single-pass scan over tiles with decoupled
+//     look-back under the concatenation h(S1 S2) = h(S1) r^|S2| + h(S2).
+#include "device.h"
+
+namespace ed {
+
+namespace {
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+struct PrepShared {
+    uint64_t lut32[8][256];  // packed byte k of a 2-bit word: sum_j c_j r^(31-4k-j)
+    uint64_t lut8[8][256];   // byte k of an 8-char word: v r^(7-k)
+    uint64_t lut4[256];      // packed byte (4 chars): c0 r^3 + c1 r^2 + c2 r + c3
+    uint64_t rp[65];         // r^p
+    uint64_t rseg[257];      // r^(64 k)
+    uint64_t tilepow[65];    // R^d, R = r^16384
+    uint64_t wsum[kPrepThreads / 64];
+    uint64_t excl;
+    int32_t tile;
+    uint32_t tor;
+};
+
+__device__ __forceinline__ uint32_t pack_dword(uint32_t d) {
+    // four 8-bit characters -> four 2-bit codes (low bits of each byte)
+    return (d & 3u) | ((d >> 6) & 0xCu) | ((d >> 12) & 0x30u) | ((d >> 18) & 0xC0u);
+}
+
+// Hash of the 64 characters of one segment, processed in units of U chars
+// (U divides b); when EMIT, writes T at every block end inside the segment.
+// `h` enters as the prefix hash at the segment start.
+template <bool EMIT>
+__device__ __forceinline__ uint64_t seg_pass(const PrepShared& S, const uint32_t (&dw)[16],
+                                             const uint64_t (&pk)[2], bool big, int32_t log2b,
+                                             uint64_t h, int32_t seg_start, int32_t len,
+                                             uint64_t* tab) {
+    const int32_t bmask = (1 << log2b) - 1;
+    auto emit = [&](int32_t pos) {
+        if (EMIT) {
+            const int32_t e = seg_start + pos;
+            if ((e & bmask) == 0 && e <= len) tab[e >> log2b] = h;
+        }
+    };
+    if (!big) {
+        if (log2b >= 5) {  // units of 32 characters: one packed word
+            for (int w = 0; w < 2; ++w) {
+                uint64_t s = 0;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) s += S.lut32[k][(pk[w] >> (8 * k)) & 0xFF];
+                h = mp_add(mp_mul(h, S.rp[32]), mp_fold(s));
+                emit(32 * (w + 1));
+            }
+        } else if (log2b >= 2) {  // units of 4 characters: one packed byte
+            for (int u = 0; u < 16; ++u) {
+                const uint32_t byte = static_cast<uint32_t>(pk[u >> 3] >> (8 * (u & 7))) & 0xFFu;
+                h = mp_add(mp_mul(h, S.rp[4]), S.lut4[byte]);
+                emit(4 * (u + 1));
+            }
+        } else {  // single characters
+            for (int c = 0; c < 64; ++c) {
+                const uint64_t ch = (dw[c >> 2] >> (8 * (c & 3))) & 0xFFu;
+                h = mp_add(mp_mul(h, S.rp[1]), ch);
+                emit(c + 1);
+            }
+        }
+    } else {
+        if (log2b >= 3) {  // units of 8 characters: one 8-bit word
+            for (int w = 0; w < 8; ++w) {
+                uint64_t s = 0;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const uint32_t v = (dw[2 * w + (k >> 2)] >> (8 * (k & 3))) & 0xFFu;
+                    s += S.lut8[k][v];
+                }
+                h = mp_add(mp_mul(h, S.rp[8]), mp_fold(s));
+                emit(8 * (w + 1));
+            }
+        } else {
+            for (int c = 0; c < 64; ++c) {
+                const uint64_t ch = (dw[c >> 2] >> (8 * (c & 3))) & 0xFFu;
+                h = mp_add(mp_mul(h, S.rp[1]), ch);
+                emit(c + 1);
+            }
+        }
+    }
+    return h;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_mod(uint64_t v) {
+    for (int o = 32; o > 0; o >>= 1) v = mp_add(v, __shfl_xor(static_cast<unsigned long long>(v), o));
+    return v;
+}
+
+}  // namespace
+
+__global__ void prep_clear_kernel(PrepParams P) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < P.total_tiles) {
+        P.tile_status[i] = 0;
+        P.tile_big[i] = 0;
+    }
+    if (i == 0) {
+        *P.ticket = 0u;
+        *P.alpha = 0u;
+    }
+}
+
+__global__ __launch_bounds__(kPrepThreads) void prepare_kernel(PrepParams P, const uint64_t* rtab) {
+    __shared__ PrepShared S;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+
+    if (P.build_table) {
+        // rtab: r^0..r^64 | r^(64k), k = 0..256 | R^d, d = 0..64
+        for (int i = tid; i < 65; i += kPrepThreads) S.rp[i] = rtab[i];
+        for (int i = tid; i < 257; i += kPrepThreads) S.rseg[i] = rtab[65 + i];
+        for (int i = tid; i < 65; i += kPrepThreads) S.tilepow[i] = rtab[65 + 257 + i];
+        __syncthreads();
+        for (int e = tid; e < 8 * 256; e += kPrepThreads) {
+            const int k = e >> 8, v = e & 255;
+            uint64_t h = 0;
+            for (int j = 0; j < 4; ++j)
+                h = mp_add(h, mp_mul(static_cast<uint64_t>((v >> (2 * j)) & 3), S.rp[31 - 4 * k - j]));
+            S.lut32[k][v] = h;
+            S.lut8[k][v] = mp_mul(static_cast<uint64_t>(v), S.rp[7 - k]);
+        }
+        for (int v = tid; v < 256; v += kPrepThreads) {
+            uint64_t h = 0;
+            for (int j = 0; j < 4; ++j)
+                h = mp_add(h, mp_mul(static_cast<uint64_t>((v >> (2 * j)) & 3), S.rp[3 - j]));
+            S.lut4[v] = h;
+        }
+    }
+
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) {
+            S.tile = static_cast<int32_t>(atomicAdd(P.ticket, 1u));
+            S.tor = 0u;
+        }
+        __syncthreads();
+        const int32_t g = S.tile;
+        if (g >= P.total_tiles) break;
+        const int si = g >= P.s[1].tile0 ? 1 : 0;
+        const PrepString& str = P.s[si];
+        const int32_t t = g - str.tile0;
+        const int32_t seg_start = t * kTileChars + tid * kSegChars;
+        const int32_t len = str.len;
+
+        // ---- load 64 characters (zero beyond the string) ----
+        uint32_t dw[16];
+        if (seg_start + kSegChars <= len) {
+            const u32x4* src = reinterpret_cast<const u32x4*>(str.raw + seg_start);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const u32x4 v = __builtin_nontemporal_load(src + k);
+                dw[4 * k + 0] = v.x;
+                dw[4 * k + 1] = v.y;
+                dw[4 * k + 2] = v.z;
+                dw[4 * k + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                uint32_t d = 0;
+                for (int j = 0; j < 4; ++j) {
+                    const int32_t p = seg_start + 4 * k + j;
+                    if (p < len) d |= static_cast<uint32_t>(str.raw[p]) << (8 * j);
+                }
+                dw[k] = d;
+            }
+        }
+
+        // ---- alphabet OR ----
+        uint32_t o = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) o |= dw[k];
+        o |= o >> 16;
+        o |= o >> 8;
+        o &= 0xFFu;
+        for (int s = 32; s > 0; s >>= 1) o |= __shfl_xor(o, s);
+        if (lane == 0) atomicOr(&S.tor, o);
+
+        // ---- 2-bit pack: 32 characters per word ----
+        uint64_t pk[2];
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            uint64_t v = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v |= static_cast<uint64_t>(pack_dword(dw[8 * w + k])) << (8 * k);
+            pk[w] = v;
+        }
+        {
+            uint64_t* dst = str.w2 + static_cast<int64_t>(t) * kTileWords2 + tid * 2;
+            dst[0] = pk[0];
+            dst[1] = pk[1];
+        }
+        __syncthreads();
+        const uint32_t tor = S.tor;
+        const bool big = tor > 3u;
+        if (tid == 0) {
+            if (tor) atomicOr(P.alpha, tor);
+            P.tile_big[g] = big ? 1 : 0;
+        }
+        // ---- 8-bit copy of tiles that cannot be packed ----
+        if (big || P.force8) {
+            uint64_t* dst = str.w8 + static_cast<int64_t>(t) * kTileWords8 + tid * 8;
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                dst[k] = static_cast<uint64_t>(dw[2 * k]) | (static_cast<uint64_t>(dw[2 * k + 1]) << 32);
+        }
+        if (!P.build_table) continue;
+
+        // ---- segment hash, block-scan within the tile ----
+        const uint64_t hseg = seg_pass<false>(S, dw, pk, big, P.log2b, 0, seg_start, len, nullptr);
+        uint64_t x = hseg;  // inclusive over the wave, Hillis-Steele
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint64_t y = __shfl_up(static_cast<unsigned long long>(x), d);
+            if (lane >= d) x = mp_add(mp_mul(y, S.rseg[d]), x);
+        }
+        if (lane == 63) S.wsum[wave] = x;
+        __syncthreads();
+        uint64_t pre = 0;  // hash of the waves before this one
+        for (int v = 0; v < wave; ++v) pre = mp_add(mp_mul(pre, S.rseg[64]), S.wsum[v]);
+        const uint64_t xprev = __shfl_up(static_cast<unsigned long long>(x), 1);
+        const uint64_t excl_thread = lane == 0 ? pre : mp_add(mp_mul(pre, S.rseg[lane]), xprev);
+
+        // ---- decoupled look-back over tiles (wave 0) ----
+        if (wave == 0) {
+            uint64_t agg = 0;
+            for (int v = 0; v < kPrepThreads / 64; ++v) agg = mp_add(mp_mul(agg, S.rseg[64]), S.wsum[v]);
+            uint64_t* status = P.tile_status + str.tile0;
+            uint64_t excl = 0;
+            if (t == 0) {
+                if (lane == 0)
+                    __hip_atomic_store(status + t, kTileInc | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                if (lane == 0)
+                    __hip_atomic_store(status + t, kTileAgg | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                uint64_t acc = 0, mul = 1;
+                int32_t base = t - 1;
+                for (;;) {
+                    const int32_t pidx = base - lane;
+                    uint64_t st;
+                    if (pidx < 0) {
+                        st = kTileInc;  // the prefix before the first tile is h(empty) = 0
+                    } else {
+                        do {
+                            st = __hip_atomic_load(status + pidx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        } while ((st >> 62) == 0);
+                    }
+                    const uint64_t incm = ballot((st >> 62) == 2);
+                    const int f = incm ? ctz64(incm) : 64;
+                    const uint64_t term = lane <= f ? mp_mul(st & kTileValMask, S.tilepow[lane]) : 0;
+                    const uint64_t sum = wave_sum_mod(term);
+                    acc = mp_add(acc, mp_mul(sum, mul));
+                    if (incm) break;
+                    mul = mp_mul(mul, S.tilepow[64]);
+                    base -= 64;
+                }
+                excl = acc;
+                if (lane == 0)
+                    __hip_atomic_store(status + t, kTileInc | mp_add(mp_mul(excl, S.tilepow[1]), agg),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (lane == 0) S.excl = excl;
+        }
+        __syncthreads();
+        // ---- emit T at block ends: prefix at segment start, then the units ----
+        const uint64_t hstart = mp_add(mp_mul(S.excl, S.rseg[tid]), excl_thread);
+        if (seg_start < len) seg_pass<true>(S, dw, pk, big, P.log2b, hstart, seg_start, len, str.tab);
+        if (t == 0 && tid == 0) str.tab[0] = 0;
+    }
+}
+
+// Second pass for strings that cannot be packed: 8-bit copy of the tiles the
+// first pass skipped.  One workgroup per tile; exits at once when packable.
+__global__ __launch_bounds__(kPrepThreads) void copy8_rest_kernel(PrepParams P) {
+    const uint32_t alpha = *P.alpha;
+    if (alpha <= 3u || P.force8) return;
+    const int32_t g = blockIdx.x;
+    if (g >= P.total_tiles || P.tile_big[g]) return;
+    const int si = g >= P.s[1].tile0 ? 1 : 0;
+    const PrepString& str = P.s[si];
+    const int32_t t = g - str.tile0;
+    const int32_t seg_start = t * kTileChars + threadIdx.x * kSegChars;
+    uint64_t* dst = str.w8 + static_cast<int64_t>(t) * kTileWords8 + threadIdx.x * 8;
+    for (int k = 0; k < 8; ++k) {
+        uint64_t v = 0;
+        for (int j = 0; j < 8; ++j) {
+            const int32_t p = seg_start + 8 * k + j;
+            if (p < str.len) v |= static_cast<uint64_t>(str.raw[p]) << (8 * j);
+        }
+        dst[k] = v;
+    }
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void fill_u32_kernel(unsigned int* p, int64_t n, unsigned int v) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_prep_clear(const PrepParams& pp, hipStream_t s) {
+    const int blocks = (pp.total_tiles + 255) / 256 + 1;
+    hipLaunchKernelGGL(prep_clear_kernel, dim3(blocks), dim3(256), 0, s, pp);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepare(const PrepParams& pp, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(prepare_kernel, dim3(grid), dim3(kPrepThreads), 0, s, pp, pp.rtab);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy8_rest(const PrepParams& pp, hipStream_t s) {
+    hipLaunchKernelGGL(copy8_rest_kernel, dim3(pp.total_tiles), dim3(kPrepThreads), 0, s, pp);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace ed

@@ -1,0 +1,339 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Every comparison is exact: the edit distance, the frontier rows, the LCPs, the
+packed strings and the prefix tables are integers.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ed():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2306_17461_amd as edmod
+    return edmod
+
+
+@pytest.fixture(scope="module")
+def make_ctx(ed):
+    made = []
+
+    def make(**kw):
+        c = ed.ed_init(0, **kw)
+        made.append(c)
+        return c
+
+    yield make
+    for c in made:
+        ed.ed_shutdown(c)
+
+
+def gpu_ed(ed, ctx, A, B, k_max=-1):
+    p = ed.ed_prepare(ctx, A, B)
+    try:
+        return ed.ed_distance(ctx, p, k_max)
+    finally:
+        ed.ed_release(p)
+
+
+def unpack2(words_u8, n):
+    w = words_u8.view(np.uint64)
+    out = np.empty(len(w) * 32, dtype=np.uint8)
+    for j in range(32):
+        out[j::32] = ((w >> np.uint64(2 * j)) & np.uint64(3)).astype(np.uint8)
+    return out[:n]
+
+
+# ---------------------------------------------------------------------------
+# pack, copy, alphabet detection
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [0, 1, 31, 32, 33, 1000, 16383, 16384, 16385, 100003])
+def test_pack_roundtrip(ed, make_ctx, n):
+    say("pack", n)
+    ctx = make_ctx()
+    A = synth.random_string(n, synth.CharDist("uniform", 4), 7)
+    B = synth.random_string(n // 2 + 3, synth.CharDist("uniform", 4), 8)
+    p = ed.ed_prepare(ctx, A, B)
+    st = ed.ed_pair_stats(p)
+    assert st["bits_per_char"] == 2
+    assert np.array_equal(unpack2(ed.ed_pair_buffer(ctx, p, 0, ed.BUF_PACKED2), n), A)
+    assert np.array_equal(unpack2(ed.ed_pair_buffer(ctx, p, 1, ed.BUF_PACKED2), len(B)), B)
+    ed.ed_release(p)
+
+
+@pytest.mark.parametrize("case", ["sigma256", "mixed", "force8"])
+def test_byte_copy(ed, make_ctx, case):
+    say("bytes", case)
+    n = 50000
+    if case == "sigma256":
+        ctx = make_ctx()
+        A = synth.random_string(n, synth.CharDist("uniform", 256), 1)
+        B = synth.random_string(n + 7, synth.CharDist("uniform", 256), 2)
+    elif case == "mixed":
+        # one string packable everywhere, the other with a large character in one tile only
+        ctx = make_ctx()
+        A = synth.random_string(n, synth.CharDist("uniform", 4), 3)
+        B = synth.random_string(n, synth.CharDist("uniform", 4), 4)
+        B[40000] = 200
+    else:
+        ctx = make_ctx(pack_bits=8)
+        A = synth.random_string(n, synth.CharDist("uniform", 4), 5)
+        B = synth.random_string(n - 5, synth.CharDist("uniform", 4), 6)
+    p = ed.ed_prepare(ctx, A, B)
+    assert ed.ed_pair_stats(p)["bits_per_char"] == 8
+    assert np.array_equal(ed.ed_pair_buffer(ctx, p, 0, ed.BUF_BYTES), A)
+    assert np.array_equal(ed.ed_pair_buffer(ctx, p, 1, ed.BUF_BYTES), B)
+    ed.ed_release(p)
+
+
+def test_pack2_rejects_large_characters(ed, make_ctx):
+    say("pack2 reject")
+    ctx = make_ctx(pack_bits=2)
+    A = np.array([0, 1, 2, 3, 7], np.uint8)
+    with pytest.raises(ed.EdError) as ei:
+        ed.ed_prepare(ctx, A, A)
+    assert ei.value.status == ed.ED_EINVAL
+
+
+# ---------------------------------------------------------------------------
+# prefix tables: bit-exact against Horner's rule (sections 3.2, 3.3)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("b", [1, 2, 4, 8, 16, 32, 64, 128, 1024, 4096])
+@pytest.mark.parametrize("alpha", ["sigma4", "sigma256", "mixed"])
+def test_table_bit_exact(ed, make_ctx, orc, b, alpha):
+    say("table", b, alpha)
+    seed = 1000 + b
+    ctx = make_ctx(engine=ed.ENGINE_HASH, block=b, hash_seed=seed)
+    base = orc.hash_base(seed)
+    for n in [0, 1, b - 1, b, b + 1, 16384 + 3 * b + 1, 3 * 16384, 70001]:
+        if n < 0:
+            continue
+        if alpha == "sigma256":
+            A = synth.random_string(n, synth.CharDist("uniform", 256), n + 1)
+        else:
+            A = synth.random_string(n, synth.CharDist("uniform", 4), n + 1)
+            if alpha == "mixed" and n > 20000:
+                A[20000] = 255
+        B = synth.random_string(n // 3 + 1, synth.CharDist("uniform", 4), n + 2)
+        p = ed.ed_prepare(ctx, A, B)
+        TA = ed.ed_pair_buffer(ctx, p, 0, ed.BUF_TABLE)
+        TB = ed.ed_pair_buffer(ctx, p, 1, ed.BUF_TABLE)
+        np.testing.assert_array_equal(TA, orc.horner_table(A, b, base), err_msg="A n=%d" % n)
+        np.testing.assert_array_equal(TB, orc.horner_table(B, b, base), err_msg="B n=%d" % n)
+        ed.ed_release(p)
+
+
+# ---------------------------------------------------------------------------
+# LCP engines against the character loop (section 2)
+# ---------------------------------------------------------------------------
+def _lcp_cases():
+    d4 = synth.CharDist("uniform", 4)
+    d256 = synth.CharDist("uniform", 256)
+    A = synth.random_string(30000, d4, 11)
+    B, _ = synth.plant_edits(A, 12, d4, 12)
+    yield "sigma4_planted", A, B
+    A = synth.random_string(30000, d256, 13)
+    B, _ = synth.plant_edits(A, 12, d256, 14)
+    yield "sigma256_planted", A, B
+    A = synth.random_string(70000, d4, 15)
+    yield "equal", A, A.copy()
+    P = synth.periodic_string(50000, d4, 16, period=64)
+    yield "periodic", P, P.copy()
+    Z = np.zeros(5000, np.uint8)
+    yield "zeros", Z, Z.copy()
+
+
+@pytest.mark.parametrize("engine", [0, 1])
+@pytest.mark.parametrize("pack_bits", [0, 8])
+@pytest.mark.parametrize("block", [32, 1, 4, 256])
+def test_lcp_engines(ed, make_ctx, orc, engine, pack_bits, block):
+    if engine == 0 and block != 32:
+        pytest.skip("block size only matters for the hash engine")
+    rng = np.random.default_rng(engine * 100 + pack_bits + block)
+    ctx = make_ctx(engine=engine, pack_bits=pack_bits, block=block, hash_seed=77)
+    for name, A, B in _lcp_cases():
+        say("lcp", engine, pack_bits, block, name)
+        n, m = len(A), len(B)
+        xs, ys = [], []
+        # every alignment pair mod 32 near the start, near the end, and the ends themselves
+        for a in range(32):
+            for c in range(0, 32, 3):
+                xs.append(a); ys.append(c)
+                xs.append(max(0, n - 64 + a)); ys.append(max(0, m - 64 + c))
+        xs += [n, 0, n, 0]; ys += [m, m, 0, 0]
+        # diagonal-aligned queries (long LCPs on planted pairs)
+        for _ in range(200):
+            x = int(rng.integers(0, n + 1))
+            d = int(rng.integers(-15, 16))
+            xs.append(x); ys.append(min(m, max(0, x + d)))
+        for _ in range(200):
+            xs.append(int(rng.integers(0, n + 1))); ys.append(int(rng.integers(0, m + 1)))
+        p = ed.ed_prepare(ctx, A, B)
+        got = ed.ed_debug_lcp(ctx, p, xs, ys)
+        want = np.array([orc.lcp(A, B, x, y) for x, y in zip(xs, ys)])
+        bad = np.nonzero(got != want)[0]
+        assert len(bad) == 0, [(xs[i], ys[i], int(got[i]), int(want[i])) for i in bad[:10]]
+        ed.ed_release(p)
+
+
+# ---------------------------------------------------------------------------
+# frontier rows: every f_t[i] against R_t from the DP matrix (T2)
+# ---------------------------------------------------------------------------
+FRONTIER_MODES = [
+    ("lds", dict()),
+    ("grid", dict(flags=2)),
+    ("lds3", dict(lds_rounds=3)),
+    ("grow", dict(lds_rounds=2, init_rows=4)),
+]
+
+
+@pytest.mark.parametrize("engine", [0, 1])
+@pytest.mark.parametrize("mode", [m[0] for m in FRONTIER_MODES])
+def test_frontier_rows(ed, make_ctx, orc, engine, mode):
+    kw = dict(FRONTIER_MODES)[mode]
+    ctx = make_ctx(engine=engine, **kw)
+    rng = np.random.default_rng(1 + engine)
+    cases = [(np.zeros(0, np.uint8), np.zeros(0, np.uint8)),
+             (np.zeros(0, np.uint8), np.array([1, 2, 3], np.uint8)),
+             (np.array([3, 2, 1, 0], np.uint8), np.zeros(0, np.uint8)),
+             (np.array([1], np.uint8), np.array([1], np.uint8))]
+    for _ in range(25):
+        sigma = int(rng.choice([2, 4, 20, 256]))
+        n = int(rng.integers(0, 300))
+        d = synth.CharDist("uniform", sigma)
+        A = synth.random_string(n, d, int(rng.integers(1 << 30)))
+        B, _ = synth.plant_edits(A, int(rng.integers(0, 40)), d, int(rng.integers(1 << 30)))
+        cases.append((A, B))
+    for ci, (A, B) in enumerate(cases):
+        say("rows", engine, mode, ci, len(A), len(B))
+        ed_ref, rows_ref = orc.rt_dump(A, B)
+        p = ed.ed_prepare(ctx, A, B)
+        cap = (max(len(A), len(B)) + 2) ** 2
+        k, rows = ed.ed_distance_dump(ctx, p, cap)
+        ed.ed_release(p)
+        assert k == ed_ref
+        np.testing.assert_array_equal(rows, rows_ref, err_msg="case %d" % ci)
+
+
+# ---------------------------------------------------------------------------
+# distances
+# ---------------------------------------------------------------------------
+def test_config1_all_seeds_direct(ed, make_ctx, orc):
+    ctx = make_ctx(engine=0)
+    for seed in range(100):
+        A, B, info = synth.small_pair(seed)
+        say("config1 direct", seed)
+        assert gpu_ed(ed, ctx, A, B) == orc.lv_naive(A, B), seed
+
+
+def test_config1_seeds_hash(ed, make_ctx, orc):
+    ctx = make_ctx(engine=1)
+    for seed in range(30):
+        A, B, info = synth.small_pair(seed)
+        say("config1 hash", seed)
+        assert gpu_ed(ed, ctx, A, B) == orc.lv_naive(A, B), seed
+
+
+@pytest.mark.parametrize("engine", [0, 1])
+def test_edge_cases(ed, make_ctx, orc, engine):
+    ctx = make_ctx(engine=engine)
+    d4 = synth.CharDist("uniform", 4)
+    X = synth.random_string(5000, d4, 1)
+    Y = synth.random_string(3000, d4, 2)
+    cases = {
+        "empty": (np.zeros(0, np.uint8), np.zeros(0, np.uint8)),
+        "emptyA": (np.zeros(0, np.uint8), X),
+        "emptyB": (X, np.zeros(0, np.uint8)),
+        "identical": (X, X.copy()),
+        "prefix": (X, X[:4000].copy()),
+        "suffix": (X[1000:].copy(), X),
+        "unrelated": (X[:1500].copy(), Y[:1500].copy()),
+        "lengths": (X, Y[:200].copy()),
+        "ones": (np.array([1], np.uint8), np.array([2], np.uint8)),
+        "zeros_vs_ones": (np.zeros(700, np.uint8), np.ones(900, np.uint8)),
+        "periodic": (synth.periodic_string(9000, d4, 3, 64), synth.periodic_string(9050, d4, 3, 64)),
+    }
+    for name, (A, B) in cases.items():
+        say("edge", engine, name)
+        want = orc.lv_omp(A, B)
+        assert gpu_ed(ed, ctx, A, B) == want, name
+        assert gpu_ed(ed, ctx, B, A) == want, name + " swapped"
+
+
+@pytest.mark.parametrize("engine", [0, 1])
+def test_k_max_cutoff(ed, make_ctx, orc, engine):
+    ctx = make_ctx(engine=engine)
+    A, B, _ = synth.single_pair(20000, 300, 5)
+    k = orc.lv_omp(A, B)
+    say("kmax", engine, k)
+    assert gpu_ed(ed, ctx, A, B, k_max=k) == k
+    assert gpu_ed(ed, ctx, A, B, k_max=k + 10) == k
+    assert gpu_ed(ed, ctx, A, B, k_max=k - 1) == k
+    assert gpu_ed(ed, ctx, A, B, k_max=k // 3) == k // 3 + 1
+
+
+@pytest.mark.parametrize("engine", [0, 1])
+@pytest.mark.parametrize("mode", ["default", "grid", "grow"])
+def test_medium_pairs(ed, make_ctx, orc, engine, mode):
+    kw = {"default": {}, "grid": dict(flags=2), "grow": dict(lds_rounds=64, init_rows=100)}[mode]
+    ctx = make_ctx(engine=engine, **kw)
+    for (n, k, sigma, seed) in [(200000, 3000, 4, 1), (100000, 9000, 4, 2), (150000, 2000, 20, 3),
+                                (300000, 500, 256, 4), (60000, 6000, 2, 5)]:
+        A, B, _ = synth.single_pair(n, k, seed, sigma=sigma)
+        say("medium", engine, mode, n, k, sigma)
+        assert gpu_ed(ed, ctx, A, B) == orc.lv_omp(A, B)
+
+
+# ---------------------------------------------------------------------------
+# batch
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("engine", [0, 1])
+def test_batch_matches_oracle_and_single(ed, make_ctx, orc, engine):
+    ctx = make_ctx(engine=engine)
+    specs = synth.batch_specs(300, 9, lo_exp=1.0, hi_exp=4.7, kfrac=0.05)
+    pairs, want = [], []
+    for n, k, ps in specs:
+        A, B, _ = synth.single_pair(n, k, ps)
+        pairs.append(ed.ed_prepare(ctx, A, B))
+        want.append(orc.lv_omp(A, B))
+    say("batch", engine, len(pairs))
+    got, st = ed.ed_batch(ctx, pairs)
+    assert st == [0] * len(pairs)
+    assert got == want
+    single = [ed.ed_distance(ctx, p) for p in pairs[:40]]
+    assert single == want[:40]
+    ed.ed_set_options(ctx, engine=engine, flags=4, hash_seed=0x5EED)
+    got2, _ = ed.ed_batch(ctx, pairs)
+    assert got2 == want
+    ed.ed_set_options(ctx, engine=engine, lds_rounds=16, flags=4, hash_seed=0x5EED)
+    got3, _ = ed.ed_batch(ctx, pairs)
+    assert got3 == want
+    for p in pairs:
+        ed.ed_release(p)
+
+
+def test_device_inputs_and_unaligned(ed, make_ctx, orc):
+    import torch
+    ctx = make_ctx()
+    A, B, _ = synth.single_pair(30000, 200, 21)
+    want = orc.lv_omp(A, B)
+    tA = torch.from_numpy(A).cuda()
+    tB = torch.from_numpy(B).cuda()
+    say("device inputs")
+    assert gpu_ed(ed, ctx, tA, tB) == want
+    # unaligned device views go through a staging copy
+    tA2 = torch.zeros(len(A) + 3, dtype=torch.uint8, device="cuda")
+    tA2[3:] = tA
+    assert gpu_ed(ed, ctx, tA2[3:], tB) == want
