@@ -1,0 +1,197 @@
+"""Benchmark: exact edit distance, chars/sec at n = 1e8 for k = 1e2, 1e3, 1e4, 1e5.
+
+One step = the whole hot path for the four single pairs (A: 1e8 characters
+uniform over {0,1,2,3}; B = A with k planted edits; seed 0): for each pair,
+alphabet detection, 2-bit packing, [prefix tables], all frontier rounds with
+LCP extension, and the distance read back to the host.  Inputs are resident in
+device memory (torch uint8 tensors) when the timed region starts.
+
+    value = 4e8 characters / (seconds per step)
+
+Prints one JSON line.  With --gpus N > 1 it exits: this build measures one GPU.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+KS = [100, 1000, 10000, 100000]
+N = 10 ** 8
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def pair_stats(ed, pair):
+    return ed.ed_pair_stats(pair)
+
+
+def run_pair(ed, ctx, tA, tB, stream):
+    pair = ed.ed_prepare(ctx, tA, tB, stream=stream)
+    k = ed.ed_distance(ctx, pair, stream=stream)
+    st = pair_stats(ed, pair)
+    ed.ed_release(pair)
+    return k, st
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--engine", choices=["direct", "hash"], default="direct")
+    ap.add_argument("--ks", type=str, default=",".join(str(k) for k in KS))
+    ap.add_argument("--n", type=int, default=N)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-other-engine", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: --gpus %d is not supported "
+              "(pairs shard across GPUs without communication; see the design notes)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_2306_17461_amd as ed
+
+    ks = [int(x) for x in args.ks.split(",")]
+    n = args.n
+    log("generating %d pairs, n=%d" % (len(ks), n))
+    host = []
+    for k in ks:
+        A, B, info = synth.single_pair(n, k, 0)
+        host.append((A, B, info))
+    dev = [(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()) for A, B, _ in host]
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    engines = {"direct": ed.ENGINE_DIRECT, "hash": ed.ENGINE_HASH}
+    ctxs = {name: ed.ed_init(0, engine=e, flags=ed.FLAG_TIMING) for name, e in engines.items()}
+
+    def step(name):
+        out = []
+        for (tA, tB) in dev:
+            out.append(run_pair(ed, ctxs[name], tA, tB, stream))
+        return out
+
+    main_engine = args.engine
+    for w in range(args.warmup):
+        log("warmup", w)
+        step(main_engine)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for s in range(args.steps):
+        results.append(step(main_engine))
+        log("step", s, "done")
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    value = n * len(ks) / dt
+
+    # per-k summary from the last step
+    per_k = {}
+    prep_ns = [0.0] * len(ks)
+    front_ns = [0.0] * len(ks)
+    for r in results:
+        for i, (k, st) in enumerate(r):
+            prep_ns[i] += st["gpu_ns_prepare_kernel"] / len(results)
+            front_ns[i] += st["gpu_ns_frontier_kernel"] / len(results)
+    last = results[-1]
+    for i, (k, st) in enumerate(last):
+        wall = (st["ns_prepare"] + st["ns_distance"]) / 1e6
+        per_k[str(ks[i])] = {
+            "ed": k, "m": int(host[i][2]["m"]), "bits_per_char": st["bits_per_char"],
+            "prepare_kernel_ms": round(prep_ns[i] / 1e6, 4),
+            "frontier_kernel_ms": round(front_ns[i] / 1e6, 4),
+            "host_wall_ms": round(wall, 4),
+            "rounds": st["rounds"], "updates": st["updates"],
+            "us_per_round": round(front_ns[i] / 1e3 / max(1, st["rounds"]), 4),
+            "updates_per_s": st["updates"] / (front_ns[i] / 1e9) if front_ns[i] else None,
+            "lcp_chars": st["lcp_chars"], "wave_lcps": st["wave_lcps"],
+            "chars_per_s": n / (wall / 1e3) if wall else None,
+        }
+
+    # dominant kernel of the step, and its roofline (algorithmic bytes)
+    tot_prep = sum(prep_ns)
+    tot_front = sum(front_ns)
+    bits = last[0][1]["bits_per_char"]
+    if tot_front >= tot_prep:
+        # frontier: compulsory bytes = every character of A and B read once
+        # along the optimal path, (n + m) * bits / 8 per launch
+        byts = sum((n + host[i][2]["m"]) * bits / 8 for i in range(len(ks))) / len(ks)
+        avg_ns = tot_front / len(ks)
+        dom = "frontier_kernel"
+    else:
+        # prepare: n bytes read + packed words (n/4) written per string, plus
+        # the table for the hash engine
+        byts = 0
+        for i in range(len(ks)):
+            for L in (n, host[i][2]["m"]):
+                byts += L + L * bits / 8 + (8 * (L // 32 + 1) if main_engine == "hash" else 0)
+        byts /= len(ks)
+        avg_ns = tot_prep / len(ks)
+        dom = "prepare_kernel"
+    achieved = byts / avg_ns  # bytes/ns = GB/s
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 3), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 6), "traffic": None,
+                "algorithmic_bytes_per_launch": byts, "avg_launch_ms": round(avg_ns / 1e6, 4)}
+
+    other = None
+    if not args.no_other_engine:
+        oname = "hash" if main_engine == "direct" else "direct"
+        step(oname)
+        r = step(oname)
+        other = {"engine": oname, "per_k_ms": {}}
+        for i, (k, st) in enumerate(r):
+            other["per_k_ms"][str(ks[i])] = {
+                "ed": k, "prepare_kernel_ms": round(st["gpu_ns_prepare_kernel"] / 1e6, 4),
+                "frontier_kernel_ms": round(st["gpu_ns_frontier_kernel"] / 1e6, 4),
+                "host_wall_ms": round((st["ns_prepare"] + st["ns_distance"]) / 1e6, 4)}
+            if k != last[i][0]:
+                raise SystemExit("engines disagree at k=%d: %d vs %d" % (ks[i], k, last[i][0]))
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        log("cpu baseline (oracle lv_omp) on the same %d pairs" % len(ks))
+        t1 = time.perf_counter()
+        for i, (A, B, _) in enumerate(host):
+            kc = oracle.lv_omp(A, B)
+            if kc != last[i][0]:
+                raise SystemExit("GPU %d != oracle %d at k=%d" % (last[i][0], kc, ks[i]))
+        tc = time.perf_counter() - t1
+        cpu = {"value": n * len(ks) / tc, "unit": "chars/s", "cores": oracle.omp_max_threads(),
+               "kind": "oracle",
+               "sample": "oracle lv_omp (OpenMP Landau-Vishkin, 8-byte word LCP) on the same %d "
+                         "pairs, once, %.1f s" % (len(ks), tc)}
+
+    for c in ctxs.values():
+        ed.ed_shutdown(c)
+
+    line = {
+        "metric": "chars/sec at n=1e8, k=1e2..1e5 (exact)",
+        "value": value, "unit": "chars/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "single pairs n=1e8, alphabet {0,1,2,3} uniform, B = A + k planted "
+                               "uniform edits, k in %s, seed 0, one launch per pair" % ks,
+                   "engine": main_engine, "bits_per_char": bits},
+        "per_k": per_k,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "other_engine": other,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

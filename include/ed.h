@@ -57,6 +57,7 @@ extern "C" {
 #define ED_FLAG_DEBUG_DUMP 1u  /* keep per-round frontier rows (see ed_distance_dump) */
 #define ED_FLAG_NO_PHASE_A 2u  /* run every round grid-wide (skip the one-workgroup phase) */
 #define ED_FLAG_SHUFFLE 4u     /* batch: permute the work order with hash_seed (race test) */
+#define ED_FLAG_TIMING 8u      /* time the prepare and frontier kernels with HIP events */
 
 typedef struct ed_options {
     uint32_t engine;    /* ED_ENGINE_DIRECT or ED_ENGINE_HASH */
@@ -158,6 +159,9 @@ typedef struct ed_stats {
     double collision_bound;   /* union bound on an undetected collision for the last run */
     uint64_t launches;        /* kernel launches of the last ed_distance */
     double ns_prepare, ns_distance; /* host wall time of the last calls */
+    /* with ED_FLAG_TIMING: HIP-event time of the prepare kernel and of the
+     * frontier kernel launches (summed over relaunches), on the call's stream */
+    double gpu_ns_prepare_kernel, gpu_ns_frontier_kernel;
 } ed_stats;
 
 int ed_pair_stats(const ed_pair *pair, ed_stats *out);

@@ -33,6 +33,7 @@ ENGINE_HASH = 1
 FLAG_DEBUG_DUMP = 1
 FLAG_NO_PHASE_A = 2
 FLAG_SHUFFLE = 4
+FLAG_TIMING = 8
 BUF_PACKED2 = 0
 BUF_BYTES = 1
 BUF_TABLE = 2
@@ -62,7 +63,9 @@ class ed_stats(ctypes.Structure):
                 ("grid_lcps", ctypes.c_uint64), ("hash_queries", ctypes.c_uint64),
                 ("hash_probes", ctypes.c_uint64), ("collisions", ctypes.c_uint64),
                 ("collision_bound", ctypes.c_double), ("launches", ctypes.c_uint64),
-                ("ns_prepare", ctypes.c_double), ("ns_distance", ctypes.c_double)]
+                ("ns_prepare", ctypes.c_double), ("ns_distance", ctypes.c_double),
+                ("gpu_ns_prepare_kernel", ctypes.c_double),
+                ("gpu_ns_frontier_kernel", ctypes.c_double)]
 
 
 class ed_result(ctypes.Structure):

@@ -221,6 +221,11 @@ int ed_init(ed_ctx** out, int device, const ed_options* opt) {
         ed_shutdown(c);
         return ED_ENOMEM;
     }
+    if (hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess) {
+        set_error("ed_init: hipEventCreate failed");
+        ed_shutdown(c);
+        return ED_EDEVICE;
+    }
     int rc = ctx_set_hash(c, o.hash_seed);
     if (rc != ED_OK) {
         ed_shutdown(c);
@@ -260,6 +265,8 @@ int ed_shutdown(ed_ctx* c) {
     if (c->d_cnt) (void)hipFree(c->d_cnt);
     if (c->h_ctl) (void)hipHostFree(c->h_ctl);
     if (c->h_cnt) (void)hipHostFree(c->h_cnt);
+    for (hipEvent_t& e : c->ev)
+        if (e) (void)hipEventDestroy(e);
     delete c;
     return ED_OK;
 }
@@ -275,6 +282,11 @@ static int log2u(uint32_t b) {
 
 void ed::pair_free(ed_pair* p) {
     DevPool& pool = p->ctx->pool;
+    for (hipEvent_t& e : p->ev_prep)
+        if (e) {
+            (void)hipEventDestroy(e);
+            e = nullptr;
+        }
     for (void** q : {&p->w2[0], &p->w2[1], &p->w8[0], &p->w8[1], &p->tab[0], &p->tab[1], &p->misc,
                      &p->stage[0], &p->stage[1], &p->f0, &p->f1}) {
         pool.put(*q);
@@ -399,7 +411,14 @@ int ed::prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B
     int grid = std::min(total, c->num_cu * 4);
     if (grid < 1) grid = 1;
     HIP_TRY(launch_prep_clear(pp, s));
+    if (c->opt.flags & ED_FLAG_TIMING) {
+        HIP_TRY(hipEventCreate(&p->ev_prep[0]));
+        HIP_TRY(hipEventCreate(&p->ev_prep[1]));
+        HIP_TRY(hipEventRecord(p->ev_prep[0], s));
+        p->prep_timed = true;
+    }
     HIP_TRY(launch_prepare(pp, grid, s));
+    if (p->prep_timed) HIP_TRY(hipEventRecord(p->ev_prep[1], s));
     if (c->opt.pack_bits != 2) HIP_TRY(launch_copy8_rest(pp, s));
     p->launches_prepare = c->opt.pack_bits != 2 ? 3 : 2;
     if (c->opt.pack_bits == 2) {
@@ -501,6 +520,7 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
     fp.counters = c->d_cnt;
     int32_t t0 = 0;
     int launches = 0;
+    double gpu_ns = 0;
     CountersDev total;
     std::memset(&total, 0, sizeof total);
     int rc = ED_OK;
@@ -510,8 +530,11 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
         fp.f1 = static_cast<int32_t*>(f1);
         fp.K = static_cast<int32_t>(K);
         fp.t0 = t0;
+        const bool timed = (c->opt.flags & ED_FLAG_TIMING) != 0;
         hipError_t e = launch_ctl_init(c->d_ctl, c->d_cnt, s);
+        if (e == hipSuccess && timed) e = hipEventRecord(c->ev[0], s);
         if (e == hipSuccess) e = launch_frontier(fp, frontier_grid(c), s);
+        if (e == hipSuccess && timed) e = hipEventRecord(c->ev[1], s);
         if (e == hipSuccess) e = hipMemcpyAsync(c->h_ctl, c->d_ctl, sizeof(FrontierCtl), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipMemcpyAsync(c->h_cnt, c->d_cnt, sizeof(CountersDev), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -521,6 +544,10 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
             break;
         }
         ++launches;
+        if (timed) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) gpu_ns += 1e6 * ms;
+        }
         const CountersDev& cd = *c->h_cnt;
         total.updates += cd.updates;
         total.lcp_chars += cd.lcp_chars;
@@ -581,6 +608,7 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
         p->rounds = result;
         p->counters = total;
         p->launches_distance = launches;
+        p->gpu_ns_frontier = gpu_ns;
         if (rows) {
             const uint64_t need = (result + 1) * (result + 1);
             if (need > rows_cap) {
@@ -649,6 +677,13 @@ int ed_pair_stats(const ed_pair* p, ed_stats* o) {
     o->launches = static_cast<uint64_t>(p->launches_distance);
     o->ns_prepare = p->ns_prepare;
     o->ns_distance = p->ns_distance;
+    o->gpu_ns_frontier_kernel = p->gpu_ns_frontier;
+    if (p->prep_timed) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p->ev_prep[1]) == hipSuccess &&
+            hipEventElapsedTime(&ms, p->ev_prep[0], p->ev_prep[1]) == hipSuccess)
+            o->gpu_ns_prepare_kernel = 1e6 * ms;
+    }
     return ED_OK;
 }
 

@@ -48,6 +48,7 @@ struct ed_ctx {
     ed::CountersDev* d_cnt = nullptr;
     ed::FrontierCtl* h_ctl = nullptr;  // pinned
     ed::CountersDev* h_cnt = nullptr;  // pinned
+    hipEvent_t ev[2] = {nullptr, nullptr};  // frontier timing
     ed::DevPool pool;
 };
 
@@ -70,6 +71,9 @@ struct ed_pair {
     int launches_prepare = 0;
     int launches_distance = 0;
     double ns_prepare = 0, ns_distance = 0;
+    hipEvent_t ev_prep[2] = {nullptr, nullptr};  // around the prepare kernel (ED_FLAG_TIMING)
+    bool prep_timed = false;
+    double gpu_ns_frontier = 0;
 };
 
 namespace ed {
