@@ -48,7 +48,7 @@ extern "C" {
 #define ED_EBUSY (-5)      /* serving: host queue full */
 #define ED_EINTERNAL (-6)  /* an internal consistency check failed (a bug) */
 
-#define ED_MAX_LEN ((uint64_t)2147418112u) /* 2^31 - 2^16 characters */
+#define ED_MAX_LEN ((uint64_t)2146435072u) /* 2^31 - 2^20 characters */
 
 /* ---- options ------------------------------------------------------------ */
 #define ED_ENGINE_DIRECT 0u
@@ -70,6 +70,8 @@ typedef struct ed_options {
     uint32_t lane_words;   /* words compared per lane before a wave takes over an LCP */
     uint32_t grid_blocks;  /* workgroups of the persistent kernels */
     uint32_t init_rows;    /* initial frontier capacity in diagonals per side (grown on demand) */
+    uint32_t block_rounds; /* grid-wide phase: rounds per device-wide barrier (temporal blocking) */
+    uint32_t reserved[3];
 } ed_options;
 
 /* Fills *opt with the defaults: direct engine, automatic packing, b = 32,
@@ -162,6 +164,10 @@ typedef struct ed_stats {
     /* with ED_FLAG_TIMING: HIP-event time of the prepare kernel and of the
      * frontier kernel launches (summed over relaunches), on the call's stream */
     double gpu_ns_prepare_kernel, gpu_ns_frontier_kernel;
+    /* device clock split of the last frontier launch: rounds and microseconds
+     * in the one-workgroup phase and in the grid-wide phase */
+    uint64_t rounds_phase_a;
+    double us_phase_a, us_phase_b;
 } ed_stats;
 
 int ed_pair_stats(const ed_pair *pair, ed_stats *out);

@@ -38,7 +38,7 @@ BUF_PACKED2 = 0
 BUF_BYTES = 1
 BUF_TABLE = 2
 NONE = -(1 << 30)
-MAX_LEN = 2147418112
+MAX_LEN = 2146435072
 
 
 class EdError(RuntimeError):
@@ -52,7 +52,8 @@ class ed_options(ctypes.Structure):
                 ("block", ctypes.c_uint32), ("flags", ctypes.c_uint32),
                 ("hash_seed", ctypes.c_uint64), ("lds_rounds", ctypes.c_uint32),
                 ("lane_words", ctypes.c_uint32), ("grid_blocks", ctypes.c_uint32),
-                ("init_rows", ctypes.c_uint32)]
+                ("init_rows", ctypes.c_uint32), ("block_rounds", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 3)]
 
 
 class ed_stats(ctypes.Structure):
@@ -65,7 +66,9 @@ class ed_stats(ctypes.Structure):
                 ("collision_bound", ctypes.c_double), ("launches", ctypes.c_uint64),
                 ("ns_prepare", ctypes.c_double), ("ns_distance", ctypes.c_double),
                 ("gpu_ns_prepare_kernel", ctypes.c_double),
-                ("gpu_ns_frontier_kernel", ctypes.c_double)]
+                ("gpu_ns_frontier_kernel", ctypes.c_double),
+                ("rounds_phase_a", ctypes.c_uint64), ("us_phase_a", ctypes.c_double),
+                ("us_phase_b", ctypes.c_double)]
 
 
 class ed_result(ctypes.Structure):

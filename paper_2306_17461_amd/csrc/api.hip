@@ -148,6 +148,8 @@ static int check_options(const ed_options* o) {
     if (b > 4096 || (b & (b - 1)) != 0) return ED_EINVAL;
     if (o->lds_rounds > static_cast<uint32_t>(kLdsRoundsMax)) return ED_EINVAL;
     if (o->lane_words > 64) return ED_EINVAL;
+    if (o->grid_blocks > static_cast<uint32_t>(kMaxGrid)) return ED_EINVAL;
+    if (o->block_rounds > 4096) return ED_EINVAL;
     return ED_OK;
 }
 
@@ -216,7 +218,8 @@ int ed_init(ed_ctx** out, int device, const ed_options* opt) {
     if (hipMalloc(&c->d_ctl, sizeof(FrontierCtl)) != hipSuccess ||
         hipMalloc(&c->d_cnt, sizeof(CountersDev)) != hipSuccess ||
         hipHostMalloc(&c->h_ctl, sizeof(FrontierCtl)) != hipSuccess ||
-        hipHostMalloc(&c->h_cnt, sizeof(CountersDev)) != hipSuccess) {
+        hipHostMalloc(&c->h_cnt, sizeof(CountersDev)) != hipSuccess ||
+        hipMalloc(&c->d_bar, static_cast<size_t>(kMaxGrid) * kBarStride * 4) != hipSuccess) {
         set_error("ed_init: allocation failed");
         ed_shutdown(c);
         return ED_ENOMEM;
@@ -263,6 +266,7 @@ int ed_shutdown(ed_ctx* c) {
     if (c->d_pow) (void)hipFree(c->d_pow);
     if (c->d_ctl) (void)hipFree(c->d_ctl);
     if (c->d_cnt) (void)hipFree(c->d_cnt);
+    if (c->d_bar) (void)hipFree(c->d_bar);
     if (c->h_ctl) (void)hipHostFree(c->h_ctl);
     if (c->h_cnt) (void)hipHostFree(c->h_cnt);
     for (hipEvent_t& e : c->ev)
@@ -514,13 +518,17 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
     fp.lds_rounds = (c->opt.flags & ED_FLAG_NO_PHASE_A) ? 0 : static_cast<int32_t>(lds_rounds);
     fp.engine = static_cast<int32_t>(p->engine);
     fp.lane_words = static_cast<int32_t>(lane_words);
+    fp.block_rounds = static_cast<int32_t>(c->opt.block_rounds ? c->opt.block_rounds : kDefaultBlockRounds);
     fp.ctl = c->d_ctl;
+    fp.bar = c->d_bar;
     fp.dump = d_dump;
     fp.dump_cap = static_cast<int64_t>(rows_cap);
     fp.counters = c->d_cnt;
     int32_t t0 = 0;
     int launches = 0;
     double gpu_ns = 0;
+    uint64_t rounds_a = 0;
+    double us_a = 0, us_b = 0;
     CountersDev total;
     std::memset(&total, 0, sizeof total);
     int rc = ED_OK;
@@ -531,7 +539,7 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
         fp.K = static_cast<int32_t>(K);
         fp.t0 = t0;
         const bool timed = (c->opt.flags & ED_FLAG_TIMING) != 0;
-        hipError_t e = launch_ctl_init(c->d_ctl, c->d_cnt, s);
+        hipError_t e = launch_ctl_init(c->d_ctl, c->d_cnt, c->d_bar, s);
         if (e == hipSuccess && timed) e = hipEventRecord(c->ev[0], s);
         if (e == hipSuccess) e = launch_frontier(fp, frontier_grid(c), s);
         if (e == hipSuccess && timed) e = hipEventRecord(c->ev[1], s);
@@ -558,6 +566,11 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
         total.hash_eq_len += cd.hash_eq_len;
         total.collisions += cd.collisions;
         const FrontierCtl& st = *c->h_ctl;
+        if (launches == 1) {
+            rounds_a = static_cast<uint64_t>(st.phase_t);
+            us_a = (st.clk_switch - st.clk_begin) / 100.0;  // s_memrealtime: 100 MHz
+        }
+        if (st.clk_end >= st.clk_switch) us_b += (st.clk_end - st.clk_switch) / 100.0;
         if (st.status == 1 || st.status == 2) {
             result = static_cast<uint64_t>(st.result_t);
             break;
@@ -609,6 +622,9 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
         p->counters = total;
         p->launches_distance = launches;
         p->gpu_ns_frontier = gpu_ns;
+        p->rounds_phase_a = rounds_a;
+        p->us_phase_a = us_a;
+        p->us_phase_b = us_b;
         if (rows) {
             const uint64_t need = (result + 1) * (result + 1);
             if (need > rows_cap) {
@@ -678,6 +694,9 @@ int ed_pair_stats(const ed_pair* p, ed_stats* o) {
     o->ns_prepare = p->ns_prepare;
     o->ns_distance = p->ns_distance;
     o->gpu_ns_frontier_kernel = p->gpu_ns_frontier;
+    o->rounds_phase_a = p->rounds_phase_a;
+    o->us_phase_a = p->us_phase_a;
+    o->us_phase_b = p->us_phase_b;
     if (p->prep_timed) {
         float ms = 0.f;
         if (hipEventSynchronize(p->ev_prep[1]) == hipSuccess &&
@@ -725,7 +744,7 @@ int ed_pair_buffer(ed_ctx* c, const ed_pair* p, int which, int kind, void* out, 
 int ed_debug_lcp(ed_ctx* c, ed_pair* p, int engine, const int64_t* x, const int64_t* y,
                  uint64_t count, int64_t* out, void* hip_stream) {
     if (!c || !p || (count && (!x || !y || !out))) return ED_EINVAL;
-    if (engine < -1 || engine > 1) return ED_EINVAL;
+    if (engine < -1 || engine > 2) return ED_EINVAL;
     std::lock_guard<std::mutex> lk(c->mu);
     HIP_TRY(hipSetDevice(c->device));
     const int eng = engine < 0 ? static_cast<int>(p->engine) : engine;
@@ -764,7 +783,7 @@ int ed_debug_lcp(ed_ctx* c, ed_pair* p, int engine, const int64_t* x, const int6
     q.counters = c->d_cnt;
     hipError_t e = hipMemcpyAsync(dx, x, count * 8, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(dy, y, count * 8, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_ctl_init(c->d_ctl, c->d_cnt, s);
+    if (e == hipSuccess) e = launch_ctl_init(c->d_ctl, c->d_cnt, nullptr, s);
     if (e == hipSuccess) e = launch_lcp_queries(q, s);
     if (e == hipSuccess) e = hipMemcpyAsync(out, dout, count * 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(c->h_cnt, c->d_cnt, sizeof(CountersDev), hipMemcpyDeviceToHost, s);

@@ -125,7 +125,7 @@ int batch_locked(ed_ctx* c, ed_pair* const* pairs, uint64_t count, int64_t k_max
     hipError_t e = hipMemcpyAsync(d_items, items.data(), items_bytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(d_order, order.data(), order_bytes, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_fill_u32(d_ticket, 1, 0u, s);
-    if (e == hipSuccess) e = launch_ctl_init(c->d_ctl, c->d_cnt, s);
+    if (e == hipSuccess) e = launch_ctl_init(c->d_ctl, c->d_cnt, nullptr, s);
     if (e == hipSuccess) e = launch_batch(bp, grid, s);
     if (e == hipSuccess) e = hipMemcpyAsync(kres.data(), d_kout, kout_bytes, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -193,7 +193,7 @@ __device__ __forceinline__ uint64_t get_hash(const SView& S, const uint64_t* T, 
 // direct step finds the mismatch character, which confirms the answer.  When
 // the direct step finds no mismatch below hi, a hash collision made some
 // "equal" verdict wrong: the LCP is recomputed directly (counted).
-__device__ int32_t lcp_wave_hash(const SView& A, const SView& B, const uint64_t* TA,
+__device__ __forceinline__ int32_t lcp_wave_hash(const SView& A, const SView& B, const uint64_t* TA,
                                  const uint64_t* TB, const HashQ& q, int32_t x, int32_t y,
                                  int32_t lim, int32_t l0, CountersDev& cnt) {
     const int lane = lane_id();

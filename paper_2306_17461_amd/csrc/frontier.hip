@@ -12,81 +12,281 @@
 // The search stops at the first t with f_t[n-m] = n; that t is the distance.
 //
 // Kernels:
-//   frontier_kernel  one pair, all rounds in one persistent launch: workgroup
-//                    0 runs the first rounds alone with both rows in LDS
-//                    (barriers are s_barrier only); when the rows outgrow LDS
-//                    the frontier moves to global memory and every workgroup
-//                    takes a slice of the diagonals, with a device-wide
-//                    barrier between rounds.
+//   frontier_kernel  one pair, all rounds in one persistent launch.
+//                    Phase A: workgroup 0 runs the first rounds alone with
+//                    both rows in LDS (workgroup barriers only).
+//                    Phase B: every workgroup owns a slice of the diagonals;
+//                    it loads its slice plus a halo of H diagonals per side,
+//                    advances H rounds in LDS (the halo shrinks by one
+//                    diagonal per round, so every value it computes is
+//                    exact), writes its slice back, and meets the others at a
+//                    device-wide barrier: one barrier per H rounds.
 //   batch_kernel     many pairs in one persistent launch: workgroups take
 //                    pairs from a device queue (largest first) and run all
 //                    rounds of a pair with workgroup barriers only.
 //   lcp_query_kernel one LCP query per wavefront (tests of the engines).
+//
+// Inside a round every thread takes up to kU diagonals and issues the first
+// word loads of all of them before comparing (one memory latency per pass).
+// LCPs that run past the lane tier go to a job list in LDS: the direct engine
+// extends each job with the whole workgroup (4 words per thread per step),
+// the hash engine gives each job to one wavefront.
+#include <climits>
+
 #include "device.h"
 
 namespace ed {
 
 namespace {
 
+constexpr int kU = 4;          // diagonals per thread per pass
+constexpr int kJobHalf = 128;  // jobs per pass (a ring of two halves)
+
+struct RoundShared {
+    int32_t jx[2 * kJobHalf];
+    int32_t jy[2 * kJobHalf];
+    int32_t jlim[2 * kJobHalf];
+    int32_t jl[2 * kJobHalf];
+    int32_t jres[2 * kJobHalf];
+    int32_t jcount[2];  // monotonic job counters, one per pass parity
+    int32_t wmin;       // workgroup-tier reduction slot
+    int32_t flag;
+    int32_t pair;
+    int32_t pad_;
+};
+
+struct LdsState {
+    int32_t row[2][kLdsRowLen];
+    uint64_t lut4[256];
+    RoundShared rs;
+};
+
+// Per-workgroup cursor into the job counters (uniform, kept in registers).
+struct JobCursor {
+    int32_t start[2];
+};
+
 __device__ __forceinline__ int32_t imax(int32_t a, int32_t b) { return a > b ? a : b; }
 __device__ __forceinline__ int32_t imin(int32_t a, int32_t b) { return a < b ? a : b; }
 
-// One round over entries [e_begin, e_end) of the 2t+5 row entries (entry e
-// is diagonal e - (t+2)).  `prev` and `cur` point at diagonal 0 of their
-// rows.  The loop trip count is uniform over the calling threads, so every
-// wavefront reaches the wave-level LCP code with all 64 lanes.  Returns true
-// in the thread that found f_t[target] = n.
+__device__ __forceinline__ void rs_init(RoundShared& RS, JobCursor& jc) {
+    if (threadIdx.x == 0) {
+        RS.jcount[0] = 0;
+        RS.jcount[1] = 0;
+        RS.flag = 0;
+    }
+    jc.start[0] = 0;
+    jc.start[1] = 0;
+}
+
+// Engine (a), workgroup tier: every thread of the workgroup compares 4 words
+// per step (131072 characters per step at 2 bits, 32768 at 8 bits); the first
+// mismatch is the minimum over wavefronts.  Uniform arguments; returns LCP.
+__device__ __forceinline__ int32_t lcp_wg_direct(const SView& A, const SView& B, int32_t x, int32_t y,
+                                                 int32_t lim, int32_t l, int32_t& wmin) {
+    constexpr int W = 4;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int32_t cpw = 1 << A.lcpw;
+    while (l < lim) {
+        if (tid == 0) wmin = INT_MAX;
+        __syncthreads();
+        uint64_t d[W];
+        int32_t p[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            p[w] = l + (w * nthr + tid) * cpw;
+            const bool ok = p[w] < lim;
+            const int32_t q = ok ? p[w] : 0;
+            const uint64_t v = fetch(A, x + q) ^ fetch(B, y + q);
+            d[w] = ok ? v : 0;
+        }
+        int32_t best = INT_MAX;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const uint64_t b = ballot(d[w] != 0);
+            if (b && best == INT_MAX) {
+                const int s = ctz64(b);
+                best = shfl_i32(p[w], s) + ctz64(shfl_u64(d[w], s)) / A.bpc;
+            }
+        }
+        if (lane_id() == 0 && best != INT_MAX) atomicMin(&wmin, best);
+        __syncthreads();
+        const int32_t mres = wmin;
+        __syncthreads();
+        if (mres != INT_MAX) return mres < lim ? mres : lim;
+        l += W * nthr * cpw;
+    }
+    return lim;
+}
+
+// One round over diagonals [i_begin, i_end) (any i outside [max(-t,-m),
+// min(t,n)] is written as kNone).  Diagonal i of a row lives at
+// row[i + ofs]; every index formed here is inside the row, so no pointer
+// ever points before an array (rows in LDS stay LDS addresses).  Called by
+// every thread of the workgroup.  Diagonals in [dlo, dhi] are also copied to
+// dump_row[i + t].  Returns true in the thread that found f_t[n-m] = n.
 template <typename PrevPtr, typename CurPtr>
-__device__ __forceinline__ bool do_round(const Engine& en, int32_t t, PrevPtr prev, CurPtr cur,
-                                         int32_t e_begin, int32_t e_end, int tid, int nthr,
-                                         int32_t* dump_row, CountersDev& cnt) {
+__device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr prev, CurPtr cur,
+                                            int32_t ofs, int32_t i_begin, int32_t i_end, RoundShared& RS,
+                                            JobCursor& jc, int32_t* dump_row, int32_t dlo, int32_t dhi,
+                                            CountersDev& cnt) {
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
     const int32_t n = en.A.len, m = en.B.len;
     const int32_t lo = imax(-t, -m), hi = imin(t, n);
     const int32_t target = n - m;
+    const int32_t cpw = 1 << en.A.lcpw;
     bool found = false;
-    for (int32_t base = e_begin; base < e_end; base += nthr) {
-        const int32_t e = base + tid;
-        const bool active = e < e_end;
-        const int32_t i = e - (t + 2);
-        const bool inr = active && i >= lo && i <= hi;
-        int32_t c = -1;
-        if (inr) {
-            if (t == 0) {
-                c = 0;
-            } else {
-                const int32_t a = prev[i], b = prev[i - 1], d = prev[i + 1];
-                c = imax(imax(a + 1, b + 1), d);  // kNone + 1 stays negative
-                if (c >= 0) c = imin(imin(c, n), m + i);
+    int par = 0;
+    for (int32_t base = i_begin; base < i_end; base += nthr * kU) {
+        int32_t iv[kU], c[kU], l[kU], lim[kU], slot[kU];
+        bool val[kU], act[kU], pend[kU];
+        uint64_t d[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int32_t i = base + u * nthr + tid;
+            iv[u] = i;
+            act[u] = i < i_end;
+            const bool inr = act[u] && i >= lo && i <= hi;
+            int32_t cc = -1;
+            if (inr) {
+                if (t == 0) {
+                    cc = 0;
+                } else {
+                    const int32_t a = prev[i + ofs], b = prev[i + ofs - 1], e = prev[i + ofs + 1];
+                    cc = imax(imax(a + 1, b + 1), e);  // kNone + 1 stays negative
+                    if (cc >= 0) cc = imin(imin(cc, n), m + i);
+                }
+            }
+            c[u] = cc;
+            val[u] = inr && cc >= 0;
+            lim[u] = val[u] ? imin(n - cc, m - (cc - i)) : 0;
+        }
+        // first word of every diagonal: all loads in flight together
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int32_t xs = lim[u] > 0 ? c[u] : 0;
+            const int32_t ys = lim[u] > 0 ? c[u] - iv[u] : 0;
+            d[u] = fetch(en.A, xs) ^ fetch(en.B, ys);
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            l[u] = 0;
+            pend[u] = false;
+            if (lim[u] > 0) {
+                if (d[u]) {
+                    l[u] = imin(ctz64(d[u]) / en.A.bpc, lim[u]);
+                } else if (lim[u] <= cpw) {
+                    l[u] = lim[u];
+                } else {
+                    l[u] = cpw;
+                    pend[u] = true;
+                }
             }
         }
-        const bool valid = inr && c >= 0;
-        const int32_t l = slide(en, valid, c, c - i, cnt);
-        const int32_t f = valid ? c + l : kNone;
-        if (active) {
-            cur[i] = f;
-            if (dump_row && i >= -t && i <= t) dump_row[i + t] = f;
+        if (en.lane_words > 1) {
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                if (pend[u]) {
+                    bool more = false;
+                    const int32_t l2 = lcp_lane(en.A, en.B, c[u] + cpw, c[u] - iv[u] + cpw, lim[u] - cpw,
+                                                en.lane_words - 1, &more);
+                    l[u] = cpw + l2;
+                    pend[u] = more;
+                }
+            }
         }
-        if (valid) {
-            cnt.updates++;
-            if (i == target && f == n) found = true;
+        // long LCPs: job list for this pass
+        const int half = par * kJobHalf;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            slot[u] = -1;
+            if (pend[u]) {
+                const int32_t s = atomicAdd(&RS.jcount[par], 1) - jc.start[par];
+                if (s < kJobHalf) {
+                    slot[u] = half + s;
+                    RS.jx[half + s] = c[u];
+                    RS.jy[half + s] = c[u] - iv[u];
+                    RS.jlim[half + s] = lim[u];
+                    RS.jl[half + s] = l[u];
+                }
+            }
         }
+        __syncthreads();
+        const int32_t jend = RS.jcount[par];
+        const int32_t nj = imin(jend - jc.start[par], kJobHalf);
+        jc.start[par] = jend;
+        if (nj > 0) {
+            if (en.kind == 0) {
+                for (int j = 0; j < nj; ++j) {
+                    const int32_t r = lcp_wg_direct(en.A, en.B, RS.jx[half + j], RS.jy[half + j],
+                                                    RS.jlim[half + j], RS.jl[half + j], RS.wmin);
+                    if (tid == 0) RS.jres[half + j] = r;
+                }
+            } else {
+                for (int j = wave; j < nj; j += nwaves) {
+                    const int32_t jx = RS.jx[half + j], jy = RS.jy[half + j];
+                    const int32_t jlim = RS.jlim[half + j], jl = RS.jl[half + j];
+                    const int32_t r = jl > 0 ? lcp_wave_hash(en.A, en.B, en.TA, en.TB, en.q, jx, jy, jlim, jl, cnt)
+                                             : lcp_wave_direct(en.A, en.B, jx, jy, jlim, jl);
+                    if (lane == 0) RS.jres[half + j] = r;
+                }
+            }
+            if (tid == 0) cnt.wave_lcps += static_cast<unsigned long long>(nj);
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+                if (slot[u] >= 0) l[u] = RS.jres[slot[u]];
+        }
+        // job list overflow: the lane's own wavefront extends it
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            uint64_t pm = ballot(pend[u] && slot[u] < 0);
+            while (pm) {
+                const int src = ctz64(pm);
+                pm &= pm - 1;
+                const int32_t jx = shfl_i32(c[u], src), jy = shfl_i32(c[u] - iv[u], src);
+                const int32_t jlim = shfl_i32(lim[u], src), jl = shfl_i32(l[u], src);
+                const int32_t r = (en.kind == 1 && jl > 0)
+                                      ? lcp_wave_hash(en.A, en.B, en.TA, en.TB, en.q, jx, jy, jlim, jl, cnt)
+                                      : lcp_wave_direct(en.A, en.B, jx, jy, jlim, jl);
+                if (lane == src) l[u] = r;
+                if (lane == 0) cnt.wave_lcps++;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int32_t f = val[u] ? c[u] + l[u] : kNone;
+            if (act[u]) {
+                cur[iv[u] + ofs] = f;
+                if (dump_row && iv[u] >= dlo && iv[u] <= dhi) dump_row[iv[u] + t] = f;
+            }
+            if (val[u]) {
+                cnt.updates++;
+                cnt.lcp_chars += static_cast<unsigned long long>(l[u]);
+                if (iv[u] == target && f == n) found = true;
+            }
+        }
+        par ^= 1;
     }
     return found;
 }
 
-__device__ __forceinline__ void grid_barrier(FrontierCtl* ctl) {
+// Device-wide barrier: workgroup g > 0 raises its flag to `epoch`; workgroup 0
+// waits for every flag, then publishes `epoch` in ctl->release.
+__device__ __forceinline__ void grid_sync(FrontierCtl* ctl, unsigned int* bar, unsigned int epoch) {
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned int g = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned int arrived =
-            __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == gridDim.x - 1) {
-            __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctl->bar_gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g)
+    if (blockIdx.x == 0) {
+        for (int g = threadIdx.x + 1; g < static_cast<int>(gridDim.x); g += blockDim.x)
+            while (__hip_atomic_load(bar + g * kBarStride, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < epoch)
                 __builtin_amdgcn_s_sleep(1);
-        }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&ctl->release, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else if (threadIdx.x == 0) {
+        __hip_atomic_store(bar + blockIdx.x * kBarStride, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        while (__hip_atomic_load(&ctl->release, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < epoch)
+            __builtin_amdgcn_s_sleep(1);
     }
     __syncthreads();
 }
@@ -107,55 +307,52 @@ __device__ __forceinline__ Engine make_engine(const PairDev& p, const HashDev& h
     return en;
 }
 
-struct LdsState {
-    int32_t row[2][kLdsRowLen];
-    uint64_t lut4[256];
-    int32_t flag;
-    int32_t pair;
-};
+__device__ __forceinline__ int32_t* dump_row_for(int32_t* dump, int64_t cap, int32_t t) {
+    return (dump && static_cast<int64_t>(t + 1) * (t + 1) <= cap) ? dump + static_cast<int64_t>(t) * t : nullptr;
+}
 
-// Rounds of one pair inside one workgroup, starting from round 0, first in
-// LDS (up to lds_rounds rounds), then in the global rows g0/g1 (capacity K).
+// Rounds of one pair inside one workgroup, from round 0: first in LDS (up to
+// lds_rounds rounds), then in the global rows g0/g1 (capacity K).
 // Returns k, kmax + 1, or -3 when the rows are too small.
-__device__ int32_t pair_in_workgroup(const Engine& en, LdsState& L, int32_t lds_rounds, int32_t kmax,
-                                     int32_t* g0, int32_t* g1, int32_t K, CountersDev& cnt) {
+__device__ __forceinline__ int32_t pair_in_workgroup(const Engine& en, LdsState& L, JobCursor& jc, int32_t lds_rounds,
+                                     int32_t kmax, int32_t* g0, int32_t* g1, int32_t K, CountersDev& cnt) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int32_t n = en.A.len, m = en.B.len;
     const int32_t maxnm = imax(n, m);
-    const int32_t off = kLdsRoundsMax + 2;
-    int32_t* la = L.row[0] + off;
-    int32_t* lb = L.row[1] + off;
-    if (tid == 0) L.flag = 0;
+    const int32_t off = kLdsRoundsMax + 2;  // diagonal i at row[i + off]
+    int32_t* la = L.row[0];
+    int32_t* lb = L.row[1];
+    RoundShared& RS = L.rs;
+    if (tid == 0) RS.flag = 0;
     __syncthreads();
     int32_t t = 0;
-    if (do_round(en, 0, la, la, 0, 5, tid, nthr, nullptr, cnt)) L.flag = 1;
+    if (round_range(en, 0, la, la, off, -2, 3, RS, jc, nullptr, 0, -1, cnt)) RS.flag = 1;
     __syncthreads();
     const int32_t lr = imin(lds_rounds, kLdsRoundsMax);
-    // LDS phase
     for (;;) {
-        if (L.flag) return t;
+        if (RS.flag) return t;
         if (kmax >= 0 && t >= kmax) return kmax + 1;
         if (t > maxnm) return -3;
         if (t >= lr) break;
         ++t;
-        if (do_round(en, t, la, lb, 0, 2 * t + 5, tid, nthr, nullptr, cnt)) L.flag = 1;
+        if (round_range(en, t, la, lb, off, -(t + 2), t + 3, RS, jc, nullptr, 0, -1, cnt)) RS.flag = 1;
         int32_t* tmp = la;
         la = lb;
         lb = tmp;
         __syncthreads();
     }
-    // global phase: copy the last LDS row out
-    if (t + 2 > K + 2 || g0 == nullptr) return -3;
-    int32_t* ga = g0 + K + 2;
-    int32_t* gb = g1 + K + 2;
-    for (int32_t e = tid; e < 2 * t + 5; e += nthr) ga[e - (t + 2)] = la[e - (t + 2)];
+    if (t > K || g0 == nullptr) return -3;
+    // global rows: diagonal i at g[i + K + 2]
+    int32_t* ga = g0;
+    int32_t* gb = g1;
+    for (int32_t e = tid; e < 2 * t + 5; e += nthr) ga[K + 2 + e - (t + 2)] = la[off + e - (t + 2)];
     __syncthreads();
     for (;;) {
-        if (L.flag) return t;
+        if (RS.flag) return t;
         if (kmax >= 0 && t >= kmax) return kmax + 1;
         if (t > maxnm || t >= K) return -3;
         ++t;
-        if (do_round(en, t, ga, gb, 0, 2 * t + 5, tid, nthr, nullptr, cnt)) L.flag = 1;
+        if (round_range(en, t, ga, gb, K + 2, -(t + 2), t + 3, RS, jc, nullptr, 0, -1, cnt)) RS.flag = 1;
         int32_t* tmp = ga;
         ga = gb;
         gb = tmp;
@@ -163,138 +360,185 @@ __device__ int32_t pair_in_workgroup(const Engine& en, LdsState& L, int32_t lds_
     }
 }
 
+__device__ __forceinline__ uint64_t clock_now() { return __builtin_amdgcn_s_memrealtime(); }
+
 }  // namespace
 
-__global__ void ctl_init_kernel(FrontierCtl* ctl, CountersDev* cnt) {
-    if (threadIdx.x == 0) {
-        ctl->bar_count = 0;
-        ctl->bar_gen = 0;
+__global__ void ctl_init_kernel(FrontierCtl* ctl, CountersDev* cnt, unsigned int* bar) {
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        ctl->release = 0;
         ctl->phase = 0;
         ctl->phase_t = 0;
-        ctl->found_t = -1;
+        ctl->found_t = INT_MAX;
         ctl->status = 0;
         ctl->result_t = 0;
         ctl->wbuf = 0;
+        ctl->clk_begin = 0;
+        ctl->clk_switch = 0;
+        ctl->clk_end = 0;
     }
-    if (cnt && threadIdx.x < sizeof(CountersDev) / 8)
-        reinterpret_cast<unsigned long long*>(cnt)[threadIdx.x] = 0;
+    if (cnt && tid < static_cast<int>(sizeof(CountersDev) / 8))
+        reinterpret_cast<unsigned long long*>(cnt)[tid] = 0;
+    if (bar)
+        for (int g = tid; g < kMaxGrid; g += blockDim.x) bar[g * kBarStride] = 0;
 }
 
 __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierParams P) {
     __shared__ LdsState L;
     const int tid = threadIdx.x, nthr = blockDim.x;
+    const int G = gridDim.x;
     CountersDev cnt = {};
+    JobCursor jc;
+    rs_init(L.rs, jc);
     if (P.engine == 1) build_lut4(L.lut4, P.h.r, tid, nthr);
     __syncthreads();
     const Engine en = make_engine(P.p, P.h, P.engine, P.lane_words, L.lut4);
+    RoundShared& RS = L.rs;
     const int32_t n = en.A.len, m = en.B.len;
     const int32_t maxnm = imax(n, m);
     FrontierCtl* ctl = P.ctl;
     const int32_t K = P.K;
     int32_t t = P.t0;
-    int32_t* gp = P.f0 + K + 2;  // holds f_t
-    int32_t* gc = P.f1 + K + 2;
+    const int32_t gofs = K + 2;  // diagonal i of a global row at row[i + gofs]
+    int32_t* gp = P.f0;          // holds f_t
+    int32_t* gc = P.f1;
     bool finished = false;
+    unsigned int epoch = 0;
+    if (blockIdx.x == 0 && tid == 0) ctl->clk_begin = clock_now();
 
     if (P.t0 == 0) {
-        if (P.lds_rounds > 0) {
-            // ---------------- phase A: workgroup 0, rows in LDS ----------------
-            if (blockIdx.x == 0) {
-                const int32_t off = kLdsRoundsMax + 2;
-                int32_t* la = L.row[0] + off;
-                int32_t* lb = L.row[1] + off;
-                if (tid == 0) L.flag = 0;
+        // ---------------- phase A: workgroup 0, rows in LDS ----------------
+        if (blockIdx.x == 0) {
+            const int32_t off = kLdsRoundsMax + 2;  // diagonal i at row[i + off]
+            int32_t* la = L.row[0];
+            int32_t* lb = L.row[1];
+            if (round_range(en, 0, la, la, off, -2, 3, RS, jc, P.dump && P.dump_cap >= 1 ? P.dump : nullptr, 0, 0, cnt))
+                RS.flag = 1;
+            __syncthreads();
+            const int32_t lr = imin(imin(P.lds_rounds, kLdsRoundsMax), K);
+            int32_t status = 0, result = 0;
+            for (;;) {
+                if (RS.flag) { status = 1; result = t; break; }
+                if (P.kmax >= 0 && t >= P.kmax) { status = 2; result = P.kmax + 1; break; }
+                if (t > maxnm) { status = 4; result = t; break; }
+                if (t >= lr) break;
+                ++t;
+                if (round_range(en, t, la, lb, off, -(t + 2), t + 3, RS, jc, dump_row_for(P.dump, P.dump_cap, t), -t, t, cnt))
+                    RS.flag = 1;
+                int32_t* tmp = la;
+                la = lb;
+                lb = tmp;
                 __syncthreads();
-                if (do_round(en, 0, la, la, 0, 5, tid, nthr, P.dump, cnt)) L.flag = 1;
-                __syncthreads();
-                const int32_t lr = imin(imin(P.lds_rounds, kLdsRoundsMax), K);
-                int32_t status = 0, result = 0;
-                for (;;) {
-                    if (L.flag) { status = 1; result = t; break; }
-                    if (P.kmax >= 0 && t >= P.kmax) { status = 2; result = P.kmax + 1; break; }
-                    if (t > maxnm) { status = 4; result = t; break; }
-                    if (t >= lr) break;
-                    ++t;
-                    int32_t* drow = (P.dump && static_cast<int64_t>(t + 1) * (t + 1) <= P.dump_cap)
-                                        ? P.dump + static_cast<int64_t>(t) * t : nullptr;
-                    if (do_round(en, t, la, lb, 0, 2 * t + 5, tid, nthr, drow, cnt)) L.flag = 1;
-                    int32_t* tmp = la;
-                    la = lb;
-                    lb = tmp;
-                    __syncthreads();
-                }
-                if (status == 0) {
-                    for (int32_t e = tid; e < 2 * t + 5; e += nthr) gp[e - (t + 2)] = la[e - (t + 2)];
-                }
-                __syncthreads();
-                if (tid == 0) {
-                    if (status != 0) {
-                        ctl->result_t = result;
-                        __hip_atomic_store(&ctl->status, status, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                    } else {
-                        ctl->phase_t = t;
-                    }
-                    __hip_atomic_store(&ctl->phase, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                }
-                finished = status != 0;
-            } else {
-                if (tid == 0) {
-                    while (__hip_atomic_load(&ctl->phase, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0)
-                        __builtin_amdgcn_s_sleep(8);
-                    L.flag = __hip_atomic_load(&ctl->status, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                }
-                __syncthreads();
-                finished = L.flag != 0;
-                // workgroup 0 wrote phase_t before its release of `phase`
-                if (!finished) t = __hip_atomic_load(&ctl->phase_t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
+            if (status == 0)
+                for (int32_t e = tid; e < 2 * t + 5; e += nthr) gp[gofs + e - (t + 2)] = la[off + e - (t + 2)];
+            __syncthreads();
+            if (tid == 0) {
+                ctl->clk_switch = clock_now();
+                if (status != 0) {
+                    ctl->result_t = result;
+                    ctl->phase_t = t;
+                    __hip_atomic_store(&ctl->status, status, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                } else {
+                    ctl->phase_t = t;
+                }
+                __hip_atomic_store(&ctl->phase, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            finished = status != 0;
         } else {
-            // round 0 grid-wide (only workgroup 0 holds the entries)
-            int32_t* drow = P.dump && P.dump_cap >= 1 ? P.dump : nullptr;
-            if (blockIdx.x == 0) {
-                if (do_round(en, 0, gp, gp, 0, 5, tid, nthr, drow, cnt))
-                    __hip_atomic_store(&ctl->found_t, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (tid == 0) {
+                while (__hip_atomic_load(&ctl->phase, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0)
+                    __builtin_amdgcn_s_sleep(64);
+                RS.flag = __hip_atomic_load(&ctl->status, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
             }
-            grid_barrier(ctl);
+            __syncthreads();
+            finished = RS.flag != 0;
+            if (!finished) t = __hip_atomic_load(&ctl->phase_t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+    } else if (blockIdx.x == 0 && tid == 0) {
+        ctl->clk_switch = ctl->clk_begin;
+        ctl->phase_t = t;
     }
 
-    // ---------------- phase B: all workgroups, rows in global memory ----------------
+    // ---------------- phase B: every workgroup, H rounds per barrier ----------------
     if (!finished) {
-        const int G = gridDim.x;
         for (;;) {
-            // found_t is written during a round and read after that round's
-            // barrier; a value above t was written by a workgroup already in
-            // round t+1 and is acted on after the next barrier
+            // found_t only holds rounds of finished blocks once everyone passed the barrier
             const int32_t ft = __hip_atomic_load(&ctl->found_t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             int32_t status = 0, result = 0;
-            if (ft >= 0 && ft <= t) { status = 1; result = ft; }
+            if (ft <= t) { status = 1; result = ft; }
             else if (P.kmax >= 0 && t >= P.kmax) { status = 2; result = P.kmax + 1; }
             else if (t > maxnm) { status = 4; result = t; }
             else if (t >= K) { status = 3; result = t; }
             if (status != 0) {
                 if (blockIdx.x == 0 && tid == 0) {
                     ctl->result_t = result;
-                    ctl->wbuf = gp == P.f0 + K + 2 ? 0 : 1;
+                    ctl->wbuf = gp == P.f0 ? 0 : 1;
                     __hip_atomic_store(&ctl->status, status, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                 }
                 break;
             }
-            ++t;
-            const int32_t total = 2 * t + 5;
+            int32_t H = imin(imax(P.block_rounds, 1), K - t);
+            if (P.kmax >= 0) H = imin(H, P.kmax - t);
+            const int32_t T = t + H;
+            const int32_t total = 2 * T + 5;
             const int32_t chunk = (total + G - 1) / G;
             const int32_t eb = imin(total, static_cast<int32_t>(blockIdx.x) * chunk);
             const int32_t ee = imin(total, eb + chunk);
-            int32_t* drow = (P.dump && static_cast<int64_t>(t + 1) * (t + 1) <= P.dump_cap)
-                                ? P.dump + static_cast<int64_t>(t) * t : nullptr;
-            if (do_round(en, t, gp, gc, eb, ee, tid, nthr, drow, cnt))
-                __hip_atomic_store(&ctl->found_t, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            grid_barrier(ctl);
+            const int32_t a = eb - (T + 2), b = ee - 1 - (T + 2);  // owned diagonals
+            const bool in_lds = chunk + 2 * H <= kLdsRowLen;
+            if (!in_lds) {
+                // slices too wide for LDS: one round per barrier on the global rows
+                const int32_t t1 = t + 1;
+                const int32_t total1 = 2 * t1 + 5;
+                const int32_t c1 = (total1 + G - 1) / G;
+                const int32_t e0 = imin(total1, static_cast<int32_t>(blockIdx.x) * c1);
+                const int32_t e1 = imin(total1, e0 + c1);
+                if (e0 < e1 &&
+                    round_range(en, t1, gp, gc, gofs, e0 - (t1 + 2), e1 - (t1 + 2), RS, jc,
+                                dump_row_for(P.dump, P.dump_cap, t1), -t1, t1, cnt))
+                    atomicMin(&ctl->found_t, t1);
+                grid_sync(ctl, P.bar, ++epoch);
+                int32_t* tmp = gp;
+                gp = gc;
+                gc = tmp;
+                t = t1;
+                continue;
+            }
+            if (eb < ee) {
+                // window [a - H, b + H] in LDS: diagonal i at row[i + wofs],
+                // wofs = H - a, so every index used is in [0, W)
+                const int32_t W = (b - a + 1) + 2 * H;
+                const int32_t wofs = H - a;
+                int32_t* r0 = L.row[0];
+                for (int32_t li = tid; li < W; li += nthr) {
+                    const int32_t i = a - H + li;
+                    r0[li] = (i >= -(t + 2) && i <= t + 2) ? gp[i + gofs] : kNone;
+                }
+                __syncthreads();
+                int32_t* rp = L.row[0];
+                int32_t* rc = L.row[1];
+                for (int32_t s = 1; s <= H; ++s) {
+                    const int32_t tt = t + s;
+                    if (round_range(en, tt, rp, rc, wofs, a - (H - s), b + (H - s) + 1, RS, jc,
+                                    dump_row_for(P.dump, P.dump_cap, tt), imax(a, -tt), imin(b, tt), cnt))
+                        atomicMin(&ctl->found_t, tt);
+                    int32_t* tmp = rp;
+                    rp = rc;
+                    rc = tmp;
+                    __syncthreads();
+                }
+                for (int32_t i = a + tid; i <= b; i += nthr) gc[i + gofs] = rp[i + wofs];
+            }
+            grid_sync(ctl, P.bar, ++epoch);
             int32_t* tmp = gp;
             gp = gc;
             gc = tmp;
+            t = T;
         }
     }
+    if (blockIdx.x == 0 && tid == 0) ctl->clk_end = clock_now();
     flush_counters(cnt, P.counters);
 }
 
@@ -302,17 +546,19 @@ __global__ __launch_bounds__(kFrontierThreads) void batch_kernel(BatchParams P) 
     __shared__ LdsState L;
     const int tid = threadIdx.x;
     CountersDev cnt = {};
+    JobCursor jc;
+    rs_init(L.rs, jc);
     if (P.engine == 1) build_lut4(L.lut4, P.h.r, tid, blockDim.x);
     for (;;) {
         __syncthreads();
-        if (tid == 0) L.pair = static_cast<int32_t>(atomicAdd(P.ticket, 1u));
+        if (tid == 0) L.rs.pair = static_cast<int32_t>(atomicAdd(P.ticket, 1u));
         __syncthreads();
-        const int32_t idx = L.pair;
+        const int32_t idx = L.rs.pair;
         if (idx >= P.count) break;
         const int32_t pi = P.order[idx];
         const BatchItem item = P.items[pi];
         const Engine en = make_engine(item.p, P.h, P.engine, P.lane_words, L.lut4);
-        const int32_t k = pair_in_workgroup(en, L, P.lds_rounds, P.kmax, item.f0, item.f1, item.K, cnt);
+        const int32_t k = pair_in_workgroup(en, L, jc, P.lds_rounds, P.kmax, item.f0, item.f1, item.K, cnt);
         if (tid == 0) P.k_out[pi] = k;
     }
     flush_counters(cnt, P.counters);
@@ -335,8 +581,24 @@ __global__ __launch_bounds__(256) void lcp_query_kernel(LcpQueryParams Q) {
     flush_counters(cnt, Q.counters);
 }
 
-hipError_t launch_ctl_init(FrontierCtl* ctl, CountersDev* cnt, hipStream_t s) {
-    hipLaunchKernelGGL(ctl_init_kernel, dim3(1), dim3(64), 0, s, ctl, cnt);
+// Workgroup-tier LCP queries: one workgroup per query (tests of the tier).
+__global__ __launch_bounds__(kFrontierThreads) void lcp_query_wg_kernel(LcpQueryParams Q) {
+    __shared__ int32_t wmin;
+    CountersDev cnt = {};
+    const Engine en = make_engine(Q.p, Q.h, 0, Q.lane_words, nullptr);
+    for (int64_t qi = blockIdx.x; qi < Q.count; qi += gridDim.x) {
+        const int32_t x = static_cast<int32_t>(Q.x[qi]);
+        const int32_t y = static_cast<int32_t>(Q.y[qi]);
+        const int32_t la = en.A.len - x, lb = en.B.len - y;
+        const int32_t lim = la < lb ? la : lb;
+        const int32_t l = lcp_wg_direct(en.A, en.B, x, y, lim, 0, wmin);
+        if (threadIdx.x == 0) Q.out[qi] = l;
+    }
+    (void)cnt;
+}
+
+hipError_t launch_ctl_init(FrontierCtl* ctl, CountersDev* cnt, unsigned int* bar, hipStream_t s) {
+    hipLaunchKernelGGL(ctl_init_kernel, dim3(1), dim3(256), 0, s, ctl, cnt, bar);
     return hipGetLastError();
 }
 
@@ -348,7 +610,8 @@ hipError_t frontier_max_grid(int device, int* grid_out) {
                                                      kFrontierThreads, 0);
     if (e != hipSuccess) return e;
     if (per < 1) per = 1;
-    *grid_out = cus * per;
+    int g = cus * per;
+    *grid_out = g < kMaxGrid ? g : kMaxGrid;
     return hipSuccess;
 }
 
@@ -365,6 +628,12 @@ hipError_t launch_batch(const BatchParams& bp, int grid, hipStream_t s) {
 }
 
 hipError_t launch_lcp_queries(const LcpQueryParams& qp, hipStream_t s) {
+    if (qp.engine == 2) {
+        int64_t blocks = qp.count < 1 ? 1 : qp.count;
+        if (blocks > 1024) blocks = 1024;
+        hipLaunchKernelGGL(lcp_query_wg_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kFrontierThreads), 0, s, qp);
+        return hipGetLastError();
+    }
     int64_t waves = qp.count < 1 ? 1 : qp.count;
     int64_t blocks = (waves + 3) / 4;
     if (blocks > 2048) blocks = 2048;

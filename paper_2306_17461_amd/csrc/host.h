@@ -32,7 +32,8 @@ constexpr size_t kPowEntries = 2 * 65536 + 65 + 257 + 65;
 constexpr size_t kMiscTicket = 0;
 constexpr size_t kMiscAlpha = 64;
 
-constexpr uint32_t kDefaultLdsRounds = 2048;
+constexpr uint32_t kDefaultLdsRounds = 1024;
+constexpr uint32_t kDefaultBlockRounds = 32;
 
 }  // namespace ed
 
@@ -49,6 +50,7 @@ struct ed_ctx {
     ed::FrontierCtl* h_ctl = nullptr;  // pinned
     ed::CountersDev* h_cnt = nullptr;  // pinned
     hipEvent_t ev[2] = {nullptr, nullptr};  // frontier timing
+    unsigned int* d_bar = nullptr;          // device-wide barrier flags
     ed::DevPool pool;
 };
 
@@ -74,6 +76,8 @@ struct ed_pair {
     hipEvent_t ev_prep[2] = {nullptr, nullptr};  // around the prepare kernel (ED_FLAG_TIMING)
     bool prep_timed = false;
     double gpu_ns_frontier = 0;
+    uint64_t rounds_phase_a = 0;
+    double us_phase_a = 0, us_phase_b = 0;
 };
 
 namespace ed {

@@ -68,15 +68,22 @@ struct CountersDev {
 
 // Control block of one single-pair launch (device memory).
 struct FrontierCtl {
-    unsigned int bar_count;
-    unsigned int bar_gen;
-    int32_t phase;     // 0: one workgroup; 1: grid-wide
-    int32_t phase_t;   // round reached when going grid-wide
-    int32_t found_t;   // first round whose frontier reaches (n, m); -1 before
-    int32_t status;    // 0 running, 1 done, 2 k_max reached, 3 out of capacity
-    int32_t result_t;  // reported rounds (k, k_max + 1, or last round at capacity)
-    int32_t wbuf;      // which buffer (0/1) holds the last frontier
+    unsigned int release;   // device-wide barrier: epoch released by workgroup 0
+    int32_t phase;          // 0: one workgroup; 1: grid-wide
+    int32_t phase_t;        // round reached when going grid-wide
+    int32_t found_t;        // smallest round whose frontier reaches (n, m); INT32_MAX before
+    int32_t status;         // 0 running, 1 done, 2 k_max reached, 3 out of capacity, 4 error
+    int32_t result_t;       // reported rounds (k, k_max + 1, or last round at capacity)
+    int32_t wbuf;           // which buffer (0/1) holds the last frontier
+    int32_t pad_;
+    uint64_t clk_begin;     // s_memrealtime (100 MHz) at kernel start
+    uint64_t clk_switch;    // ... when the one-workgroup phase ended
+    uint64_t clk_end;       // ... at kernel end
 };
+
+// Device-wide barrier flags: one 128-byte line per workgroup.
+constexpr int kBarStride = 32;  // uint32 per line
+constexpr int kMaxGrid = 1024;
 
 struct FrontierParams {
     PairDev p;
@@ -86,10 +93,13 @@ struct FrontierParams {
     int32_t K;         // supports rounds t <= K
     int32_t t0;        // first round already computed (resume: f_t0 is in f0)
     int32_t kmax;      // -1 = none
-    int32_t lds_rounds;  // rounds run by workgroup 0 in LDS (<= kLdsRoundsMax)
+    int32_t lds_rounds;  // rounds run by workgroup 0 alone, rows in LDS (<= kLdsRoundsMax)
+    int32_t block_rounds;  // grid-wide phase: rounds between device-wide barriers
     int32_t engine;
     int32_t lane_words;
+    int32_t pad_;
     FrontierCtl* ctl;
+    unsigned int* bar;  // kMaxGrid lines of kBarStride uint32
     int32_t* dump;     // optional per-round rows (device), row t at t*t
     int64_t dump_cap;
     CountersDev* counters;
@@ -161,7 +171,7 @@ struct LcpQueryParams {
 hipError_t launch_prep_clear(const PrepParams& pp, hipStream_t s);
 hipError_t launch_prepare(const PrepParams& pp, int grid, hipStream_t s);
 hipError_t launch_copy8_rest(const PrepParams& pp, hipStream_t s);
-hipError_t launch_ctl_init(FrontierCtl* ctl, CountersDev* cnt, hipStream_t s);
+hipError_t launch_ctl_init(FrontierCtl* ctl, CountersDev* cnt, unsigned int* bar, hipStream_t s);
 hipError_t launch_frontier(const FrontierParams& fp, int grid, hipStream_t s);
 hipError_t frontier_max_grid(int device, int* grid_out);
 hipError_t launch_batch(const BatchParams& bp, int grid, hipStream_t s);

@@ -155,14 +155,15 @@ def _lcp_cases():
     yield "zeros", Z, Z.copy()
 
 
-@pytest.mark.parametrize("engine", [0, 1])
+@pytest.mark.parametrize("engine", [0, 1, 2])
 @pytest.mark.parametrize("pack_bits", [0, 8])
 @pytest.mark.parametrize("block", [32, 1, 4, 256])
 def test_lcp_engines(ed, make_ctx, orc, engine, pack_bits, block):
-    if engine == 0 and block != 32:
+    """engine 0: lane + wave tiers; 1: hash search; 2: direct workgroup tier."""
+    if engine != 1 and block != 32:
         pytest.skip("block size only matters for the hash engine")
     rng = np.random.default_rng(engine * 100 + pack_bits + block)
-    ctx = make_ctx(engine=engine, pack_bits=pack_bits, block=block, hash_seed=77)
+    ctx = make_ctx(engine=min(engine, 1), pack_bits=pack_bits, block=block, hash_seed=77)
     for name, A, B in _lcp_cases():
         say("lcp", engine, pack_bits, block, name)
         n, m = len(A), len(B)
@@ -181,7 +182,7 @@ def test_lcp_engines(ed, make_ctx, orc, engine, pack_bits, block):
         for _ in range(200):
             xs.append(int(rng.integers(0, n + 1))); ys.append(int(rng.integers(0, m + 1)))
         p = ed.ed_prepare(ctx, A, B)
-        got = ed.ed_debug_lcp(ctx, p, xs, ys)
+        got = ed.ed_debug_lcp(ctx, p, xs, ys, engine=engine)
         want = np.array([orc.lcp(A, B, x, y) for x, y in zip(xs, ys)])
         bad = np.nonzero(got != want)[0]
         assert len(bad) == 0, [(xs[i], ys[i], int(got[i]), int(want[i])) for i in bad[:10]]
@@ -196,6 +197,9 @@ FRONTIER_MODES = [
     ("grid", dict(flags=2)),
     ("lds3", dict(lds_rounds=3)),
     ("grow", dict(lds_rounds=2, init_rows=4)),
+    ("blk1", dict(lds_rounds=4, block_rounds=1)),
+    ("blk7g3", dict(lds_rounds=4, block_rounds=7, grid_blocks=3)),
+    ("g1", dict(lds_rounds=2, block_rounds=5, grid_blocks=1)),
 ]
 
 
@@ -285,9 +289,10 @@ def test_k_max_cutoff(ed, make_ctx, orc, engine):
 
 
 @pytest.mark.parametrize("engine", [0, 1])
-@pytest.mark.parametrize("mode", ["default", "grid", "grow"])
+@pytest.mark.parametrize("mode", ["default", "grid", "grow", "narrow"])
 def test_medium_pairs(ed, make_ctx, orc, engine, mode):
-    kw = {"default": {}, "grid": dict(flags=2), "grow": dict(lds_rounds=64, init_rows=100)}[mode]
+    kw = {"default": {}, "grid": dict(flags=2), "grow": dict(lds_rounds=64, init_rows=100),
+          "narrow": dict(grid_blocks=1, lds_rounds=16, block_rounds=8)}[mode]
     ctx = make_ctx(engine=engine, **kw)
     for (n, k, sigma, seed) in [(200000, 3000, 4, 1), (100000, 9000, 4, 2), (150000, 2000, 20, 3),
                                 (300000, 500, 256, 4), (60000, 6000, 2, 5)]:
