@@ -126,6 +126,41 @@ __device__ __forceinline__ int32_t lcp_wave_direct(const SView& A, const SView& 
     return lim;
 }
 
+// Engine (a), wave tier with a step budget: at most `steps` steps of 4 words
+// per lane (8192 characters at 2-bit, 2048 at 8-bit per step).  Returns the
+// matched length; `done` tells whether the LCP is complete.
+__device__ __forceinline__ int32_t lcp_wave_steps(const SView& A, const SView& B, int32_t x, int32_t y,
+                                                  int32_t lim, int32_t l, int steps, bool& done) {
+    constexpr int W = 4;
+    const int lane = lane_id();
+    const int32_t cpw = 1 << A.lcpw;
+    for (int s = 0; s < steps && l < lim; ++s) {
+        uint64_t d[W];
+        int32_t p[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            p[w] = l + (w * 64 + lane) * cpw;
+            const bool ok = p[w] < lim;
+            const int32_t q = ok ? p[w] : 0;
+            const uint64_t v = fetch(A, x + q) ^ fetch(B, y + q);
+            d[w] = ok ? v : 0;
+        }
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const uint64_t b = ballot(d[w] != 0);
+            if (b) {
+                const int s0 = ctz64(b);
+                const int32_t c = shfl_i32(p[w], s0) + ctz64(shfl_u64(d[w], s0)) / A.bpc;
+                done = true;
+                return c < lim ? c : lim;
+            }
+        }
+        l += W * 64 * cpw;
+    }
+    done = l >= lim;
+    return l < lim ? l : lim;
+}
+
 // ---------------------------------------------------------------------------
 // Engine (b): prefix hashes.  H(S, p) = h(S[0..p)) is rebuilt from the
 // blocked table as T[p/b] * r^(p mod b) + h(S[(p/b)b .. p)) (Algorithm 2,

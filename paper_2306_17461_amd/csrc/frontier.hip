@@ -40,15 +40,16 @@ namespace ed {
 namespace {
 
 constexpr int kU = 4;          // diagonals per thread per pass
-constexpr int kJobHalf = 128;  // jobs per pass (a ring of two halves)
+constexpr int kJobHalf = 128;  // queued LCPs per round (a ring of two halves)
+constexpr int kWaveSteps = 2;  // wavefront steps before the hash search / workgroup tier
 
 struct RoundShared {
+    int32_t ji[2 * kJobHalf];
     int32_t jx[2 * kJobHalf];
     int32_t jy[2 * kJobHalf];
     int32_t jlim[2 * kJobHalf];
     int32_t jl[2 * kJobHalf];
-    int32_t jres[2 * kJobHalf];
-    int32_t jcount[2];  // monotonic job counters, one per pass parity
+    int32_t jcount[2];  // monotonic job counters, one per round parity
     int32_t wmin;       // workgroup-tier reduction slot
     int32_t flag;
     int32_t pair;
@@ -123,25 +124,37 @@ __device__ __forceinline__ int32_t lcp_wg_direct(const SView& A, const SView& B,
 // min(t,n)] is written as kNone).  Diagonal i of a row lives at
 // row[i + ofs]; every index formed here is inside the row, so no pointer
 // ever points before an array (rows in LDS stay LDS addresses).  Called by
-// every thread of the workgroup.  Diagonals in [dlo, dhi] are also copied to
-// dump_row[i + t].  Returns true in the thread that found f_t[n-m] = n.
+// every thread of the workgroup; ends with a workgroup barrier, after which
+// `cur` is complete and RS.flag is 1 if f_t[n-m] = n was found.  Diagonals in
+// [dlo, dhi] are also copied to dump_row[i + t].  Returns true in the thread
+// that found the target.
+//
+// Tiers of the slide: (1) each lane compares the first two words of each of
+// its diagonals, all loads in flight together; (2) a lane whose LCP runs on
+// is extended by its own wavefront, kWaveSteps steps of 4 words per lane;
+// (3) the hash engine then finishes with its wavefront-parallel search, the
+// direct engine queues the LCP and the whole workgroup extends it after the
+// round barrier (the queue and its counter alternate with the round parity,
+// so the next round's pushes never meet this round's reads).
 template <typename PrevPtr, typename CurPtr>
 __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr prev, CurPtr cur,
                                             int32_t ofs, int32_t i_begin, int32_t i_end, RoundShared& RS,
                                             JobCursor& jc, int32_t* dump_row, int32_t dlo, int32_t dhi,
                                             CountersDev& cnt) {
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
+    const int lane = tid & 63;
     const int32_t n = en.A.len, m = en.B.len;
     const int32_t lo = imax(-t, -m), hi = imin(t, n);
     const int32_t target = n - m;
     const int32_t cpw = 1 << en.A.lcpw;
+    const int par = t & 1;
+    const int half = par * kJobHalf;
+    const int32_t jstart = jc.start[par];
     bool found = false;
-    int par = 0;
     for (int32_t base = i_begin; base < i_end; base += nthr * kU) {
-        int32_t iv[kU], c[kU], l[kU], lim[kU], slot[kU];
-        bool val[kU], act[kU], pend[kU];
-        uint64_t d[kU];
+        int32_t iv[kU], c[kU], l[kU], lim[kU];
+        bool val[kU], act[kU], pend[kU], queued[kU];
+        uint64_t d0[kU], d1[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             const int32_t i = base + u * nthr + tid;
@@ -162,100 +175,76 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
             val[u] = inr && cc >= 0;
             lim[u] = val[u] ? imin(n - cc, m - (cc - i)) : 0;
         }
-        // first word of every diagonal: all loads in flight together
+        // (1) first two words of every diagonal, all loads in flight together
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-            const int32_t xs = lim[u] > 0 ? c[u] : 0;
-            const int32_t ys = lim[u] > 0 ? c[u] - iv[u] : 0;
-            d[u] = fetch(en.A, xs) ^ fetch(en.B, ys);
+            const bool go = lim[u] > 0;
+            const int32_t xs = go ? c[u] : 0;
+            const int32_t ys = go ? c[u] - iv[u] : 0;
+            const bool two = lim[u] > cpw;
+            d0[u] = fetch(en.A, xs) ^ fetch(en.B, ys);
+            d1[u] = two ? (fetch(en.A, xs + cpw) ^ fetch(en.B, ys + cpw)) : 0;
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             l[u] = 0;
             pend[u] = false;
+            queued[u] = false;
             if (lim[u] > 0) {
-                if (d[u]) {
-                    l[u] = imin(ctz64(d[u]) / en.A.bpc, lim[u]);
+                if (d0[u]) {
+                    l[u] = imin(ctz64(d0[u]) / en.A.bpc, lim[u]);
                 } else if (lim[u] <= cpw) {
                     l[u] = lim[u];
+                } else if (d1[u]) {
+                    l[u] = imin(cpw + ctz64(d1[u]) / en.A.bpc, lim[u]);
+                } else if (lim[u] <= 2 * cpw) {
+                    l[u] = lim[u];
                 } else {
-                    l[u] = cpw;
+                    l[u] = 2 * cpw;
                     pend[u] = true;
                 }
             }
         }
-        if (en.lane_words > 1) {
-#pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                if (pend[u]) {
-                    bool more = false;
-                    const int32_t l2 = lcp_lane(en.A, en.B, c[u] + cpw, c[u] - iv[u] + cpw, lim[u] - cpw,
-                                                en.lane_words - 1, &more);
-                    l[u] = cpw + l2;
-                    pend[u] = more;
-                }
-            }
-        }
-        // long LCPs: job list for this pass
-        const int half = par * kJobHalf;
+        // (2)/(3) the wavefront extends its lanes' long LCPs
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-            slot[u] = -1;
-            if (pend[u]) {
-                const int32_t s = atomicAdd(&RS.jcount[par], 1) - jc.start[par];
-                if (s < kJobHalf) {
-                    slot[u] = half + s;
-                    RS.jx[half + s] = c[u];
-                    RS.jy[half + s] = c[u] - iv[u];
-                    RS.jlim[half + s] = lim[u];
-                    RS.jl[half + s] = l[u];
-                }
-            }
-        }
-        __syncthreads();
-        const int32_t jend = RS.jcount[par];
-        const int32_t nj = imin(jend - jc.start[par], kJobHalf);
-        jc.start[par] = jend;
-        if (nj > 0) {
-            if (en.kind == 0) {
-                for (int j = 0; j < nj; ++j) {
-                    const int32_t r = lcp_wg_direct(en.A, en.B, RS.jx[half + j], RS.jy[half + j],
-                                                    RS.jlim[half + j], RS.jl[half + j], RS.wmin);
-                    if (tid == 0) RS.jres[half + j] = r;
-                }
-            } else {
-                for (int j = wave; j < nj; j += nwaves) {
-                    const int32_t jx = RS.jx[half + j], jy = RS.jy[half + j];
-                    const int32_t jlim = RS.jlim[half + j], jl = RS.jl[half + j];
-                    const int32_t r = jl > 0 ? lcp_wave_hash(en.A, en.B, en.TA, en.TB, en.q, jx, jy, jlim, jl, cnt)
-                                             : lcp_wave_direct(en.A, en.B, jx, jy, jlim, jl);
-                    if (lane == 0) RS.jres[half + j] = r;
-                }
-            }
-            if (tid == 0) cnt.wave_lcps += static_cast<unsigned long long>(nj);
-            __syncthreads();
-#pragma unroll
-            for (int u = 0; u < kU; ++u)
-                if (slot[u] >= 0) l[u] = RS.jres[slot[u]];
-        }
-        // job list overflow: the lane's own wavefront extends it
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            uint64_t pm = ballot(pend[u] && slot[u] < 0);
+            uint64_t pm = ballot(pend[u]);
             while (pm) {
                 const int src = ctz64(pm);
                 pm &= pm - 1;
                 const int32_t jx = shfl_i32(c[u], src), jy = shfl_i32(c[u] - iv[u], src);
                 const int32_t jlim = shfl_i32(lim[u], src), jl = shfl_i32(l[u], src);
-                const int32_t r = (en.kind == 1 && jl > 0)
-                                      ? lcp_wave_hash(en.A, en.B, en.TA, en.TB, en.q, jx, jy, jlim, jl, cnt)
-                                      : lcp_wave_direct(en.A, en.B, jx, jy, jlim, jl);
-                if (lane == src) l[u] = r;
+                bool done = false;
+                int32_t r = lcp_wave_steps(en.A, en.B, jx, jy, jlim, jl, kWaveSteps, done);
                 if (lane == 0) cnt.wave_lcps++;
+                if (!done) {
+                    if (en.kind == 1) {
+                        r = lcp_wave_hash(en.A, en.B, en.TA, en.TB, en.q, jx, jy, jlim, r, cnt);
+                    } else {
+                        int32_t s = 0;
+                        if (lane == 0) s = atomicAdd(&RS.jcount[par], 1) - jstart;
+                        s = shfl_i32(s, 0);
+                        if (s < kJobHalf) {
+                            if (lane == src) {
+                                RS.ji[half + s] = iv[u];
+                                RS.jx[half + s] = jx;
+                                RS.jy[half + s] = jy;
+                                RS.jlim[half + s] = jlim;
+                                RS.jl[half + s] = r;
+                                queued[u] = true;
+                            }
+                            continue;
+                        }
+                        // queue full: the wavefront finishes it
+                        r = lcp_wave_direct(en.A, en.B, jx, jy, jlim, r);
+                    }
+                }
+                if (lane == src) l[u] = r;
             }
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
+            if (queued[u]) continue;
             const int32_t f = val[u] ? c[u] + l[u] : kNone;
             if (act[u]) {
                 cur[iv[u] + ofs] = f;
@@ -267,26 +256,56 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
                 if (iv[u] == target && f == n) found = true;
             }
         }
-        par ^= 1;
+    }
+    if (found) RS.flag = 1;
+    __syncthreads();
+    // workgroup tier for the queued LCPs of this round (direct engine)
+    const int32_t jend = RS.jcount[par];
+    const int32_t nj = imin(jend - jstart, kJobHalf);
+    jc.start[par] = jend;
+    if (nj > 0) {
+        for (int j = 0; j < nj; ++j) {
+            const int32_t jx = RS.jx[half + j];
+            const int32_t r = lcp_wg_direct(en.A, en.B, jx, RS.jy[half + j], RS.jlim[half + j],
+                                            RS.jl[half + j], RS.wmin);
+            if (tid == 0) {
+                const int32_t i = RS.ji[half + j];
+                const int32_t f = jx + r;
+                cur[i + ofs] = f;
+                if (dump_row && i >= dlo && i <= dhi) dump_row[i + t] = f;
+                cnt.updates++;
+                cnt.grid_lcps++;
+                cnt.lcp_chars += static_cast<unsigned long long>(r);
+                if (i == target && f == n) {
+                    found = true;
+                    RS.flag = 1;
+                }
+            }
+        }
+        __syncthreads();
     }
     return found;
 }
 
 // Device-wide barrier: workgroup g > 0 raises its flag to `epoch`; workgroup 0
-// waits for every flag, then publishes `epoch` in ctl->release.
+// waits for every flag, then publishes `epoch` in ctl->release.  Waiting
+// loops poll with relaxed loads (no cache invalidation per poll) and take one
+// acquire fence once the value arrived.
 __device__ __forceinline__ void grid_sync(FrontierCtl* ctl, unsigned int* bar, unsigned int epoch) {
     __syncthreads();
     if (blockIdx.x == 0) {
         for (int g = threadIdx.x + 1; g < static_cast<int>(gridDim.x); g += blockDim.x)
-            while (__hip_atomic_load(bar + g * kBarStride, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < epoch)
+            while (__hip_atomic_load(bar + g * kBarStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch)
                 __builtin_amdgcn_s_sleep(1);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         __syncthreads();
         if (threadIdx.x == 0)
             __hip_atomic_store(&ctl->release, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else if (threadIdx.x == 0) {
         __hip_atomic_store(bar + blockIdx.x * kBarStride, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        while (__hip_atomic_load(&ctl->release, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < epoch)
+        while (__hip_atomic_load(&ctl->release, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch)
             __builtin_amdgcn_s_sleep(1);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
 }
@@ -326,8 +345,7 @@ __device__ __forceinline__ int32_t pair_in_workgroup(const Engine& en, LdsState&
     if (tid == 0) RS.flag = 0;
     __syncthreads();
     int32_t t = 0;
-    if (round_range(en, 0, la, la, off, -2, 3, RS, jc, nullptr, 0, -1, cnt)) RS.flag = 1;
-    __syncthreads();
+    round_range(en, 0, la, la, off, -2, 3, RS, jc, nullptr, 0, -1, cnt);
     const int32_t lr = imin(lds_rounds, kLdsRoundsMax);
     for (;;) {
         if (RS.flag) return t;
@@ -335,11 +353,10 @@ __device__ __forceinline__ int32_t pair_in_workgroup(const Engine& en, LdsState&
         if (t > maxnm) return -3;
         if (t >= lr) break;
         ++t;
-        if (round_range(en, t, la, lb, off, -(t + 2), t + 3, RS, jc, nullptr, 0, -1, cnt)) RS.flag = 1;
+        round_range(en, t, la, lb, off, -(t + 2), t + 3, RS, jc, nullptr, 0, -1, cnt);
         int32_t* tmp = la;
         la = lb;
         lb = tmp;
-        __syncthreads();
     }
     if (t > K || g0 == nullptr) return -3;
     // global rows: diagonal i at g[i + K + 2]
@@ -352,11 +369,10 @@ __device__ __forceinline__ int32_t pair_in_workgroup(const Engine& en, LdsState&
         if (kmax >= 0 && t >= kmax) return kmax + 1;
         if (t > maxnm || t >= K) return -3;
         ++t;
-        if (round_range(en, t, ga, gb, K + 2, -(t + 2), t + 3, RS, jc, nullptr, 0, -1, cnt)) RS.flag = 1;
+        round_range(en, t, ga, gb, K + 2, -(t + 2), t + 3, RS, jc, nullptr, 0, -1, cnt);
         int32_t* tmp = ga;
         ga = gb;
         gb = tmp;
-        __syncthreads();
     }
 }
 
@@ -413,9 +429,7 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
             const int32_t off = kLdsRoundsMax + 2;  // diagonal i at row[i + off]
             int32_t* la = L.row[0];
             int32_t* lb = L.row[1];
-            if (round_range(en, 0, la, la, off, -2, 3, RS, jc, P.dump && P.dump_cap >= 1 ? P.dump : nullptr, 0, 0, cnt))
-                RS.flag = 1;
-            __syncthreads();
+            round_range(en, 0, la, la, off, -2, 3, RS, jc, P.dump && P.dump_cap >= 1 ? P.dump : nullptr, 0, 0, cnt);
             const int32_t lr = imin(imin(P.lds_rounds, kLdsRoundsMax), K);
             int32_t status = 0, result = 0;
             for (;;) {
@@ -424,12 +438,10 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
                 if (t > maxnm) { status = 4; result = t; break; }
                 if (t >= lr) break;
                 ++t;
-                if (round_range(en, t, la, lb, off, -(t + 2), t + 3, RS, jc, dump_row_for(P.dump, P.dump_cap, t), -t, t, cnt))
-                    RS.flag = 1;
+                round_range(en, t, la, lb, off, -(t + 2), t + 3, RS, jc, dump_row_for(P.dump, P.dump_cap, t), -t, t, cnt);
                 int32_t* tmp = la;
                 la = lb;
                 lb = tmp;
-                __syncthreads();
             }
             if (status == 0)
                 for (int32_t e = tid; e < 2 * t + 5; e += nthr) gp[gofs + e - (t + 2)] = la[off + e - (t + 2)];
@@ -448,8 +460,10 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
             finished = status != 0;
         } else {
             if (tid == 0) {
-                while (__hip_atomic_load(&ctl->phase, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0)
+                // relaxed polling (no cache invalidation per poll), one acquire fence
+                while (__hip_atomic_load(&ctl->phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
                     __builtin_amdgcn_s_sleep(64);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 RS.flag = __hip_atomic_load(&ctl->status, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
             }
             __syncthreads();
@@ -527,7 +541,6 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
                     int32_t* tmp = rp;
                     rp = rc;
                     rc = tmp;
-                    __syncthreads();
                 }
                 for (int32_t i = a + tid; i <= b; i += nthr) gc[i + gofs] = rp[i + wofs];
             }

@@ -268,6 +268,9 @@ def test_edge_cases(ed, make_ctx, orc, engine):
         "ones": (np.array([1], np.uint8), np.array([2], np.uint8)),
         "zeros_vs_ones": (np.zeros(700, np.uint8), np.ones(900, np.uint8)),
         "periodic": (synth.periodic_string(9000, d4, 3, 64), synth.periodic_string(9050, d4, 3, 64)),
+        # almost every diagonal has a long LCP: more long LCPs per round than the queue holds
+        "zeros_edits": (np.zeros(20000, np.uint8),
+                        synth.plant_edits(np.zeros(20000, np.uint8), 300, synth.CharDist("uniform", 2), 4)[0]),
     }
     for name, (A, B) in cases.items():
         say("edge", engine, name)
