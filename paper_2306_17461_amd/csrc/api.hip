@@ -215,6 +215,9 @@ int ed_init(ed_ctx** out, int device, const ed_options* opt) {
     int fg = 0;
     if (frontier_max_grid(device, &fg) != hipSuccess || fg < 1) fg = c->num_cu;
     c->frontier_grid_max = fg;
+    int tg = 0;
+    if (task_max_grid(device, &tg) != hipSuccess || tg < 1) tg = c->num_cu;
+    c->task_grid_max = tg;
     if (hipMalloc(&c->d_ctl, sizeof(FrontierCtl)) != hipSuccess ||
         hipMalloc(&c->d_cnt, sizeof(CountersDev)) != hipSuccess ||
         hipHostMalloc(&c->h_ctl, sizeof(FrontierCtl)) != hipSuccess ||

@@ -32,6 +32,84 @@ int64_t batch_row_capacity(int64_t maxnm, int64_t k_max, uint32_t lds_rounds) {
     return K;
 }
 
+// Device buffers of one task launch (pair states, queue, rows).
+struct TaskLaunch {
+    void* blk = nullptr;
+    TaskPair* d_pairs = nullptr;
+    unsigned long long* d_seq = nullptr;
+    long long* d_task = nullptr;
+    unsigned long long* d_ctr = nullptr;  // head, tail
+    int32_t* d_remaining = nullptr;
+    uint32_t qcap = 0;
+};
+
+int tasks_run(ed_ctx* c, std::vector<TaskPair>& st, const std::vector<int32_t>& first, int64_t k_max,
+              uint32_t engine, hipStream_t s) {
+    const uint64_t count = st.size();
+    const uint32_t solo = c->opt.lds_rounds ? c->opt.lds_rounds : kDefaultLdsRounds;
+    const int32_t C = kChunkDiags;
+    // every task that can be in flight at once: one per pair, plus one
+    // super-step of chunks per pair with rows, plus slack for the workgroups
+    uint64_t qcap = count + 256;
+    for (const TaskPair& tp : st)
+        if (tp.K > 0) qcap += (2ull * tp.K + 5 + C - 1) / C;
+    const size_t pairs_bytes = count * sizeof(TaskPair);
+    const size_t head = (pairs_bytes + 255) & ~size_t(255);
+    const size_t qbytes = qcap * 16;
+    void* blk = c->pool.get(head + qbytes + 256);
+    if (!blk) {
+        set_error("ed_batch: device allocation failed");
+        return ED_ENOMEM;
+    }
+    char* base = static_cast<char*>(blk);
+    TaskParams tp;
+    std::memset(&tp, 0, sizeof tp);
+    tp.pairs = reinterpret_cast<TaskPair*>(base);
+    tp.qseq = reinterpret_cast<unsigned long long*>(base + head);
+    tp.qtask = reinterpret_cast<long long*>(base + head + qcap * 8);
+    tp.qhead = reinterpret_cast<unsigned long long*>(base + head + qbytes);
+    tp.qtail = tp.qhead + 1;
+    tp.remaining = reinterpret_cast<int32_t*>(tp.qhead + 2);
+    tp.qcap = static_cast<uint32_t>(qcap);
+    tp.count = static_cast<int32_t>(count);
+    tp.kmax = k_max >= 0 ? static_cast<int32_t>(std::min<int64_t>(k_max, INT32_MAX - 1)) : -1;
+    tp.engine = static_cast<int32_t>(engine);
+    tp.lane_words = static_cast<int32_t>(c->opt.lane_words ? c->opt.lane_words : 2u);
+    tp.solo_rounds = static_cast<int32_t>(solo);
+    tp.block_rounds = static_cast<int32_t>(c->opt.block_rounds ? c->opt.block_rounds : kDefaultBlockRounds);
+    tp.chunk_diags = C;
+    tp.h = ctx_hash(c);
+    tp.counters = c->d_cnt;
+    // queue image: the first tasks full, every other slot waiting for lap 0
+    std::vector<unsigned long long> seq(qcap);
+    std::vector<long long> task(qcap, 0);
+    for (uint64_t q = 0; q < qcap; ++q) seq[q] = q;
+    for (size_t q = 0; q < first.size(); ++q) {
+        seq[q] = q + 1;
+        task[q] = static_cast<long long>(static_cast<uint32_t>(first[q])) |
+                  (static_cast<long long>(kTaskSolo) << 32);
+    }
+    unsigned long long ctr[2] = {0ull, static_cast<unsigned long long>(first.size())};
+    int32_t remaining = static_cast<int32_t>(first.size());
+    int grid = c->opt.grid_blocks ? static_cast<int>(c->opt.grid_blocks) : c->task_grid_max;
+    grid = std::max(1, grid);
+    hipError_t e = hipMemcpyAsync(tp.pairs, st.data(), pairs_bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(tp.qseq, seq.data(), qcap * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(tp.qtask, task.data(), qcap * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(tp.qhead, ctr, 16, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(tp.remaining, &remaining, 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_ctl_init(c->d_ctl, c->d_cnt, nullptr, s);
+    if (e == hipSuccess && remaining > 0) e = launch_tasks(tp, grid, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(st.data(), tp.pairs, pairs_bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    c->pool.put(blk);
+    if (e != hipSuccess) {
+        set_error("task launch: %s", hipGetErrorString(e));
+        return ED_EDEVICE;
+    }
+    return ED_OK;
+}
+
 int batch_locked(ed_ctx* c, ed_pair* const* pairs, uint64_t count, int64_t k_max, uint64_t* k_out,
                  int32_t* status_out, hipStream_t s) {
     if (count == 0) return ED_OK;
@@ -51,16 +129,13 @@ int batch_locked(ed_ctx* c, ed_pair* const* pairs, uint64_t count, int64_t k_max
         int rc = ctx_set_hash(c, pairs[0]->seed);
         if (rc != ED_OK) return rc;
     }
-    const uint32_t lds_rounds = c->opt.lds_rounds ? c->opt.lds_rounds : kDefaultLdsRounds;
-    const uint32_t lane_words = c->opt.lane_words ? c->opt.lane_words : (engine == ED_ENGINE_HASH ? 1u : 2u);
+    const uint32_t solo = c->opt.lds_rounds ? c->opt.lds_rounds : kDefaultLdsRounds;
 
-    // order: largest pairs first (longest-processing-time first), or a
-    // seeded permutation when testing order independence
+    // processing order: largest pairs first (longest-processing-time first), or
+    // a seeded permutation when testing order independence
     std::vector<int32_t> order(count);
     std::iota(order.begin(), order.end(), 0);
-    auto size_of = [&](int32_t i) {
-        return std::max(pairs[i]->len[0], pairs[i]->len[1]);
-    };
+    auto size_of = [&](int32_t i) { return std::max(pairs[i]->len[0], pairs[i]->len[1]); };
     if (c->opt.flags & ED_FLAG_SHUFFLE) {
         std::vector<uint64_t> key(count);
         for (uint64_t i = 0; i < count; ++i) key[i] = mix64(c->opt.hash_seed * 0x9E3779B97F4A7C15ull + i);
@@ -69,85 +144,57 @@ int batch_locked(ed_ctx* c, ed_pair* const* pairs, uint64_t count, int64_t k_max
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return size_of(a) > size_of(b); });
     }
 
-    // rows for pairs that outgrow the LDS rounds, carved out of one block
+    // rows for the pairs that can outgrow a whole-pair task, from one block
+    std::vector<TaskPair> st(count);
     std::vector<int64_t> K(count, 0);
     size_t row_ints = 0;
     for (uint64_t i = 0; i < count; ++i) {
         const int64_t maxnm = static_cast<int64_t>(std::max(pairs[i]->len[0], pairs[i]->len[1]));
-        K[i] = batch_row_capacity(maxnm, k_max, lds_rounds);
+        K[i] = batch_row_capacity(maxnm, k_max, solo);
         if (K[i] > 0) row_ints += 2 * static_cast<size_t>(2 * K[i] + 5);
     }
-    const size_t items_bytes = count * sizeof(BatchItem);
-    const size_t order_bytes = count * 4;
-    const size_t kout_bytes = count * 4;
-    const size_t head = (items_bytes + order_bytes + kout_bytes + 64 + 255) & ~size_t(255);
-    void* blk = c->pool.get(head + row_ints * 4 + 4);
-    if (!blk) {
+    void* rows_blk = row_ints ? c->pool.get(row_ints * 4) : nullptr;
+    if (row_ints && !rows_blk) {
         set_error("ed_batch: device allocation failed");
         return ED_ENOMEM;
     }
-    char* base = static_cast<char*>(blk);
-    BatchItem* d_items = reinterpret_cast<BatchItem*>(base);
-    int32_t* d_order = reinterpret_cast<int32_t*>(base + items_bytes);
-    int32_t* d_kout = reinterpret_cast<int32_t*>(base + items_bytes + order_bytes);
-    unsigned int* d_ticket = reinterpret_cast<unsigned int*>(base + items_bytes + order_bytes + kout_bytes);
-    int32_t* rows = reinterpret_cast<int32_t*>(base + head);
-
-    std::vector<BatchItem> items(count);
+    int32_t* rows = static_cast<int32_t*>(rows_blk);
     size_t off = 0;
     for (uint64_t i = 0; i < count; ++i) {
-        std::memset(&items[i], 0, sizeof(BatchItem));
-        items[i].p = pair_dev(pairs[i]);
-        items[i].K = static_cast<int32_t>(K[i]);
+        TaskPair& tp = st[i];
+        std::memset(&tp, 0, sizeof tp);
+        tp.p = pair_dev(pairs[i]);
+        tp.K = static_cast<int32_t>(K[i]);
         if (K[i] > 0) {
-            items[i].f0 = rows + off;
+            tp.f0 = rows + off;
             off += 2 * K[i] + 5;
-            items[i].f1 = rows + off;
+            tp.f1 = rows + off;
             off += 2 * K[i] + 5;
         }
+        tp.t_limit = INT32_MAX;
+        tp.found_t = INT32_MAX;
     }
-    BatchParams bp;
-    std::memset(&bp, 0, sizeof bp);
-    bp.items = d_items;
-    bp.order = d_order;
-    bp.count = static_cast<int32_t>(count);
-    bp.kmax = k_max >= 0 ? static_cast<int32_t>(std::min<int64_t>(k_max, INT32_MAX - 1)) : -1;
-    bp.engine = static_cast<int32_t>(engine);
-    bp.lane_words = static_cast<int32_t>(lane_words);
-    bp.lds_rounds = static_cast<int32_t>(lds_rounds);
-    bp.h = ctx_hash(c);
-    bp.ticket = d_ticket;
-    bp.k_out = d_kout;
-    bp.counters = c->d_cnt;
-    std::vector<int32_t> kres(count, -1);
-    int grid = c->opt.grid_blocks ? static_cast<int>(c->opt.grid_blocks) : c->frontier_grid_max;
-    grid = std::max(1, std::min<int>(grid, static_cast<int>(std::min<uint64_t>(count, INT32_MAX))));
-    hipError_t e = hipMemcpyAsync(d_items, items.data(), items_bytes, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(d_order, order.data(), order_bytes, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_fill_u32(d_ticket, 1, 0u, s);
-    if (e == hipSuccess) e = launch_ctl_init(c->d_ctl, c->d_cnt, nullptr, s);
-    if (e == hipSuccess) e = launch_batch(bp, grid, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(kres.data(), d_kout, kout_bytes, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    c->pool.put(blk);
-    if (e != hipSuccess) {
-        set_error("ed_batch: %s", hipGetErrorString(e));
-        return ED_EDEVICE;
-    }
+    int rc = tasks_run(c, st, order, k_max, engine, s);
+    c->pool.put(rows_blk);
+    if (rc != ED_OK) return rc;
     int first = ED_OK;
     for (uint64_t i = 0; i < count; ++i) {
-        int st = ED_OK;
+        int status = ED_OK;
         uint64_t k = 0;
-        if (kres[i] >= 0) {
-            k = static_cast<uint64_t>(kres[i]);
+        if (st[i].status == 1 || st[i].status == 2) {
+            k = static_cast<uint64_t>(st[i].result);
             pairs[i]->rounds = k;
-        } else {
+        } else if (st[i].status == 3) {
             // rows too small for this pair: finish it on the single-pair path
-            st = distance_locked(c, pairs[i], k_max, &k, nullptr, 0, s);
+            status = distance_locked(c, pairs[i], k_max, &k, nullptr, 0, s);
+        } else {
+            if (first == ED_OK)
+                set_error("ed_batch: pair %llu ended with status %d", (unsigned long long)i, st[i].status);
+            status = ED_EINTERNAL;
         }
         if (k_out) k_out[i] = k;
-        if (status_out) status_out[i] = st;
-        if (st != ED_OK && first == ED_OK) first = st;
+        if (status_out) status_out[i] = status;
+        if (status != ED_OK && first == ED_OK) first = status;
     }
     return first;
 }

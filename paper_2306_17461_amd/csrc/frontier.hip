@@ -21,9 +21,8 @@
 //                    diagonal per round, so every value it computes is
 //                    exact), writes its slice back, and meets the others at a
 //                    device-wide barrier: one barrier per H rounds.
-//   batch_kernel     many pairs in one persistent launch: workgroups take
-//                    pairs from a device queue (largest first) and run all
-//                    rounds of a pair with workgroup barriers only.
+//   task_kernel      many pairs in one persistent launch, work stealing over
+//                    (pair, diagonal-chunk) tasks (batch and serving).
 //   lcp_query_kernel one LCP query per wavefront (tests of the engines).
 //
 // Inside a round every thread takes up to kU diagonals and issues the first
@@ -53,7 +52,7 @@ struct RoundShared {
     int32_t wmin;       // workgroup-tier reduction slot
     int32_t flag;
     int32_t pair;
-    int32_t pad_;
+    long long task;
 };
 
 struct LdsState {
@@ -330,27 +329,109 @@ __device__ __forceinline__ int32_t* dump_row_for(int32_t* dump, int64_t cap, int
     return (dump && static_cast<int64_t>(t + 1) * (t + 1) <= cap) ? dump + static_cast<int64_t>(t) * t : nullptr;
 }
 
-// Rounds of one pair inside one workgroup, from round 0: first in LDS (up to
-// lds_rounds rounds), then in the global rows g0/g1 (capacity K).
-// Returns k, kmax + 1, or -3 when the rows are too small.
-__device__ __forceinline__ int32_t pair_in_workgroup(const Engine& en, LdsState& L, JobCursor& jc, int32_t lds_rounds,
-                                     int32_t kmax, int32_t* g0, int32_t* g1, int32_t K, CountersDev& cnt) {
+// ---------------------------------------------------------------------------
+// Work stealing over (pair, diagonal-chunk) tasks.
+//
+// A pair starts as a whole-pair task: one workgroup runs its rounds with both
+// rows in LDS.  When its frontier outgrows `solo_rounds` the workgroup writes
+// the row to the pair's global rows and schedules a super-step: the 2T+5
+// entries of round T = t + H are cut into chunks of `chunk_diags` diagonals,
+// one task each.  A chunk task loads its diagonals plus a halo of H per side,
+// runs H rounds in LDS and writes its diagonals back; the workgroup that
+// finishes the last chunk of a super-step schedules the next one (or records
+// the result).  Tasks travel through a bounded multi-producer multi-consumer
+// ring: position p lives in slot p mod cap, whose sequence number is p while
+// the slot waits for the push of p and p + 1 once it holds that task.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void q_push(const TaskParams& P, long long task, unsigned long long pos) {
+    const uint32_t slot = static_cast<uint32_t>(pos % P.qcap);
+    while (__hip_atomic_load(P.qseq + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != pos)
+        __builtin_amdgcn_s_sleep(1);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __hip_atomic_store(P.qtask + slot, task, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(P.qseq + slot, pos + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One thread: the next task, or -1 once no pair of the launch is active.
+__device__ __forceinline__ long long q_pop(const TaskParams& P) {
+    const unsigned long long pos = atomicAdd(P.qhead, 1ull);
+    const uint32_t slot = static_cast<uint32_t>(pos % P.qcap);
+    for (;;) {
+        if (__hip_atomic_load(P.qseq + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == pos + 1) break;
+        if (__hip_atomic_load(P.remaining, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= 0) return -1;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const long long task = __hip_atomic_load(P.qtask + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(P.qseq + slot, pos + P.qcap, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    return task;
+}
+
+__device__ __forceinline__ void pair_finish(const TaskParams& P, TaskPair* S, int32_t status, int32_t result) {
+    S->status = status;
+    S->result = result;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(P.remaining, -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One thread: schedule the next super-step of pair pi (f_t in row S->cur).
+__device__ void schedule_superstep(const TaskParams& P, TaskPair* S, int32_t pi) {
+    const int32_t t = S->t;
+    int32_t H = imin(P.block_rounds, S->K - t);
+    H = imin(H, (kLdsRowLen - P.chunk_diags) / 2);  // window of a chunk must fit an LDS row
+    if (P.kmax >= 0) H = imin(H, P.kmax - t);
+    H = imin(H, S->t_limit - t);
+    if (H <= 0) {
+        if (P.kmax >= 0 && t >= P.kmax) pair_finish(P, S, 2, P.kmax + 1);
+        else if (t >= S->t_limit) pair_finish(P, S, 5, 0);
+        else pair_finish(P, S, 3, t);
+        return;
+    }
+    const int32_t T = t + H;
+    const int32_t total = 2 * T + 5;
+    const int32_t C = P.chunk_diags;
+    const int32_t nch = (total + C - 1) / C;
+    S->H = H;
+    S->T = T;
+    S->chunk = C;
+    S->nchunks = nch;
+    S->chunks_left = nch;
+    S->found_t = INT_MAX;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned long long base = atomicAdd(P.qtail, static_cast<unsigned long long>(nch));
+    for (int32_t c = 0; c < nch; ++c)
+        q_push(P, static_cast<long long>(static_cast<uint32_t>(pi)) |
+                      (static_cast<long long>(c + 1) << 32), base + c);
+}
+
+__device__ void solo_task(const TaskParams& P, int32_t pi, LdsState& L, JobCursor& jc, CountersDev& cnt) {
+    TaskPair* S = P.pairs + pi;
     const int tid = threadIdx.x, nthr = blockDim.x;
+    const Engine en = make_engine(S->p, P.h, P.engine, P.lane_words, L.lut4);
     const int32_t n = en.A.len, m = en.B.len;
     const int32_t maxnm = imax(n, m);
     const int32_t off = kLdsRoundsMax + 2;  // diagonal i at row[i + off]
     int32_t* la = L.row[0];
     int32_t* lb = L.row[1];
     RoundShared& RS = L.rs;
+    int32_t t = S->t;
+    const int32_t K = S->K, cur = S->cur, t_limit = S->t_limit;
+    int32_t* g = cur ? S->f1 : S->f0;
     if (tid == 0) RS.flag = 0;
     __syncthreads();
-    int32_t t = 0;
-    round_range(en, 0, la, la, off, -2, 3, RS, jc, nullptr, 0, -1, cnt);
-    const int32_t lr = imin(lds_rounds, kLdsRoundsMax);
+    if (t == 0) {
+        round_range(en, 0, la, la, off, -2, 3, RS, jc, nullptr, 0, -1, cnt);
+    } else {
+        for (int32_t e = tid; e < 2 * t + 5; e += nthr) la[off + e - (t + 2)] = g[K + 2 + e - (t + 2)];
+        __syncthreads();
+    }
+    const int32_t lr = imin(P.solo_rounds, kLdsRoundsMax);
+    int32_t status = 0, result = 0;
     for (;;) {
-        if (RS.flag) return t;
-        if (kmax >= 0 && t >= kmax) return kmax + 1;
-        if (t > maxnm) return -3;
+        if (RS.flag) { status = 1; result = t; break; }
+        if (P.kmax >= 0 && t >= P.kmax) { status = 2; result = P.kmax + 1; break; }
+        if (t > maxnm) { status = 4; result = t; break; }
+        if (t >= t_limit) { status = 5; break; }
         if (t >= lr) break;
         ++t;
         round_range(en, t, la, lb, off, -(t + 2), t + 3, RS, jc, nullptr, 0, -1, cnt);
@@ -358,21 +439,72 @@ __device__ __forceinline__ int32_t pair_in_workgroup(const Engine& en, LdsState&
         la = lb;
         lb = tmp;
     }
-    if (t > K || g0 == nullptr) return -3;
-    // global rows: diagonal i at g[i + K + 2]
-    int32_t* ga = g0;
-    int32_t* gb = g1;
-    for (int32_t e = tid; e < 2 * t + 5; e += nthr) ga[K + 2 + e - (t + 2)] = la[off + e - (t + 2)];
+    if (status == 0 || status == 5) {
+        // the frontier continues later: it goes to the global row
+        if (K < t || g == nullptr) {
+            status = 3;
+            result = t;
+        } else {
+            for (int32_t e = tid; e < 2 * t + 5; e += nthr) g[K + 2 + e - (t + 2)] = la[off + e - (t + 2)];
+        }
+    }
     __syncthreads();
-    for (;;) {
-        if (RS.flag) return t;
-        if (kmax >= 0 && t >= kmax) return kmax + 1;
-        if (t > maxnm || t >= K) return -3;
-        ++t;
-        round_range(en, t, ga, gb, K + 2, -(t + 2), t + 3, RS, jc, nullptr, 0, -1, cnt);
-        int32_t* tmp = ga;
-        ga = gb;
-        gb = tmp;
+    if (tid == 0) {
+        S->t = t;
+        if (status != 0)
+            pair_finish(P, S, status, result);
+        else
+            schedule_superstep(P, S, pi);
+    }
+}
+
+__device__ void chunk_task(const TaskParams& P, int32_t pi, int32_t c, LdsState& L, JobCursor& jc,
+                           CountersDev& cnt) {
+    TaskPair* S = P.pairs + pi;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const Engine en = make_engine(S->p, P.h, P.engine, P.lane_words, L.lut4);
+    RoundShared& RS = L.rs;
+    const int32_t t = S->t, H = S->H, T = S->T, C = S->chunk, K = S->K, cur = S->cur;
+    const int32_t gofs = K + 2;
+    const int32_t* gp = cur ? S->f1 : S->f0;
+    int32_t* gc = cur ? S->f0 : S->f1;
+    const int32_t total = 2 * T + 5;
+    const int32_t eb = c * C;
+    const int32_t ee = imin(total, eb + C);
+    const int32_t a = eb - (T + 2), b = ee - 1 - (T + 2);
+    const int32_t W = (ee - eb) + 2 * H;
+    const int32_t wofs = H - a;  // diagonal i of the window at row[i + wofs]
+    int32_t* r0 = L.row[0];
+    for (int32_t li = tid; li < W; li += nthr) {
+        const int32_t i = a - H + li;
+        r0[li] = (i >= -(t + 2) && i <= t + 2) ? gp[i + gofs] : kNone;
+    }
+    __syncthreads();
+    int32_t* rp = L.row[0];
+    int32_t* rc = L.row[1];
+    for (int32_t s = 1; s <= H; ++s) {
+        const int32_t tt = t + s;
+        if (round_range(en, tt, rp, rc, wofs, a - (H - s), b + (H - s) + 1, RS, jc, nullptr, 0, -1, cnt))
+            atomicMin(&S->found_t, tt);
+        int32_t* tmp = rp;
+        rp = rc;
+        rc = tmp;
+    }
+    for (int32_t i = a + tid; i <= b; i += nthr) gc[i + gofs] = rp[i + wofs];
+    __syncthreads();
+    if (tid == 0) {
+        const int32_t left = __hip_atomic_fetch_add(&S->chunks_left, -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (left == 1) {
+            // every chunk of the super-step is in: f_T is in row cur ^ 1
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            S->t = T;
+            S->cur = cur ^ 1;
+            const int32_t ft = __hip_atomic_load(&S->found_t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (ft <= T)
+                pair_finish(P, S, 1, ft);
+            else
+                schedule_superstep(P, S, pi);
+        }
     }
 }
 
@@ -555,7 +687,7 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
     flush_counters(cnt, P.counters);
 }
 
-__global__ __launch_bounds__(kFrontierThreads) void batch_kernel(BatchParams P) {
+__global__ __launch_bounds__(kFrontierThreads) void task_kernel(TaskParams P) {
     __shared__ LdsState L;
     const int tid = threadIdx.x;
     CountersDev cnt = {};
@@ -564,15 +696,16 @@ __global__ __launch_bounds__(kFrontierThreads) void batch_kernel(BatchParams P) 
     if (P.engine == 1) build_lut4(L.lut4, P.h.r, tid, blockDim.x);
     for (;;) {
         __syncthreads();
-        if (tid == 0) L.rs.pair = static_cast<int32_t>(atomicAdd(P.ticket, 1u));
+        if (tid == 0) L.rs.task = q_pop(P);
         __syncthreads();
-        const int32_t idx = L.rs.pair;
-        if (idx >= P.count) break;
-        const int32_t pi = P.order[idx];
-        const BatchItem item = P.items[pi];
-        const Engine en = make_engine(item.p, P.h, P.engine, P.lane_words, L.lut4);
-        const int32_t k = pair_in_workgroup(en, L, jc, P.lds_rounds, P.kmax, item.f0, item.f1, item.K, cnt);
-        if (tid == 0) P.k_out[pi] = k;
+        const long long task = L.rs.task;
+        if (task < 0) break;
+        const int32_t pi = static_cast<int32_t>(task & 0xFFFFFFFFll);
+        const uint32_t c = static_cast<uint32_t>(static_cast<unsigned long long>(task) >> 32);
+        if (c == kTaskSolo)
+            solo_task(P, pi, L, jc, cnt);
+        else
+            chunk_task(P, pi, static_cast<int32_t>(c - 1), L, jc, cnt);
     }
     flush_counters(cnt, P.counters);
 }
@@ -635,8 +768,20 @@ hipError_t launch_frontier(const FrontierParams& fp, int grid, hipStream_t s) {
                                       dim3(kFrontierThreads), args, 0, s);
 }
 
-hipError_t launch_batch(const BatchParams& bp, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(kFrontierThreads), 0, s, bp);
+hipError_t task_max_grid(int device, int* grid_out) {
+    int cus = 0, per = 0;
+    hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(task_kernel),
+                                                     kFrontierThreads, 0);
+    if (e != hipSuccess) return e;
+    if (per < 1) per = 1;
+    *grid_out = cus * per;
+    return hipSuccess;
+}
+
+hipError_t launch_tasks(const TaskParams& tp, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(task_kernel, dim3(grid), dim3(kFrontierThreads), 0, s, tp);
     return hipGetLastError();
 }
 

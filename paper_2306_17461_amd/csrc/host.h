@@ -34,6 +34,7 @@ constexpr size_t kMiscAlpha = 64;
 
 constexpr uint32_t kDefaultLdsRounds = 1024;
 constexpr uint32_t kDefaultBlockRounds = 32;
+constexpr int32_t kChunkDiags = 2048;  // diagonals per chunk task
 
 }  // namespace ed
 
@@ -43,6 +44,7 @@ struct ed_ctx {
     std::mutex mu;
     int num_cu = 0;
     int frontier_grid_max = 0;
+    int task_grid_max = 0;
     uint64_t r = 0;              // hash base of opt.hash_seed
     uint64_t* d_pow = nullptr;   // power tables (see kPowEntries)
     ed::FrontierCtl* d_ctl = nullptr;
@@ -90,4 +92,7 @@ int prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B, ui
                    int on_device, hipStream_t s, ed_pair** out);
 int distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, int32_t* rows,
                     uint64_t rows_cap, hipStream_t s);
+int tasks_run(ed_ctx* c, std::vector<TaskPair>& st, const std::vector<int32_t>& first, int64_t k_max,
+              uint32_t engine, hipStream_t s);
+int64_t batch_row_capacity(int64_t maxnm, int64_t k_max, uint32_t lds_rounds);
 }  // namespace ed

@@ -105,27 +105,48 @@ struct FrontierParams {
     CountersDev* counters;
 };
 
-// Batched launch: one descriptor per pair.
-struct BatchItem {
+// Work-stealing launch over (pair, diagonal-chunk) tasks (batch and serving).
+// State of one pair in device memory; it persists across launches.
+struct TaskPair {
     PairDev p;
-    int32_t* f0;       // global rows for rounds beyond the LDS phase (2K+5 each)
+    int32_t* f0;          // global rows, 2K+5 entries each, diagonal i at [i + K + 2]
     int32_t* f1;
-    int32_t K;
-    int32_t pad_;
+    int32_t K;            // rows support rounds t <= K (0: no rows)
+    int32_t t;            // rounds completed
+    int32_t cur;          // row holding f_t (0: f0, 1: f1)
+    int32_t status;       // 0 active, 1 done, 2 k_max reached, 3 out of rows, 4 error, 5 round budget used
+    int32_t result;       // k (status 1) or k_max + 1 (status 2)
+    int32_t t_limit;      // stop with status 5 when t reaches it (INT32_MAX: none)
+    int32_t H, T;         // current super-step: rounds t -> T = t + H
+    int32_t chunk;        // diagonals per chunk task
+    int32_t nchunks;
+    int32_t chunks_left;  // chunk tasks of the super-step not finished yet
+    int32_t found_t;      // smallest round reaching (n, m) in the super-step (INT32_MAX: none)
 };
 
-struct BatchParams {
-    const BatchItem* items;
-    const int32_t* order;   // processing order (largest first)
+// Task encoding (always >= 0; -1 means "no task"): pair index in the low 32
+// bits; the high 32 bits hold 0 for a whole-pair task, chunk index + 1 for a
+// chunk task.
+constexpr uint32_t kTaskSolo = 0u;
+
+struct TaskParams {
+    TaskPair* pairs;
     int32_t count;
-    int32_t kmax;
+    int32_t kmax;           // -1 = none
     int32_t engine;
     int32_t lane_words;
-    int32_t lds_rounds;
+    int32_t solo_rounds;    // a whole-pair task runs rounds up to this t (LDS rows)
+    int32_t block_rounds;   // rounds per chunk super-step (H)
+    int32_t chunk_diags;    // diagonals per chunk task
     int32_t pad_;
     HashDev h;
-    unsigned int* ticket;   // work queue head
-    int32_t* k_out;         // per pair: k, k_max + 1, or -3 (capacity, internal error)
+    unsigned long long* qseq;   // per slot: sequence number (slot full when = position + 1)
+    long long* qtask;           // per slot: task
+    unsigned long long* qhead;  // next position to pop
+    unsigned long long* qtail;  // next position to push
+    int32_t* remaining;         // pairs still active in this launch
+    uint32_t qcap;
+    uint32_t pad2_;
     CountersDev* counters;
 };
 
@@ -174,7 +195,8 @@ hipError_t launch_copy8_rest(const PrepParams& pp, hipStream_t s);
 hipError_t launch_ctl_init(FrontierCtl* ctl, CountersDev* cnt, unsigned int* bar, hipStream_t s);
 hipError_t launch_frontier(const FrontierParams& fp, int grid, hipStream_t s);
 hipError_t frontier_max_grid(int device, int* grid_out);
-hipError_t launch_batch(const BatchParams& bp, int grid, hipStream_t s);
+hipError_t launch_tasks(const TaskParams& tp, int grid, hipStream_t s);
+hipError_t task_max_grid(int device, int* grid_out);
 hipError_t launch_lcp_queries(const LcpQueryParams& qp, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t s);

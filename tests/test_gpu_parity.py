@@ -316,6 +316,13 @@ def test_batch_matches_oracle_and_single(ed, make_ctx, orc, engine):
         A, B, _ = synth.single_pair(n, k, ps)
         pairs.append(ed.ed_prepare(ctx, A, B))
         want.append(orc.lv_omp(A, B))
+    # unrelated strings: the distance outgrows the rows a batch reserves
+    d4 = synth.CharDist("uniform", 4)
+    for seed in (1, 2):
+        A = synth.random_string(12000, d4, 100 + seed)
+        B = synth.random_string(11000, d4, 200 + seed)
+        pairs.append(ed.ed_prepare(ctx, A, B))
+        want.append(orc.lv_omp(A, B))
     say("batch", engine, len(pairs))
     got, st = ed.ed_batch(ctx, pairs)
     assert st == [0] * len(pairs)
@@ -328,6 +335,13 @@ def test_batch_matches_oracle_and_single(ed, make_ctx, orc, engine):
     ed.ed_set_options(ctx, engine=engine, lds_rounds=16, flags=4, hash_seed=0x5EED)
     got3, _ = ed.ed_batch(ctx, pairs)
     assert got3 == want
+    # one-workgroup grid, tiny chunks of rounds: many super-steps per pair
+    ed.ed_set_options(ctx, engine=engine, lds_rounds=8, block_rounds=3, grid_blocks=1, hash_seed=0x5EED)
+    got4, _ = ed.ed_batch(ctx, pairs[:60] + pairs[-2:])
+    assert got4 == want[:60] + want[-2:]
+    # k_max cutoff inside the batch
+    got5, _ = ed.ed_batch(ctx, pairs, k_max=50)
+    assert got5 == [min(w, 51) for w in want]
     for p in pairs:
         ed.ed_release(p)
 
