@@ -43,14 +43,47 @@ struct TaskLaunch {
     uint32_t qcap = 0;
 };
 
-int tasks_run(ed_ctx* c, std::vector<TaskPair>& st, const std::vector<int32_t>& first, int64_t k_max,
+long long task_solo(int32_t pi) { return static_cast<long long>(static_cast<uint32_t>(pi)); }
+long long task_chunk(int32_t pi, int32_t c) {
+    return static_cast<long long>(static_cast<uint32_t>(pi)) | (static_cast<long long>(c + 1) << 32);
+}
+
+int32_t block_rounds_of(const ed_ctx* c) {
+    return static_cast<int32_t>(c->opt.block_rounds ? c->opt.block_rounds : kDefaultBlockRounds);
+}
+
+// Host-side twin of the device scheduler: the next super-step of a pair whose
+// frontier f_t is in its rows.  Appends the chunk tasks; returns false when no
+// round can be taken (rows full, k_max or the round budget reached).
+bool schedule_on_host(TaskPair& tp, int32_t pi, int32_t block_rounds, int64_t k_max,
+                      std::vector<long long>& tasks) {
+    const int32_t t = tp.t;
+    int64_t H = std::min<int64_t>(block_rounds, static_cast<int64_t>(tp.K) - t);
+    H = std::min<int64_t>(H, (kLdsRowLen - kChunkDiags) / 2);
+    if (k_max >= 0) H = std::min<int64_t>(H, k_max - t);
+    H = std::min<int64_t>(H, static_cast<int64_t>(tp.t_limit) - t);
+    if (H <= 0) return false;
+    const int32_t T = t + static_cast<int32_t>(H);
+    const int32_t total = 2 * T + 5;
+    const int32_t nch = (total + kChunkDiags - 1) / kChunkDiags;
+    tp.H = static_cast<int32_t>(H);
+    tp.T = T;
+    tp.chunk = kChunkDiags;
+    tp.nchunks = nch;
+    tp.chunks_left = nch;
+    tp.found_t = INT32_MAX;
+    for (int32_t c = 0; c < nch; ++c) tasks.push_back(task_chunk(pi, c));
+    return true;
+}
+
+int tasks_run(ed_ctx* c, std::vector<TaskPair>& st, const std::vector<long long>& first, int64_t k_max,
               uint32_t engine, hipStream_t s) {
     const uint64_t count = st.size();
     const uint32_t solo = c->opt.lds_rounds ? c->opt.lds_rounds : kDefaultLdsRounds;
     const int32_t C = kChunkDiags;
     // every task that can be in flight at once: one per pair, plus one
     // super-step of chunks per pair with rows, plus slack for the workgroups
-    uint64_t qcap = count + 256;
+    uint64_t qcap = count + first.size() + 256;
     for (const TaskPair& tp : st)
         if (tp.K > 0) qcap += (2ull * tp.K + 5 + C - 1) / C;
     const size_t pairs_bytes = count * sizeof(TaskPair);
@@ -76,7 +109,7 @@ int tasks_run(ed_ctx* c, std::vector<TaskPair>& st, const std::vector<int32_t>& 
     tp.engine = static_cast<int32_t>(engine);
     tp.lane_words = static_cast<int32_t>(c->opt.lane_words ? c->opt.lane_words : 2u);
     tp.solo_rounds = static_cast<int32_t>(solo);
-    tp.block_rounds = static_cast<int32_t>(c->opt.block_rounds ? c->opt.block_rounds : kDefaultBlockRounds);
+    tp.block_rounds = block_rounds_of(c);
     tp.chunk_diags = C;
     tp.h = ctx_hash(c);
     tp.counters = c->d_cnt;
@@ -86,11 +119,11 @@ int tasks_run(ed_ctx* c, std::vector<TaskPair>& st, const std::vector<int32_t>& 
     for (uint64_t q = 0; q < qcap; ++q) seq[q] = q;
     for (size_t q = 0; q < first.size(); ++q) {
         seq[q] = q + 1;
-        task[q] = static_cast<long long>(static_cast<uint32_t>(first[q])) |
-                  (static_cast<long long>(kTaskSolo) << 32);
+        task[q] = first[q];
     }
     unsigned long long ctr[2] = {0ull, static_cast<unsigned long long>(first.size())};
-    int32_t remaining = static_cast<int32_t>(first.size());
+    int32_t remaining = 0;
+    for (const TaskPair& tp : st) remaining += tp.status == 0 ? 1 : 0;
     int grid = c->opt.grid_blocks ? static_cast<int>(c->opt.grid_blocks) : c->task_grid_max;
     grid = std::max(1, grid);
     hipError_t e = hipMemcpyAsync(tp.pairs, st.data(), pairs_bytes, hipMemcpyHostToDevice, s);
@@ -174,7 +207,10 @@ int batch_locked(ed_ctx* c, ed_pair* const* pairs, uint64_t count, int64_t k_max
         tp.t_limit = INT32_MAX;
         tp.found_t = INT32_MAX;
     }
-    int rc = tasks_run(c, st, order, k_max, engine, s);
+    std::vector<long long> tasks0;
+    tasks0.reserve(count);
+    for (int32_t pi : order) tasks0.push_back(task_solo(pi));
+    int rc = tasks_run(c, st, tasks0, k_max, engine, s);
     c->pool.put(rows_blk);
     if (rc != ED_OK) return rc;
     int first = ED_OK;

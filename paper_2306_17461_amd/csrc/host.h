@@ -92,7 +92,12 @@ int prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B, ui
                    int on_device, hipStream_t s, ed_pair** out);
 int distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, int32_t* rows,
                     uint64_t rows_cap, hipStream_t s);
-int tasks_run(ed_ctx* c, std::vector<TaskPair>& st, const std::vector<int32_t>& first, int64_t k_max,
+int tasks_run(ed_ctx* c, std::vector<TaskPair>& st, const std::vector<long long>& first, int64_t k_max,
               uint32_t engine, hipStream_t s);
+long long task_solo(int32_t pi);
+long long task_chunk(int32_t pi, int32_t c);
+int32_t block_rounds_of(const ed_ctx* c);
+bool schedule_on_host(TaskPair& tp, int32_t pi, int32_t block_rounds, int64_t k_max,
+                      std::vector<long long>& tasks);
 int64_t batch_row_capacity(int64_t maxnm, int64_t k_max, uint32_t lds_rounds);
 }  // namespace ed

@@ -1,20 +1,371 @@
-// Serving entry points (request loop with continuous batching).
+// Serving: a request loop with continuous batching.
+//
+// Submitted requests wait in a host queue.  A worker thread repeats one step:
+//   1. admission: while a slot is free and the request's device bytes (packed
+//      strings, 8-bit copies, tables, staging and frontier rows) fit in the
+//      HBM budget, the request is prepared on the server's stream and gets a
+//      slot; its strings and tables stay resident until it finishes;
+//   2. one launch of the work-stealing task kernel advances every active slot
+//      by at most kServeRounds rounds (whole-pair tasks in LDS, chunked
+//      super-steps for wide frontiers); a slot's frontier is saved in its
+//      rows when its round budget is used up;
+//   3. finished slots are recorded with their completion time and freed.
+// Requests that arrive while others run join at the next step, so work of
+// different requests shares every launch.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <vector>
+
 #include "../../include/ed.h"
 #include "host.h"
+#include "internal.h"
 
-struct ed_server {
-    ed_ctx* ctx;
+using namespace ed;
+
+namespace {
+
+constexpr int32_t kServeRounds = 256;   // rounds per slot per launch
+constexpr size_t kServeQueueMax = 1u << 20;
+
+uint64_t now_ns() {
+    return static_cast<uint64_t>(std::chrono::duration_cast<std::chrono::nanoseconds>(
+                                     std::chrono::steady_clock::now().time_since_epoch())
+                                     .count());
+}
+
+struct Request {
+    uint64_t tag;
+    std::vector<uint8_t> A, B;
+    uint64_t t_arrive;
 };
 
-int ed_serve_open(ed_ctx*, uint64_t, uint32_t, ed_server** out) {
-    if (out) *out = nullptr;
-    ed::set_error("ed_serve_open: not available in this build");
-    return ED_EINVAL;
+struct Slot {
+    ed_pair* pair = nullptr;
+    uint64_t tag = 0;
+    uint64_t t_arrive = 0;
+    TaskPair st{};
+    void* rows = nullptr;
+    int64_t K = 0;
+    uint64_t bytes = 0;
+};
+
+}  // namespace
+
+struct ed_server {
+    ed_ctx* ctx = nullptr;
+    uint64_t budget = 0;
+    uint32_t max_slots = 0;
+    std::mutex mu;
+    std::condition_variable cv_work;  // new request or stop
+    std::condition_variable cv_done;  // a request finished
+    std::deque<Request> pending;
+    std::vector<ed_result> done;
+    uint64_t submitted = 0, completed = 0;
+    bool stop = false;
+    int error = ED_OK;
+    std::thread worker;
+    hipStream_t stream = nullptr;
+    uint64_t used = 0;
+    std::vector<Slot> slots;
+};
+
+namespace {
+
+uint64_t pool_bytes(uint64_t b) { return b + (b >> 3) + 4096; }  // size-class slack
+
+// Device bytes a request holds while resident.
+uint64_t request_bytes(const ed_ctx* c, uint64_t n, uint64_t m, int64_t K) {
+    uint64_t total = 0;
+    const uint32_t b = c->opt.block ? c->opt.block : 32;
+    for (uint64_t len : {n, m}) {
+        const uint64_t tiles = std::max<uint64_t>(1, (len + kTileChars - 1) / kTileChars);
+        total += pool_bytes((tiles * kTileWords2 + kPadWords) * 8);
+        total += pool_bytes((tiles * kTileWords8 + kPadWords) * 8);
+        total += pool_bytes(len + 16);  // staging copy of the host input
+        if (c->opt.engine == ED_ENGINE_HASH) total += pool_bytes((len / b + 1) * 8);
+    }
+    total += pool_bytes(static_cast<uint64_t>(2 * (2 * K + 5)) * 4);
+    return total;
 }
-int ed_serve_submit(ed_server*, const uint8_t*, uint64_t, const uint8_t*, uint64_t, uint64_t) { return ED_EINVAL; }
-int ed_serve_poll(ed_server*, ed_result*, uint32_t, uint32_t* got) {
-    if (got) *got = 0;
-    return ED_EINVAL;
+
+int64_t serve_rows(const ed_ctx* c, int64_t maxnm) {
+    const int64_t solo = c->opt.lds_rounds ? c->opt.lds_rounds : kDefaultLdsRounds;
+    // every slot can save its frontier at any round up to the whole-pair limit
+    int64_t K = std::max<int64_t>(std::min<int64_t>(maxnm, 2 * solo), maxnm / 16);
+    return std::max<int64_t>(1, std::min<int64_t>(K, maxnm));
 }
-int ed_serve_drain(ed_server*) { return ED_EINVAL; }
-int ed_serve_close(ed_server*) { return ED_EINVAL; }
+
+void slot_free(ed_server* S, Slot& sl) {
+    ed_ctx* c = S->ctx;
+    if (sl.pair) {
+        pair_free(sl.pair);
+        delete sl.pair;
+    }
+    c->pool.put(sl.rows);
+    S->used -= sl.bytes;
+    sl = Slot();
+}
+
+// Grows the rows of a slot whose frontier reached their capacity.
+int slot_grow(ed_server* S, Slot& sl) {
+    ed_ctx* c = S->ctx;
+    const int64_t maxnm = std::max<int64_t>(sl.st.p.a.len, sl.st.p.b.len);
+    const int64_t t = sl.st.t;
+    const int64_t K2 = std::min<int64_t>(maxnm, std::max<int64_t>(2 * sl.K, t + kServeRounds + 1));
+    if (K2 <= sl.K) return ED_EINTERNAL;
+    void* nr = c->pool.get(static_cast<size_t>(2 * (2 * K2 + 5)) * 4);
+    if (!nr) return ED_ENOMEM;
+    int32_t* old = sl.st.cur ? sl.st.f1 : sl.st.f0;
+    int32_t* nf0 = static_cast<int32_t*>(nr);
+    hipError_t e = hipMemcpyAsync(nf0 + (K2 + 2) - (t + 2), old + (sl.K + 2) - (t + 2),
+                                  static_cast<size_t>(2 * t + 5) * 4, hipMemcpyDeviceToDevice, S->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
+    if (e != hipSuccess) {
+        c->pool.put(nr);
+        return ED_EDEVICE;
+    }
+    c->pool.put(sl.rows);
+    S->used += static_cast<uint64_t>(4 * 2 * (2 * (K2 - sl.K)));
+    sl.bytes += static_cast<uint64_t>(4 * 2 * (2 * (K2 - sl.K)));
+    sl.rows = nr;
+    sl.K = K2;
+    sl.st.K = static_cast<int32_t>(K2);
+    sl.st.f0 = nf0;
+    sl.st.f1 = nf0 + (2 * K2 + 5);
+    sl.st.cur = 0;
+    return ED_OK;
+}
+
+void finish_slot(ed_server* S, Slot& sl, uint64_t k, int32_t status) {
+    ed_result r;
+    std::memset(&r, 0, sizeof r);
+    r.tag = sl.tag;
+    r.k = k;
+    r.status = status;
+    r.t_arrive_ns = sl.t_arrive;
+    r.t_done_ns = now_ns();
+    slot_free(S, sl);
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->done.push_back(r);
+    S->completed++;
+    S->cv_done.notify_all();
+}
+
+// One admission + launch + collection step.  Called with ctx->mu held.
+int serve_step(ed_server* S, std::vector<Request>& admitted_now) {
+    ed_ctx* c = S->ctx;
+    // admission
+    for (Request& rq : admitted_now) {
+        Slot sl;
+        const int64_t maxnm = static_cast<int64_t>(std::max(rq.A.size(), rq.B.size()));
+        sl.K = serve_rows(c, maxnm);
+        sl.bytes = request_bytes(c, rq.A.size(), rq.B.size(), sl.K);
+        sl.tag = rq.tag;
+        sl.t_arrive = rq.t_arrive;
+        int rc = prepare_locked(c, rq.A.data(), rq.A.size(), rq.B.data(), rq.B.size(), 0, S->stream, &sl.pair);
+        if (rc == ED_OK) {
+            sl.rows = c->pool.get(static_cast<size_t>(2 * (2 * sl.K + 5)) * 4);
+            if (!sl.rows) rc = ED_ENOMEM;
+        }
+        S->used += sl.bytes;
+        if (rc != ED_OK) {
+            finish_slot(S, sl, 0, rc);
+            continue;
+        }
+        std::memset(&sl.st, 0, sizeof sl.st);
+        sl.st.p = pair_dev(sl.pair);
+        sl.st.K = static_cast<int32_t>(sl.K);
+        sl.st.f0 = static_cast<int32_t*>(sl.rows);
+        sl.st.f1 = sl.st.f0 + (2 * sl.K + 5);
+        sl.st.found_t = INT32_MAX;
+        S->slots.push_back(sl);
+    }
+    if (S->slots.empty()) return ED_OK;
+    // one launch over every active slot
+    const int32_t solo = static_cast<int32_t>(c->opt.lds_rounds ? c->opt.lds_rounds : kDefaultLdsRounds);
+    const int32_t br = block_rounds_of(c);
+    std::vector<TaskPair> st;
+    std::vector<long long> tasks;
+    std::vector<size_t> idx;
+    for (size_t j = 0; j < S->slots.size(); ++j) {
+        Slot& sl = S->slots[j];
+        if (sl.st.t >= sl.st.K && sl.st.t > solo) {
+            int rc = slot_grow(S, sl);
+            if (rc != ED_OK) {
+                sl.st.status = 4;
+                continue;
+            }
+        }
+        TaskPair tp = sl.st;
+        tp.status = 0;
+        tp.t_limit = tp.t + kServeRounds;
+        const int32_t pi = static_cast<int32_t>(st.size());
+        if (tp.t <= solo && tp.t <= kLdsRoundsMax) {
+            tasks.push_back(task_solo(pi));
+        } else if (!schedule_on_host(tp, pi, br, -1, tasks)) {
+            sl.st.status = 4;
+            continue;
+        }
+        st.push_back(tp);
+        idx.push_back(j);
+    }
+    if (!st.empty()) {
+        int rc = tasks_run(c, st, tasks, -1, c->opt.engine, S->stream);
+        if (rc != ED_OK) return rc;
+        for (size_t q = 0; q < st.size(); ++q) S->slots[idx[q]].st = st[q];
+    }
+    // collection
+    std::vector<Slot> keep;
+    keep.reserve(S->slots.size());
+    for (Slot& sl : S->slots) {
+        const int32_t status = sl.st.status;
+        if (status == 1) {
+            sl.pair->rounds = static_cast<uint64_t>(sl.st.result);
+            finish_slot(S, sl, static_cast<uint64_t>(sl.st.result), ED_OK);
+        } else if (status == 4) {
+            finish_slot(S, sl, 0, ED_EINTERNAL);
+        } else {
+            // round budget used (5) or rows full (3): continue next step
+            sl.st.status = 0;
+            keep.push_back(sl);
+        }
+    }
+    S->slots.swap(keep);
+    return ED_OK;
+}
+
+void serve_worker(ed_server* S) {
+    ed_ctx* c = S->ctx;
+    (void)hipSetDevice(c->device);
+    for (;;) {
+        std::vector<Request> adm;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            S->cv_work.wait(lk, [&] { return S->stop || !S->pending.empty() || !S->slots.empty(); });
+            if (S->stop && S->slots.empty() && S->pending.empty()) return;
+            // admit by free slots and the HBM budget, in arrival order
+            uint64_t used = S->used;
+            size_t active = S->slots.size();
+            while (!S->pending.empty() && active < S->max_slots) {
+                Request& rq = S->pending.front();
+                const int64_t maxnm = static_cast<int64_t>(std::max(rq.A.size(), rq.B.size()));
+                const uint64_t need = request_bytes(c, rq.A.size(), rq.B.size(), serve_rows(c, maxnm));
+                if (used + need > S->budget) break;
+                used += need;
+                adm.push_back(std::move(rq));
+                S->pending.pop_front();
+                ++active;
+            }
+        }
+        int rc;
+        {
+            std::lock_guard<std::mutex> lk(c->mu);
+            rc = serve_step(S, adm);
+        }
+        if (rc != ED_OK) {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->error = rc;
+            S->stop = true;
+            // fail everything left
+            for (Request& rq : S->pending) {
+                ed_result r;
+                std::memset(&r, 0, sizeof r);
+                r.tag = rq.tag;
+                r.status = rc;
+                r.t_arrive_ns = rq.t_arrive;
+                r.t_done_ns = now_ns();
+                S->done.push_back(r);
+                S->completed++;
+            }
+            S->pending.clear();
+            S->cv_done.notify_all();
+            return;
+        }
+    }
+}
+
+}  // namespace
+
+int ed_serve_open(ed_ctx* c, uint64_t hbm_budget_bytes, uint32_t max_slots, ed_server** out) {
+    if (!c || !out || max_slots == 0 || hbm_budget_bytes == 0) return ED_EINVAL;
+    *out = nullptr;
+    ed_server* S = new (std::nothrow) ed_server();
+    if (!S) return ED_ENOMEM;
+    S->ctx = c;
+    S->budget = hbm_budget_bytes;
+    S->max_slots = max_slots;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        if (hipSetDevice(c->device) != hipSuccess || hipStreamCreate(&S->stream) != hipSuccess) {
+            delete S;
+            set_error("ed_serve_open: hipStreamCreate failed");
+            return ED_EDEVICE;
+        }
+    }
+    S->worker = std::thread(serve_worker, S);
+    *out = S;
+    return ED_OK;
+}
+
+int ed_serve_submit(ed_server* S, const uint8_t* A, uint64_t n, const uint8_t* B, uint64_t m, uint64_t tag) {
+    if (!S || (n && !A) || (m && !B) || n >= ED_MAX_LEN || m >= ED_MAX_LEN) return ED_EINVAL;
+    const int64_t maxnm = static_cast<int64_t>(std::max(n, m));
+    if (request_bytes(S->ctx, n, m, serve_rows(S->ctx, maxnm)) > S->budget) {
+        set_error("ed_serve_submit: request needs more than the HBM budget");
+        return ED_ENOMEM;
+    }
+    Request rq;
+    rq.tag = tag;
+    rq.A.assign(A, A + n);
+    rq.B.assign(B, B + m);
+    rq.t_arrive = now_ns();
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) return S->error != ED_OK ? S->error : ED_EINVAL;
+    if (S->pending.size() >= kServeQueueMax) return ED_EBUSY;
+    S->pending.push_back(std::move(rq));
+    S->submitted++;
+    S->cv_work.notify_one();
+    return ED_OK;
+}
+
+int ed_serve_poll(ed_server* S, ed_result* out, uint32_t max, uint32_t* got) {
+    if (!S || !got || (max && !out)) return ED_EINVAL;
+    std::lock_guard<std::mutex> lk(S->mu);
+    const uint32_t k = static_cast<uint32_t>(std::min<size_t>(max, S->done.size()));
+    for (uint32_t i = 0; i < k; ++i) out[i] = S->done[i];
+    S->done.erase(S->done.begin(), S->done.begin() + k);
+    *got = k;
+    return ED_OK;
+}
+
+int ed_serve_drain(ed_server* S) {
+    if (!S) return ED_EINVAL;
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->cv_done.wait(lk, [&] { return S->completed >= S->submitted || S->stop; });
+    return S->error;
+}
+
+int ed_serve_close(ed_server* S) {
+    if (!S) return ED_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+        S->pending.clear();
+        S->cv_work.notify_all();
+    }
+    if (S->worker.joinable()) S->worker.join();
+    {
+        std::lock_guard<std::mutex> lk(S->ctx->mu);
+        for (Slot& sl : S->slots) slot_free(S, sl);
+        S->slots.clear();
+        if (S->stream) (void)hipStreamDestroy(S->stream);
+    }
+    const int err = S->error;
+    delete S;
+    return err;
+}

@@ -359,3 +359,61 @@ def test_device_inputs_and_unaligned(ed, make_ctx, orc):
     tA2 = torch.zeros(len(A) + 3, dtype=torch.uint8, device="cuda")
     tA2[3:] = tA
     assert gpu_ed(ed, ctx, tA2[3:], tB) == want
+
+
+# ---------------------------------------------------------------------------
+# serving: continuous batching under an HBM budget
+# ---------------------------------------------------------------------------
+def _serve_all(ed, ctx, reqs, budget, slots, gap_s=0.0):
+    import time
+    srv = ed.ed_serve_open(ctx, budget, slots)
+    for tag, (A, B) in enumerate(reqs):
+        rc = ed.ed_serve_submit(srv, A, B, tag)
+        assert rc == 0, ed.ed_last_error()
+        if gap_s:
+            time.sleep(gap_s)
+    ed.ed_serve_drain(srv)
+    res = ed.ed_serve_poll(srv, len(reqs) + 10)
+    ed.ed_serve_close(srv)
+    return res
+
+
+@pytest.mark.parametrize("engine", [0, 1])
+def test_serve_matches_oracle_and_alone(ed, make_ctx, orc, engine):
+    ctx = make_ctx(engine=engine)
+    trace = synth.arrival_trace(120, 3, rate_per_s=1e4, lo_exp=1.0, hi_exp=4.6, kfrac=0.05)
+    reqs = [synth.request_pair(r) for r in trace]
+    want = [orc.lv_omp(A, B) for A, B in reqs]
+    say("serve", engine, len(reqs))
+    res = _serve_all(ed, ctx, reqs, 8 << 30, 64)
+    assert sorted(r["tag"] for r in res) == list(range(len(reqs)))
+    got = {r["tag"]: r["k"] for r in res}
+    assert all(r["status"] == 0 for r in res)
+    assert [got[i] for i in range(len(reqs))] == want
+    assert all(r["t_done_ns"] >= r["t_arrive_ns"] for r in res)
+    # the same requests alone (one slot at a time) give the same answers
+    alone = _serve_all(ed, ctx, reqs[:25], 8 << 30, 1)
+    got1 = {r["tag"]: r["k"] for r in alone}
+    assert [got1[i] for i in range(25)] == want[:25]
+
+
+def test_serve_tiny_budget_and_growth(ed, make_ctx, orc):
+    # a budget that fits about one request at a time still completes them all,
+    # and a slow-converging pair outgrows its rows and keeps going
+    ctx = make_ctx(lds_rounds=64, block_rounds=8)
+    d4 = synth.CharDist("uniform", 4)
+    reqs = []
+    for s in range(6):
+        A, B, _ = synth.single_pair(20000, 300 + 50 * s, 40 + s)
+        reqs.append((A, B))
+    reqs.append((synth.random_string(9000, d4, 77), synth.random_string(8000, d4, 78)))
+    want = [orc.lv_omp(A, B) for A, B in reqs]
+    say("serve tiny budget")
+    res = _serve_all(ed, ctx, reqs, 400 << 10, 8)
+    got = {r["tag"]: r["k"] for r in res}
+    assert [got[i] for i in range(len(reqs))] == want
+    assert all(r["status"] == 0 for r in res)
+    srv = ed.ed_serve_open(ctx, 1 << 10, 4)
+    A, B = reqs[0]
+    assert ed.ed_serve_submit(srv, A, B, 0) == ed.ED_ENOMEM
+    ed.ed_serve_close(srv)
