@@ -47,6 +47,108 @@ def measured_traffic(kernel, engine, ks, n):
     return rec["per_launch_bytes"].get(kernel)
 
 
+def batch_leg(ed, ctx, count=4096, seed=0):
+    """Batched workload: `count` pairs, n = floor(10^U) with U ~ U[3, 6], alphabet
+    {0,1,2,3}, k ~ U{0..floor(0.01 n)} planted edits.  One ed_batch launch against
+    a loop of one ed_distance launch per pair, on the same prepared pairs."""
+    import synth
+    log("batch leg: generating %d pairs" % count)
+    specs = synth.batch_specs(count, seed)
+    pairs = []
+    chars = 0
+    for n, k, ps in specs:
+        A, B, _ = synth.single_pair(n, k, ps)
+        pairs.append(ed.ed_prepare(ctx, A, B))
+        chars += len(A)
+    ed.ed_batch(ctx, pairs)  # warm-up
+    t0 = time.perf_counter()
+    kb, _ = ed.ed_batch(ctx, pairs)
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    kp = [ed.ed_distance(ctx, p) for p in pairs]
+    tp = time.perf_counter() - t0
+    if kb != kp:
+        raise SystemExit("batch and per-pair distances differ")
+    for p in pairs:
+        ed.ed_release(p)
+    return {"workload": "%d pairs, n log-uniform [1e3, 1e6], alphabet {0,1,2,3}, k uniform "
+                        "[0, 0.01 n], seed %d" % (count, seed),
+            "pairs": count, "chars_A": chars, "sum_k": int(sum(kb)),
+            "batched_pairs_per_s": count / tb, "batched_s": tb,
+            "per_pair_pairs_per_s": count / tp, "per_pair_s": tp,
+            "speedup": tp / tb}
+
+
+def serve_leg(ed, ctx, count, seed=0, warmup=0):
+    """Served workload: Poisson arrivals, n = floor(10^U), U ~ U[2, 7], alphabet 4
+    or 20, k ~ U{0..floor(0.05 n)}.  The arrival rate is 0.7x the batched
+    throughput measured on the same requests.  Latency = completion - arrival."""
+    import threading
+    import numpy as np
+    import synth
+    log("serve leg: generating %d requests" % count)
+    trace = synth.arrival_trace(count, seed, rate_per_s=1.0)
+    reqs = [synth.request_pair(r) for r in trace]
+    gaps = np.diff([0.0] + [r["t_arrive_s"] for r in trace])
+    pairs = [ed.ed_prepare(ctx, A, B) for A, B in reqs]
+    t0 = time.perf_counter()
+    want, _ = ed.ed_batch(ctx, pairs)
+    tb = time.perf_counter() - t0
+    for p in pairs:
+        ed.ed_release(p)
+    rate = 0.7 * count / tb
+    arrive = np.cumsum(gaps / rate)
+    log("serve leg: batched %.1f pairs/s -> arrival rate %.1f /s" % (count / tb, rate))
+
+    def pct(lat):
+        lat = np.sort(np.asarray(lat))
+        return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+
+    # served: a submitter thread follows the trace, the server batches
+    srv = ed.ed_serve_open(ctx, 64 << 30, 256)
+    start = time.perf_counter()
+
+    def submit():
+        for i, (A, B) in enumerate(reqs):
+            d = start + arrive[i] - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            ed.ed_serve_submit(srv, A, B, i)
+
+    th = threading.Thread(target=submit)
+    th.start()
+    th.join()
+    ed.ed_serve_drain(srv)
+    res = ed.ed_serve_poll(srv, count + 1)
+    ed.ed_serve_close(srv)
+    got = {r["tag"]: r["k"] for r in res}
+    if [got[i] for i in range(count)] != list(want):
+        raise SystemExit("served distances differ from the batch")
+    lat = [(r["t_done_ns"] - r["t_arrive_ns"]) / 1e9 for r in res]
+    span = (max(r["t_done_ns"] for r in res) - min(r["t_arrive_ns"] for r in res)) / 1e9
+    p50, p99 = pct(lat)
+    # per-pair form on the same trace: one request at a time, in arrival order
+    start = time.perf_counter()
+    lat2 = []
+    for i, (A, B) in enumerate(reqs):
+        d = start + arrive[i] - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        p = ed.ed_prepare(ctx, A, B)
+        k = ed.ed_distance(ctx, p)
+        ed.ed_release(p)
+        if k != want[i]:
+            raise SystemExit("per-pair distance differs")
+        lat2.append(time.perf_counter() - (start + arrive[i]))
+    span2 = time.perf_counter() - start
+    q50, q99 = pct(lat2)
+    return {"workload": "%d requests, Poisson arrivals, n log-uniform [1e2, 1e7], alphabet 4 or 20, "
+                        "k uniform [0, 0.05 n], seed %d" % (count, seed),
+            "arrival_rate_per_s": rate, "batched_pairs_per_s": count / tb,
+            "served": {"pairs_per_s": count / span, "p50_s": p50, "p99_s": p99},
+            "per_pair": {"pairs_per_s": count / span2, "p50_s": q50, "p99_s": q99}}
+
+
 def pair_stats(ed, pair):
     return ed.ed_pair_stats(pair)
 
@@ -69,6 +171,9 @@ def main():
     ap.add_argument("--n", type=int, default=N)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-other-engine", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 4096-pair batch leg")
+    ap.add_argument("--serve", type=int, default=0, metavar="N",
+                    help="also run the serving leg with N requests")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -192,6 +297,13 @@ def main():
             if k != last[i][0]:
                 raise SystemExit("engines disagree at k=%d: %d vs %d" % (ks[i], k, last[i][0]))
 
+    batch = None
+    if not args.no_batch:
+        batch = batch_leg(ed, ctxs["direct"])
+    serve = None
+    if args.serve > 0:
+        serve = serve_leg(ed, ctxs["direct"], args.serve)
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -211,7 +323,7 @@ def main():
         ed.ed_shutdown(c)
 
     line = {
-        "metric": "chars/sec at n=1e8, k=1e2..1e5 (exact)",
+        "metric": "chars/sec at n=1e8, k=1e2..1e5 (exact); batched pairs/sec + p50/p99 latency",
         "value": value, "unit": "chars/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u8", "data": "synthetic",
@@ -222,6 +334,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "other_engine": other,
+        "batch": batch,
+        "serve": serve,
     }
     print(json.dumps(line))
 
