@@ -27,6 +27,8 @@ open, this module reads them as follows:
   * the edits are applied in one left-to-right pass, so m = n + #ins - #del.
 """
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -91,10 +93,38 @@ def zipf_cdf(nsym=256, s=1.0):
     return np.cumsum(w) / w.sum()
 
 
-def _zipf_from(v, cdf):
+def _zipf_guide(cdf):
+    """Guide table (Chen and Asau): g[j] = #{cdf <= j / 2^16}, plus the cdf with a sentinel."""
+    g = np.searchsorted(cdf, np.arange(1 << 16, dtype=np.float64) / 65536.0, side="right")
+    return g.astype(np.int64), np.append(cdf, np.inf)
+
+
+def _zipf_from(v, cdf, guide=None):
+    """Symbol = #{cdf <= u} (clamped to the last symbol), u = top 53 bits of v.
+
+    The guide table starts the count at the bucket of u's top 16 bits (which are
+    the top 16 bits of v); a short forward scan finishes it.  The result equals
+    searchsorted(cdf, u, side="right") exactly.
+    """
     u = _unit_float(v)
-    idx = np.searchsorted(cdf, u, side="right")
+    if guide is None:
+        guide = _zipf_guide(cdf)
+    g, ext = guide
+    idx = g[(v >> np.uint64(48)).astype(np.int64)]
+    while True:
+        adv = ext[idx] <= u
+        if not adv.any():
+            break
+        idx += adv
     return np.minimum(idx, len(cdf) - 1).astype(np.uint8)
+
+
+def _threads():
+    try:
+        n = int(os.environ.get("OMP_NUM_THREADS", "0"))
+    except ValueError:
+        n = 0
+    return max(1, min(16, n or os.cpu_count() or 1))
 
 
 class CharDist:
@@ -105,17 +135,28 @@ class CharDist:
         self.sigma = sigma
         self.s = s
         self._cdf = zipf_cdf(sigma, s) if kind == "zipf" else None
+        self._guide = _zipf_guide(self._cdf) if kind == "zipf" else None
 
     def from_draws(self, v):
         if self.kind == "uniform":
             return _uniform_from(v, self.sigma)
-        return _zipf_from(v, self._cdf)
+        return _zipf_from(v, self._cdf, self._guide)
 
     def sample(self, seed, stream, count, start=0):
         out = np.empty(count, dtype=np.uint8)
-        for a in range(0, count, _CHUNK):
+
+        def fill(a):
             b = min(count, a + _CHUNK)
             out[a:b] = self.from_draws(draws(seed, stream, b - a, start + a))
+
+        starts = range(0, count, _CHUNK)
+        if count > 2 * _CHUNK and _threads() > 1:
+            # chunks are independent (counter-based draws); numpy releases the GIL
+            with ThreadPoolExecutor(_threads()) as ex:
+                list(ex.map(fill, starts))
+        else:
+            for a in starts:
+                fill(a)
         return out
 
 

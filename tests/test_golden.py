@@ -1,0 +1,83 @@
+"""The stored full-size oracle values and the input generators they rest on.
+
+`tests/golden/fullsize.json` holds oracle distances of the full-size workloads
+(written by `tests/golden/make_golden.py`).  These CPU tests recompute a cheap
+part of it with the oracle, so a stale file or a change in the generators
+fails here before any GPU comparison uses it.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+GOLD_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize.json")
+
+
+@pytest.fixture(scope="module")
+def gold():
+    with open(GOLD_PATH) as f:
+        return json.load(f)
+
+
+def test_golden_file_complete(gold):
+    assert [g["k"] for g in gold["single"]] == [100, 1000, 10000, 100000]
+    assert all(g["n"] == 10 ** 8 and g["sigma"] == 4 for g in gold["single"])
+    assert {(g["periodic"], g["k"]) for g in gold["big"]} == {
+        (False, 1000), (False, 100000), (True, 1000), (True, 100000)}
+    assert all(g["n"] == 10 ** 9 and g["kind"] == "zipf" for g in gold["big"])
+    assert len(gold["batch"]["eds"]) == gold["batch"]["count"] == 4096
+    assert len(gold["serve"]["eds"]) == gold["serve"]["count"] == 40
+    # distance bounds of planted edits: |n - m| <= ED <= k
+    for g in gold["single"] + gold["big"]:
+        assert abs(g["n"] - g["m"]) <= g["ed"] <= g["k_planted"]
+
+
+@pytest.mark.parametrize("idx", [0, 1])
+def test_single_pairs_recomputed(gold, orc, idx):
+    g = gold["single"][idx]
+    A, B, info = synth.single_pair(g["n"], g["k"], g["seed"], sigma=g["sigma"], kind=g["kind"],
+                                   periodic=g["periodic"])
+    assert len(B) == g["m"] and info["k_planted"] == g["k_planted"]
+    assert orc.lv_omp(A, B) == g["ed"]
+
+
+def test_batch_prefix_recomputed(gold, orc):
+    b = gold["batch"]
+    specs = synth.batch_specs(b["count"], b["seed"])
+    for i in range(64):
+        n, k, ps = specs[i]
+        A, B, _ = synth.single_pair(n, k, ps)
+        assert orc.lv_omp(A, B, -1, 1) == b["eds"][i], i
+        assert abs(len(A) - len(B)) <= b["eds"][i] <= k
+
+
+def test_serve_small_requests_recomputed(gold, orc):
+    s = gold["serve"]
+    trace = synth.arrival_trace(s["count"], s["seed"], rate_per_s=1.0)
+    small = [i for i, r in enumerate(trace) if r["n"] <= 200000]
+    assert len(small) >= 10
+    for i in small:
+        A, B = synth.request_pair(trace[i])
+        assert orc.lv_omp(A, B, -1, 1) == s["eds"][i], i
+
+
+def test_zipf_guide_table_equals_search():
+    cdf = synth.zipf_cdf(256, 1.0)
+    v = synth.draws(11, synth.S_CHARS, 1 << 20)
+    u = synth._unit_float(v)
+    want = np.minimum(np.searchsorted(cdf, u, side="right"), 255).astype(np.uint8)
+    assert np.array_equal(synth._zipf_from(v, cdf), want)
+    edge = np.array([0, 1, 2 ** 64 - 1, 2 ** 63, (5 << 48) - 1, 5 << 48], dtype=np.uint64)
+    want = np.minimum(np.searchsorted(cdf, synth._unit_float(edge), side="right"), 255)
+    assert np.array_equal(synth._zipf_from(edge, cdf), want.astype(np.uint8))
+
+
+def test_threaded_sampling_matches_chunks():
+    d = synth.CharDist("zipf", 256)
+    n = 3 * (1 << 22) + 12345
+    whole = d.sample(3, synth.S_CHARS, n)
+    part = d.sample(3, synth.S_CHARS, 1000, start=(1 << 22) - 500)
+    assert np.array_equal(whole[(1 << 22) - 500:(1 << 22) + 500], part)

@@ -1,0 +1,152 @@
+"""Full-size parity: the library's distances at the workload sizes, in the launch
+configuration the benchmark times, against stored oracle values.
+
+`tests/golden/fullsize.json` is written by `tests/golden/make_golden.py`, which
+runs only `oracle.lv_omp` on `synth` inputs; these tests regenerate the same
+inputs from the same seeds.  Every comparison is exact.
+"""
+import json
+import os
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fullsize.json")) as _f:
+    GOLD = json.load(_f)
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ed():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2306_17461_amd as edmod
+    return edmod
+
+
+@pytest.fixture(scope="module")
+def ctxs(ed):
+    # the benchmark's contexts: default options, kernel timing on
+    made = {"direct": ed.ed_init(0, engine=ed.ENGINE_DIRECT, flags=ed.FLAG_TIMING),
+            "hash": ed.ed_init(0, engine=ed.ENGINE_HASH, flags=ed.FLAG_TIMING)}
+    yield made
+    for c in made.values():
+        ed.ed_shutdown(c)
+
+
+_cache = {}
+
+
+def device_pair(spec):
+    """The pair of a golden entry as device tensors (one pair cached at a time)."""
+    import torch
+    name = spec["name"]
+    if name not in _cache:
+        _cache.clear()
+        torch.cuda.empty_cache()
+        A, B, info = synth.single_pair(spec["n"], spec["k"], spec["seed"], sigma=spec["sigma"],
+                                       kind=spec["kind"], periodic=spec["periodic"])
+        assert len(B) == spec["m"] and info["k_planted"] == spec["k_planted"]
+        _cache[name] = (torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda())
+        del A, B
+    return _cache[name]
+
+
+def run_on_stream(ed, ctx, spec):
+    import torch
+    tA, tB = device_pair(spec)
+    stream = torch.cuda.current_stream()
+    pair = ed.ed_prepare(ctx, tA, tB, stream=stream)
+    try:
+        k = ed.ed_distance(ctx, pair, stream=stream)
+        st = ed.ed_pair_stats(pair)
+    finally:
+        ed.ed_release(pair)
+    return k, st
+
+
+def _cases(group):
+    return [(g["name"], e) for g in GOLD[group] for e in ("direct", "hash")]
+
+
+@pytest.mark.parametrize("name,engine", _cases("single"))
+def test_n1e8_alphabet4(ed, ctxs, name, engine):
+    spec = next(g for g in GOLD["single"] if g["name"] == name)
+    say("full", name, engine)
+    k, st = run_on_stream(ed, ctxs[engine], spec)
+    assert st["bits_per_char"] == 2
+    assert k == spec["ed"]
+    assert st["rounds"] == spec["ed"]
+
+
+@pytest.mark.parametrize("name,engine", _cases("big"))
+def test_n1e9_zipf_and_periodic(ed, ctxs, name, engine):
+    spec = next(g for g in GOLD["big"] if g["name"] == name)
+    say("full", name, engine)
+    k, st = run_on_stream(ed, ctxs[engine], spec)
+    assert st["bits_per_char"] == 8
+    assert k == spec["ed"]
+    if engine == "hash":
+        assert st["collision_bound"] < 1e-6
+
+
+def _gen_pairs(specs):
+    def one(s):
+        n, k, ps = s
+        A, B, _ = synth.single_pair(n, k, ps)
+        return A, B
+    with ThreadPoolExecutor(8) as ex:
+        return list(ex.map(one, specs))
+
+
+@pytest.mark.parametrize("engine", ["direct", "hash"])
+def test_batch4096(ed, ctxs, engine):
+    _cache.clear()
+    g = GOLD["batch"]
+    specs = synth.batch_specs(g["count"], g["seed"])
+    say("batch4096", engine, "generating")
+    pairs_h = _gen_pairs(specs)
+    ctx = ctxs[engine]
+    pairs = [ed.ed_prepare(ctx, A, B) for A, B in pairs_h]
+    del pairs_h
+    say("batch4096", engine, "running")
+    try:
+        got, st = ed.ed_batch(ctx, pairs)
+        assert st == [0] * len(pairs)
+        bad = [i for i in range(len(pairs)) if got[i] != g["eds"][i]]
+        assert not bad, "pairs %s differ (first: got %d want %d)" % (
+            bad[:10], got[bad[0]], g["eds"][bad[0]])
+    finally:
+        for p in pairs:
+            ed.ed_release(p)
+
+
+@pytest.mark.parametrize("engine", ["direct", "hash"])
+def test_serve40(ed, ctxs, engine):
+    _cache.clear()
+    g = GOLD["serve"]
+    trace = synth.arrival_trace(g["count"], g["seed"], rate_per_s=1.0)
+    reqs = [synth.request_pair(r) for r in trace]
+    say("serve40", engine)
+    srv = ed.ed_serve_open(ctxs[engine], 64 << 30, 256)
+    for tag, (A, B) in enumerate(reqs):
+        assert ed.ed_serve_submit(srv, A, B, tag) == 0, ed.ed_last_error()
+    ed.ed_serve_drain(srv)
+    res = ed.ed_serve_poll(srv, len(reqs) + 1)
+    ed.ed_serve_close(srv)
+    assert all(r["status"] == 0 for r in res)
+    got = {r["tag"]: r["k"] for r in res}
+    assert [got[i] for i in range(len(reqs))] == g["eds"]
+    # sampled sizes span the whole range
+    ns = np.array([r["n"] for r in trace])
+    assert ns.min() < 10 ** 3 and ns.max() > 10 ** 6
