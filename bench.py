@@ -47,6 +47,15 @@ def measured_traffic(kernel, engine, ks, n):
     return rec["per_launch_bytes"].get(kernel)
 
 
+def stored_oracle():
+    """Oracle distances of the workloads (tests/golden/fullsize.json), if present."""
+    try:
+        with open(os.path.join(ROOT, "tests", "golden", "fullsize.json")) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return None
+
+
 def batch_leg(ed, ctx, count=4096, seed=0):
     """Batched workload: `count` pairs, n = floor(10^U) with U ~ U[3, 6], alphabet
     {0,1,2,3}, k ~ U{0..floor(0.01 n)} planted edits.  One ed_batch launch against
@@ -62,21 +71,36 @@ def batch_leg(ed, ctx, count=4096, seed=0):
         chars += len(A)
     ed.ed_batch(ctx, pairs)  # warm-up
     t0 = time.perf_counter()
+    k0, _ = ed.ed_batch(ctx, pairs)
+    tb0 = time.perf_counter() - t0
+    # the autotuner picks the many-pair kernel's knobs on this batch (untimed)
+    log("batch leg: autotuning")
+    tune = ed.ed_autotune_batch(ctx, pairs)
+    t0 = time.perf_counter()
     kb, _ = ed.ed_batch(ctx, pairs)
     tb = time.perf_counter() - t0
     t0 = time.perf_counter()
     kp = [ed.ed_distance(ctx, p) for p in pairs]
     tp = time.perf_counter() - t0
-    if kb != kp:
+    if kb != kp or kb != k0:
         raise SystemExit("batch and per-pair distances differ")
+    gold = stored_oracle()
+    exact = None
+    if gold and gold["batch"]["count"] == count and gold["batch"]["seed"] == seed:
+        exact = kb == gold["batch"]["eds"]
+        if not exact:
+            raise SystemExit("batch distances differ from the stored oracle values")
     for p in pairs:
         ed.ed_release(p)
     return {"workload": "%d pairs, n log-uniform [1e3, 1e6], alphabet {0,1,2,3}, k uniform "
                         "[0, 0.01 n], seed %d" % (count, seed),
             "pairs": count, "chars_A": chars, "sum_k": int(sum(kb)),
             "batched_pairs_per_s": count / tb, "batched_s": tb,
+            "untuned_batched_pairs_per_s": count / tb0,
+            "autotune": {"knobs": tune["knobs"], "default_ms": round(tune["default_ms"], 3),
+                         "best_ms": round(tune["best_ms"], 3), "evaluated": tune["evaluated"]},
             "per_pair_pairs_per_s": count / tp, "per_pair_s": tp,
-            "speedup": tp / tb}
+            "speedup": tp / tb, "equal_to_stored_oracle": exact}
 
 
 def serve_leg(ed, ctx, count, seed=0, warmup=0):
@@ -283,6 +307,29 @@ def main():
                 "traffic": measured_traffic(dom, main_engine, ks, n),
                 "algorithmic_bytes_per_launch": byts, "avg_launch_ms": round(avg_ns / 1e6, 4)}
 
+    def prep_roofline(engine, prep_ms):
+        """Prepare kernels (pack, [table]) against the HBM peak: algorithmic
+        bytes = input read once + packed words written [+ prefix table written]."""
+        byts = 0
+        for i in range(len(ks)):
+            for L in (n, host[i][2]["m"]):
+                byts += L + L * bits / 8 + (8 * (L // 32 + 1) if engine == "hash" else 0)
+        byts /= len(ks)
+        avg_ns = sum(prep_ms) / len(prep_ms) * 1e6
+        return {"engine": engine, "bound": "hbm", "achieved": round(byts / avg_ns, 3), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(byts / avg_ns / PEAK_HBM_GBS, 4),
+                "algorithmic_bytes_per_call": byts, "avg_ms": round(avg_ns / 1e6, 4)}
+
+    prepare_roofline = [prep_roofline(main_engine, [x / 1e6 for x in prep_ns])]
+    gold = stored_oracle()
+    exact = None
+    if gold and n == N:
+        want = {g["k"]: g["ed"] for g in gold["single"]}
+        if all(k in want for k in ks):
+            exact = all(last[i][0] == want[ks[i]] for i in range(len(ks)))
+            if not exact:
+                raise SystemExit("distances differ from the stored oracle values")
+
     other = None
     if not args.no_other_engine:
         oname = "hash" if main_engine == "direct" else "direct"
@@ -296,6 +343,7 @@ def main():
                 "host_wall_ms": round((st["ns_prepare"] + st["ns_distance"]) / 1e6, 4)}
             if k != last[i][0]:
                 raise SystemExit("engines disagree at k=%d: %d vs %d" % (ks[i], k, last[i][0]))
+        prepare_roofline.append(prep_roofline(oname, [st["gpu_ns_prepare_kernel"] / 1e6 for _, st in r]))
 
     batch = None
     if not args.no_batch:
@@ -331,7 +379,9 @@ def main():
                                "uniform edits, k in %s, seed 0, one launch per pair" % ks,
                    "engine": main_engine, "bits_per_char": bits},
         "per_k": per_k,
+        "equal_to_stored_oracle": exact,
         "roofline": roofline,
+        "prepare_roofline": prepare_roofline,
         "cpu_baseline": cpu,
         "other_engine": other,
         "batch": batch,

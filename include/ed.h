@@ -71,7 +71,10 @@ typedef struct ed_options {
     uint32_t grid_blocks;  /* workgroups of the persistent kernels */
     uint32_t init_rows;    /* initial frontier capacity in diagonals per side (grown on demand) */
     uint32_t block_rounds; /* grid-wide phase: rounds per device-wide barrier (temporal blocking) */
-    uint32_t reserved[3];
+    /* knobs of the many-pair kernel (ed_batch, serving); 0 = default or autotuned */
+    uint32_t chunk_diags;       /* diagonals per chunk task (64..8000) */
+    uint32_t task_lds_rounds;   /* rounds a whole-pair task keeps in LDS (<= 4096) */
+    uint32_t task_block_rounds; /* rounds per chunk task (<= 4096) */
 } ed_options;
 
 /* Fills *opt with the defaults: direct engine, automatic packing, b = 32,
@@ -171,6 +174,27 @@ typedef struct ed_stats {
 } ed_stats;
 
 int ed_pair_stats(const ed_pair *pair, ed_stats *out);
+
+/* ---- autotuning ------------------------------------------------------------------ */
+typedef struct ed_tune_result {
+    ed_options best;    /* the context's options after tuning */
+    double default_ms;  /* batch time with the options the call started from */
+    double best_ms;     /* batch time with `best` */
+    uint32_t evaluated; /* configurations timed */
+    uint32_t pad;
+} ed_tune_result;
+
+/* Autotuner of the many-pair kernel (the batch form of section 3.1's rounds,
+ * not a passage of the paper): times ed_batch on `pairs` for candidate values
+ * of task_lds_rounds, task_block_rounds and chunk_diags by coordinate descent
+ * (`passes` sweeps over the knobs, 0 = 2), requires every configuration to
+ * return the same distances, and leaves the fastest configuration in the
+ * context's options (ed_batch and the serving loop use it).  The pairs stay
+ * prepared.  Each configuration runs the whole batch once; the call takes about
+ * (3 + 18 * passes) batch times.  Errors: as ed_batch; ED_EINTERNAL when two
+ * configurations disagree (the message names the pair). */
+int ed_autotune_batch(ed_ctx *ctx, ed_pair *const *pairs, uint64_t count, int64_t k_max,
+                      uint32_t passes, ed_tune_result *out, void *hip_stream);
 
 /* ---- debug read-backs (used by the tests) ------------------------------------ */
 #define ED_BUF_PACKED2 0 /* 2-bit words, char j at bits [2(j mod 32), +2) of word j/32 */

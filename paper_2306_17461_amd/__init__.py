@@ -53,7 +53,13 @@ class ed_options(ctypes.Structure):
                 ("hash_seed", ctypes.c_uint64), ("lds_rounds", ctypes.c_uint32),
                 ("lane_words", ctypes.c_uint32), ("grid_blocks", ctypes.c_uint32),
                 ("init_rows", ctypes.c_uint32), ("block_rounds", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 3)]
+                ("chunk_diags", ctypes.c_uint32), ("task_lds_rounds", ctypes.c_uint32),
+                ("task_block_rounds", ctypes.c_uint32)]
+
+
+class ed_tune_result(ctypes.Structure):
+    _fields_ = [("best", ed_options), ("default_ms", ctypes.c_double), ("best_ms", ctypes.c_double),
+                ("evaluated", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
 
 
 class ed_stats(ctypes.Structure):
@@ -81,7 +87,8 @@ class ed_result(ctypes.Structure):
 EXPORTS = [
     "ed_default_options", "ed_hash_base", "ed_init", "ed_set_options", "ed_get_options",
     "ed_shutdown", "ed_prepare", "ed_release", "ed_distance", "ed_distance_dump", "ed_batch",
-    "ed_pair_stats", "ed_pair_buffer", "ed_debug_lcp", "ed_serve_open", "ed_serve_submit",
+    "ed_autotune_batch", "ed_pair_stats", "ed_pair_buffer", "ed_debug_lcp", "ed_serve_open",
+    "ed_serve_submit",
     "ed_serve_poll", "ed_serve_drain", "ed_serve_close", "ed_strerror", "ed_last_error",
 ]
 
@@ -108,6 +115,7 @@ def _load():
         "ed_distance": (i32, [vp, vp, i64, P(u64), vp]),
         "ed_distance_dump": (i32, [vp, vp, i64, P(u64), vp, u64, vp]),
         "ed_batch": (i32, [vp, P(vp), u64, i64, P(u64), P(ctypes.c_int32), vp]),
+        "ed_autotune_batch": (i32, [vp, P(vp), u64, i64, ctypes.c_uint32, P(ed_tune_result), vp]),
         "ed_pair_stats": (i32, [vp, P(ed_stats)]),
         "ed_pair_buffer": (i32, [vp, vp, i32, i32, vp, u64, P(u64)]),
         "ed_debug_lcp": (i32, [vp, vp, i32, vp, vp, u64, vp, vp]),
@@ -250,6 +258,18 @@ def ed_batch(ctx, pairs, k_max=-1, stream=None, check=True):
     if check:
         _check(rc, "ed_batch")
     return [int(kout[i]) for i in range(cnt)], [int(st[i]) for i in range(cnt)]
+
+
+def ed_autotune_batch(ctx, pairs, k_max=-1, passes=0, stream=None):
+    """Tunes the many-pair kernel on these pairs; returns the chosen knobs and timings."""
+    cnt = len(pairs)
+    arr = (ctypes.c_void_p * max(cnt, 1))(*[p.value for p in pairs])
+    r = ed_tune_result()
+    _check(lib.ed_autotune_batch(ctx, arr, cnt, k_max, passes, ctypes.byref(r), _stream_handle(stream)),
+           "ed_autotune_batch")
+    best = {f: getattr(r.best, f) for f, _ in r.best._fields_}
+    return {"best": best, "default_ms": r.default_ms, "best_ms": r.best_ms, "evaluated": r.evaluated,
+            "knobs": {k: best[k] for k in ("task_lds_rounds", "task_block_rounds", "chunk_diags")}}
 
 
 def ed_pair_stats(pair):

@@ -150,6 +150,9 @@ static int check_options(const ed_options* o) {
     if (o->lane_words > 64) return ED_EINVAL;
     if (o->grid_blocks > static_cast<uint32_t>(kMaxGrid)) return ED_EINVAL;
     if (o->block_rounds > 4096) return ED_EINVAL;
+    if (o->chunk_diags != 0 && (o->chunk_diags < 64 || o->chunk_diags > 8000)) return ED_EINVAL;
+    if (o->task_lds_rounds > static_cast<uint32_t>(kLdsRoundsMax)) return ED_EINVAL;
+    if (o->task_block_rounds > 4096) return ED_EINVAL;
     return ED_OK;
 }
 
@@ -361,7 +364,7 @@ int ed::prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B
         }
     }
     const int32_t total = tiles[0] + tiles[1];
-    p->misc = c->pool.get(kMiscAlpha + 64 + static_cast<size_t>(total) * 9);
+    p->misc = c->pool.get(kMiscAlpha + 64 + static_cast<size_t>(total) * (8 + kTileChunks));
     if (!p->misc) {
         pair_free(p);
         delete p;
@@ -413,10 +416,12 @@ int ed::prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B
     pp.tile_status = reinterpret_cast<uint64_t*>(misc + kMiscAlpha + 64);
     pp.ticket = reinterpret_cast<unsigned int*>(misc + kMiscTicket);
     pp.alpha = reinterpret_cast<uint32_t*>(misc + kMiscAlpha);
-    pp.tile_big = reinterpret_cast<uint8_t*>(misc + kMiscAlpha + 64 + static_cast<size_t>(total) * 8);
+    pp.chunk_big = reinterpret_cast<uint8_t*>(misc + kMiscAlpha + 64 + static_cast<size_t>(total) * 8);
     pp.rtab = c->d_pow + 2 * 65536;
-    int grid = std::min(total, c->num_cu * 4);
-    if (grid < 1) grid = 1;
+    // streaming kernels: enough wavefronts to keep every CU full, each taking
+    // several chunks; the table kernel: a few tiles in flight per CU
+    const int stream_grid = std::max(1, std::min(total, c->num_cu * 8));
+    const int table_grid = std::max(1, std::min(total, c->num_cu * 4));
     HIP_TRY(launch_prep_clear(pp, s));
     if (c->opt.flags & ED_FLAG_TIMING) {
         HIP_TRY(hipEventCreate(&p->ev_prep[0]));
@@ -424,10 +429,11 @@ int ed::prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B
         HIP_TRY(hipEventRecord(p->ev_prep[0], s));
         p->prep_timed = true;
     }
-    HIP_TRY(launch_prepare(pp, grid, s));
+    HIP_TRY(launch_pack(pp, stream_grid, s));
+    if (c->opt.pack_bits != 2) HIP_TRY(launch_copy8_rest(pp, stream_grid, s));
+    if (table) HIP_TRY(launch_table(pp, table_grid, s));
     if (p->prep_timed) HIP_TRY(hipEventRecord(p->ev_prep[1], s));
-    if (c->opt.pack_bits != 2) HIP_TRY(launch_copy8_rest(pp, s));
-    p->launches_prepare = c->opt.pack_bits != 2 ? 3 : 2;
+    p->launches_prepare = 2 + (c->opt.pack_bits != 2 ? 1 : 0) + (table ? 1 : 0);
     if (c->opt.pack_bits == 2) {
         uint32_t alpha = 0;
         HIP_TRY(hipMemcpyAsync(&alpha, pp.alpha, 4, hipMemcpyDeviceToHost, s));

@@ -1,5 +1,6 @@
 // ed_batch: many prepared pairs in one persistent launch.
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -48,27 +49,42 @@ long long task_chunk(int32_t pi, int32_t c) {
     return static_cast<long long>(static_cast<uint32_t>(pi)) | (static_cast<long long>(c + 1) << 32);
 }
 
+// Knobs of the many-pair kernel: their own option, else the single-pair one,
+// else the default.
 int32_t block_rounds_of(const ed_ctx* c) {
-    return static_cast<int32_t>(c->opt.block_rounds ? c->opt.block_rounds : kDefaultBlockRounds);
+    const uint32_t v = c->opt.task_block_rounds ? c->opt.task_block_rounds
+                       : c->opt.block_rounds    ? c->opt.block_rounds
+                                                : kDefaultBlockRounds;
+    return static_cast<int32_t>(v);
+}
+
+uint32_t task_solo_rounds(const ed_ctx* c) {
+    return c->opt.task_lds_rounds ? c->opt.task_lds_rounds
+           : c->opt.lds_rounds    ? c->opt.lds_rounds
+                                  : kDefaultLdsRounds;
+}
+
+int32_t chunk_diags_of(const ed_ctx* c) {
+    return static_cast<int32_t>(c->opt.chunk_diags ? c->opt.chunk_diags : kChunkDiags);
 }
 
 // Host-side twin of the device scheduler: the next super-step of a pair whose
 // frontier f_t is in its rows.  Appends the chunk tasks; returns false when no
 // round can be taken (rows full, k_max or the round budget reached).
-bool schedule_on_host(TaskPair& tp, int32_t pi, int32_t block_rounds, int64_t k_max,
+bool schedule_on_host(TaskPair& tp, int32_t pi, int32_t block_rounds, int32_t chunk, int64_t k_max,
                       std::vector<long long>& tasks) {
     const int32_t t = tp.t;
     int64_t H = std::min<int64_t>(block_rounds, static_cast<int64_t>(tp.K) - t);
-    H = std::min<int64_t>(H, (kLdsRowLen - kChunkDiags) / 2);
+    H = std::min<int64_t>(H, (kLdsRowLen - chunk) / 2);
     if (k_max >= 0) H = std::min<int64_t>(H, k_max - t);
     H = std::min<int64_t>(H, static_cast<int64_t>(tp.t_limit) - t);
     if (H <= 0) return false;
     const int32_t T = t + static_cast<int32_t>(H);
     const int32_t total = 2 * T + 5;
-    const int32_t nch = (total + kChunkDiags - 1) / kChunkDiags;
+    const int32_t nch = (total + chunk - 1) / chunk;
     tp.H = static_cast<int32_t>(H);
     tp.T = T;
-    tp.chunk = kChunkDiags;
+    tp.chunk = chunk;
     tp.nchunks = nch;
     tp.chunks_left = nch;
     tp.found_t = INT32_MAX;
@@ -79,8 +95,8 @@ bool schedule_on_host(TaskPair& tp, int32_t pi, int32_t block_rounds, int64_t k_
 int tasks_run(ed_ctx* c, std::vector<TaskPair>& st, const std::vector<long long>& first, int64_t k_max,
               uint32_t engine, hipStream_t s) {
     const uint64_t count = st.size();
-    const uint32_t solo = c->opt.lds_rounds ? c->opt.lds_rounds : kDefaultLdsRounds;
-    const int32_t C = kChunkDiags;
+    const uint32_t solo = task_solo_rounds(c);
+    const int32_t C = chunk_diags_of(c);
     // every task that can be in flight at once: one per pair, plus one
     // super-step of chunks per pair with rows, plus slack for the workgroups
     uint64_t qcap = count + first.size() + 256;
@@ -162,7 +178,7 @@ int batch_locked(ed_ctx* c, ed_pair* const* pairs, uint64_t count, int64_t k_max
         int rc = ctx_set_hash(c, pairs[0]->seed);
         if (rc != ED_OK) return rc;
     }
-    const uint32_t solo = c->opt.lds_rounds ? c->opt.lds_rounds : kDefaultLdsRounds;
+    const uint32_t solo = task_solo_rounds(c);
 
     // processing order: largest pairs first (longest-processing-time first), or
     // a seeded permutation when testing order independence
@@ -243,4 +259,124 @@ int ed_batch(ed_ctx* c, ed_pair* const* pairs, uint64_t count, int64_t k_max, ui
     std::lock_guard<std::mutex> lk(c->mu);
     if (hipSetDevice(c->device) != hipSuccess) return ED_EDEVICE;
     return batch_locked(c, pairs, count, k_max, k_out, status_out, static_cast<hipStream_t>(hip_stream));
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner of the many-pair kernel: coordinate descent over its three knobs,
+// timing whole batches; every configuration must give the same distances.
+// ---------------------------------------------------------------------------
+int ed_autotune_batch(ed_ctx* c, ed_pair* const* pairs, uint64_t count, int64_t k_max, uint32_t passes,
+                      ed_tune_result* out, void* hip_stream) {
+    if (!c || (count && !pairs) || !out) return ED_EINVAL;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (hipSetDevice(c->device) != hipSuccess) return ED_EDEVICE;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    if (passes == 0) passes = 2;
+    std::memset(out, 0, sizeof *out);
+    const ed_options start = c->opt;
+    std::vector<uint64_t> want(count), got(count);
+    std::vector<int32_t> st(count);
+    uint32_t evaluated = 0;
+
+    // one timed batch with the current options; compares with `want` once set
+    auto run = [&](bool reference, double* ms) -> int {
+        const auto t0 = std::chrono::steady_clock::now();
+        int rc = batch_locked(c, pairs, count, k_max, reference ? want.data() : got.data(), st.data(), s);
+        const auto t1 = std::chrono::steady_clock::now();
+        if (rc != ED_OK) return rc;
+        *ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        ++evaluated;
+        if (!reference) {
+            for (uint64_t i = 0; i < count; ++i)
+                if (got[i] != want[i]) {
+                    set_error("ed_autotune_batch: pair %llu gave %llu under chunk_diags=%u "
+                              "task_lds_rounds=%u task_block_rounds=%u, %llu before",
+                              (unsigned long long)i, (unsigned long long)got[i], c->opt.chunk_diags,
+                              c->opt.task_lds_rounds, c->opt.task_block_rounds,
+                              (unsigned long long)want[i]);
+                    return ED_EINTERNAL;
+                }
+        }
+        return ED_OK;
+    };
+
+    // the starting configuration, with its knobs made explicit
+    ed_options start_x = start;
+    start_x.chunk_diags = static_cast<uint32_t>(chunk_diags_of(c));
+    start_x.task_lds_rounds = task_solo_rounds(c);
+    start_x.task_block_rounds = static_cast<uint32_t>(block_rounds_of(c));
+    ed_options best = start_x;
+    double warm = 0, default_ms = 0;
+    c->opt = best;
+    int rc = run(true, &warm);  // warm-up and reference distances
+    if (rc == ED_OK) rc = run(false, &default_ms);
+    if (rc != ED_OK) {
+        c->opt = start;
+        return rc;
+    }
+    double best_ms = default_ms;
+    static const uint32_t kLds[] = {64, 128, 256, 512, 1024, 2048, 4096};
+    static const uint32_t kBlock[] = {8, 16, 32, 64, 128, 256};
+    static const uint32_t kChunk[] = {512, 1024, 2048, 4096, 6144};
+    for (uint32_t pass = 0; pass < passes; ++pass) {
+        bool moved = false;
+        for (int knob = 0; knob < 3; ++knob) {
+            const uint32_t* vals = knob == 0 ? kLds : knob == 1 ? kBlock : kChunk;
+            const int nv = knob == 0 ? 7 : knob == 1 ? 6 : 5;
+            for (int v = 0; v < nv; ++v) {
+                ed_options cand = best;
+                uint32_t& field = knob == 0 ? cand.task_lds_rounds
+                                  : knob == 1 ? cand.task_block_rounds
+                                              : cand.chunk_diags;
+                if (field == vals[v]) continue;
+                field = vals[v];
+                // a chunk and its halo must fit one LDS row
+                if (cand.chunk_diags + 2 * std::min<uint32_t>(cand.task_block_rounds, 4096) >
+                    static_cast<uint32_t>(kLdsRowLen))
+                    continue;
+                c->opt = cand;
+                double ms = 0;
+                rc = run(false, &ms);
+                if (rc != ED_OK) {
+                    c->opt = start;
+                    return rc;
+                }
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = cand;
+                    moved = true;
+                }
+            }
+        }
+        if (!moved) break;
+    }
+    // re-time the winner and the start: the winner is kept only if it is
+    // still faster (a lucky single timing is not kept)
+    if (best_ms < default_ms) {
+        double again = 0, again0 = 0;
+        c->opt = best;
+        rc = run(false, &again);
+        if (rc == ED_OK) {
+            c->opt = start_x;
+            rc = run(false, &again0);
+        }
+        if (rc != ED_OK) {
+            c->opt = start;
+            return rc;
+        }
+        const double tb = std::min(again, best_ms), t0 = std::min(again0, default_ms);
+        if (tb >= t0) {
+            best = start_x;
+            best_ms = t0;
+        } else {
+            best_ms = tb;
+        }
+        default_ms = t0;
+    }
+    c->opt = best;
+    out->best = best;
+    out->default_ms = default_ms;
+    out->best_ms = best_ms;
+    out->evaluated = evaluated;
+    return ED_OK;
 }

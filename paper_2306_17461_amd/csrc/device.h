@@ -162,6 +162,29 @@ __device__ __forceinline__ int32_t lcp_wave_steps(const SView& A, const SView& B
 }
 
 // ---------------------------------------------------------------------------
+// Work counters of one thread.  The per-diagonal counts stay in registers;
+// the counts of rarer events (LCPs beyond the lane tier, hash probes) go to
+// `sh`, the workgroup's copy in LDS, through one lane per wavefront.
+// ---------------------------------------------------------------------------
+struct Cnt {
+    unsigned long long updates;    // this lane's diagonal updates
+    unsigned long long lcp_chars;  // characters matched by this lane's slides
+    unsigned long long eq_len;     // sum of L over this lane's hash "equal" verdicts
+    CountersDev* sh;               // workgroup counters (LDS)
+};
+
+__device__ __forceinline__ void cnt_bind(Cnt& c, CountersDev* sh) {
+    c.updates = 0;
+    c.lcp_chars = 0;
+    c.eq_len = 0;
+    c.sh = sh;
+}
+
+__device__ __forceinline__ void cnt_init_shared(CountersDev* sh) {
+    if (threadIdx.x < sizeof(CountersDev) / 8) reinterpret_cast<unsigned long long*>(sh)[threadIdx.x] = 0;
+}
+
+// ---------------------------------------------------------------------------
 // Engine (b): prefix hashes.  H(S, p) = h(S[0..p)) is rebuilt from the
 // blocked table as T[p/b] * r^(p mod b) + h(S[(p/b)b .. p)) (Algorithm 2,
 // GetHash, with the block index read as floor(p/b)).  Equality of
@@ -230,14 +253,14 @@ __device__ __forceinline__ uint64_t get_hash(const SView& S, const uint64_t* T, 
 // "equal" verdict wrong: the LCP is recomputed directly (counted).
 __device__ __forceinline__ int32_t lcp_wave_hash(const SView& A, const SView& B, const uint64_t* TA,
                                  const uint64_t* TB, const HashQ& q, int32_t x, int32_t y,
-                                 int32_t lim, int32_t l0, CountersDev& cnt) {
+                                 int32_t lim, int32_t l0, Cnt& cnt) {
     const int lane = lane_id();
     const int32_t cpw = 1 << A.lcpw;
     const int32_t span = 64 * cpw;  // one direct step
     const uint64_t hax = get_hash(A, TA, q, x);
     const uint64_t hby = get_hash(B, TB, q, y);
     const uint64_t d0 = mp_sub(hax, hby);
-    if (lane == 0) cnt.hash_queries++;
+    if (lane == 0) atomicAdd(&cnt.sh->hash_queries, 1ull);
 
     auto eq = [&](int32_t L) -> bool {
         const uint64_t lhs = mp_sub(get_hash(A, TA, q, x + L), get_hash(B, TB, q, y + L));
@@ -252,10 +275,9 @@ __device__ __forceinline__ int32_t lcp_wave_hash(const SView& A, const SView& B,
         const bool active = Lprev < lim;  // first probe that reaches lim is the last one
         const int32_t L = static_cast<int32_t>(Lr < lim ? Lr : lim);
         const bool e = active ? eq(L) : true;
-        if (active) {
-            cnt.hash_probes++;
-            if (e) cnt.hash_eq_len += static_cast<unsigned long long>(L);
-        }
+        const uint64_t pa = ballot(active);
+        if (lane == 0) atomicAdd(&cnt.sh->hash_probes, static_cast<unsigned long long>(__builtin_popcountll(pa)));
+        if (active && e) cnt.eq_len += static_cast<unsigned long long>(L);
         const uint64_t ne = ballot(active && !e);
         if (ne == 0) return lim;  // every probe up to lim matched
         const int k = ctz64(ne);
@@ -267,12 +289,10 @@ __device__ __forceinline__ int32_t lcp_wave_hash(const SView& A, const SView& B,
         const int32_t M = lo + (lane + 1) * step;
         const bool active = M < hi;
         const bool e = active ? eq(M) : true;
-        if (active) {
-            cnt.hash_probes++;
-            if (e) cnt.hash_eq_len += static_cast<unsigned long long>(M);
-        }
-        const uint64_t ne = ballot(active && !e);
         const uint64_t act = ballot(active);
+        if (lane == 0) atomicAdd(&cnt.sh->hash_probes, static_cast<unsigned long long>(__builtin_popcountll(act)));
+        if (active && e) cnt.eq_len += static_cast<unsigned long long>(M);
+        const uint64_t ne = ballot(active && !e);
         if (ne) {
             const int k = ctz64(ne);
             const int32_t nhi = shfl_i32(M, k);
@@ -295,7 +315,7 @@ __device__ __forceinline__ int32_t lcp_wave_hash(const SView& A, const SView& B,
         if (c < hi) return c;
     }
     // no mismatch in [lo, hi): a collision hid one below lo
-    if (lane == 0) cnt.collisions++;
+    if (lane == 0) atomicAdd(&cnt.sh->collisions, 1ull);
     return lcp_wave_direct(A, B, x, y, lim, 0);
 }
 
@@ -329,7 +349,7 @@ struct Engine {
 };
 
 __device__ __forceinline__ int32_t slide(const Engine& en, bool valid, int32_t x, int32_t y,
-                                         CountersDev& cnt) {
+                                         Cnt& cnt) {
     int32_t lim = 0, l = 0;
     bool more = false;
     if (valid) {
@@ -348,32 +368,37 @@ __device__ __forceinline__ int32_t slide(const Engine& en, bool valid, int32_t x
             r = lcp_wave_hash(en.A, en.B, en.TA, en.TB, en.q, jx, jy, jlim, jl, cnt);
         else
             r = lcp_wave_direct(en.A, en.B, jx, jy, jlim, jl);
-        if (lane_id() == 0) cnt.wave_lcps++;
+        if (lane_id() == 0) atomicAdd(&cnt.sh->wave_lcps, 1ull);
         if (lane_id() == src) l = r;
     }
     if (valid) cnt.lcp_chars += static_cast<unsigned long long>(l);
     return l;
 }
 
-__device__ __forceinline__ void flush_counters(CountersDev& c, CountersDev* g) {
-    // wave-level sums, then one atomic per wave and field
+// Every thread of the workgroup: wave sums of the register counters into the
+// LDS copy, then one thread adds the LDS copy to the global counters.
+__device__ __forceinline__ void flush_counters(Cnt& c, CountersDev* g) {
     auto red = [](unsigned long long v) {
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
         return v;
     };
-    const unsigned long long u = red(c.updates), lc = red(c.lcp_chars), wl = red(c.wave_lcps),
-                             gl = red(c.grid_lcps), hq = red(c.hash_queries),
-                             hp = red(c.hash_probes), he = red(c.hash_eq_len),
-                             co = red(c.collisions);
-    if (lane_id() == 0 && g) {
-        if (u) atomicAdd(&g->updates, u);
-        if (lc) atomicAdd(&g->lcp_chars, lc);
-        if (wl) atomicAdd(&g->wave_lcps, wl);
-        if (gl) atomicAdd(&g->grid_lcps, gl);
-        if (hq) atomicAdd(&g->hash_queries, hq);
-        if (hp) atomicAdd(&g->hash_probes, hp);
-        if (he) atomicAdd(&g->hash_eq_len, he);
-        if (co) atomicAdd(&g->collisions, co);
+    const unsigned long long u = red(c.updates), lc = red(c.lcp_chars), he = red(c.eq_len);
+    if (lane_id() == 0) {
+        if (u) atomicAdd(&c.sh->updates, u);
+        if (lc) atomicAdd(&c.sh->lcp_chars, lc);
+        if (he) atomicAdd(&c.sh->hash_eq_len, he);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && g) {
+        const CountersDev& s = *c.sh;
+        if (s.updates) atomicAdd(&g->updates, s.updates);
+        if (s.lcp_chars) atomicAdd(&g->lcp_chars, s.lcp_chars);
+        if (s.wave_lcps) atomicAdd(&g->wave_lcps, s.wave_lcps);
+        if (s.grid_lcps) atomicAdd(&g->grid_lcps, s.grid_lcps);
+        if (s.hash_queries) atomicAdd(&g->hash_queries, s.hash_queries);
+        if (s.hash_probes) atomicAdd(&g->hash_probes, s.hash_probes);
+        if (s.hash_eq_len) atomicAdd(&g->hash_eq_len, s.hash_eq_len);
+        if (s.collisions) atomicAdd(&g->collisions, s.collisions);
     }
 }
 

@@ -38,7 +38,7 @@ namespace ed {
 
 namespace {
 
-constexpr int kU = 4;          // diagonals per thread per pass
+constexpr int kU = 2;          // diagonals per thread per pass
 constexpr int kJobHalf = 128;  // queued LCPs per round (a ring of two halves)
 constexpr int kWaveSteps = 2;  // wavefront steps before the hash search / workgroup tier
 
@@ -59,6 +59,7 @@ struct LdsState {
     int32_t row[2][kLdsRowLen];
     uint64_t lut4[256];
     RoundShared rs;
+    CountersDev cnt;
 };
 
 // Per-workgroup cursor into the job counters (uniform, kept in registers).
@@ -119,6 +120,48 @@ __device__ __forceinline__ int32_t lcp_wg_direct(const SView& A, const SView& B,
     return lim;
 }
 
+// Tiers (2)/(3) for one slot of diagonals of a wavefront: every lane with a
+// pending LCP is extended in turn by the whole wavefront.  Arguments are the
+// calling lane's own values; `l` and `queued` are updated in that lane.
+__device__ __forceinline__ void wave_extend(const Engine& en, bool pend, int32_t c, int32_t i,
+                                            int32_t lim, int32_t& l, bool& queued, RoundShared& RS,
+                                            int par, int half, int32_t jstart, int lane,
+                                            Cnt& cnt) {
+    uint64_t pm = ballot(pend);
+    while (pm) {
+        const int src = ctz64(pm);
+        pm &= pm - 1;
+        const int32_t jx = shfl_i32(c, src), jy = shfl_i32(c - i, src);
+        const int32_t jlim = shfl_i32(lim, src), jl = shfl_i32(l, src);
+        bool done = false;
+        int32_t r = lcp_wave_steps(en.A, en.B, jx, jy, jlim, jl, kWaveSteps, done);
+        if (lane == 0) atomicAdd(&cnt.sh->wave_lcps, 1ull);
+        if (!done) {
+            if (en.kind == 1) {
+                r = lcp_wave_hash(en.A, en.B, en.TA, en.TB, en.q, jx, jy, jlim, r, cnt);
+            } else {
+                int32_t s = 0;
+                if (lane == 0) s = atomicAdd(&RS.jcount[par], 1) - jstart;
+                s = shfl_i32(s, 0);
+                if (s < kJobHalf) {
+                    if (lane == src) {
+                        RS.ji[half + s] = i;
+                        RS.jx[half + s] = jx;
+                        RS.jy[half + s] = jy;
+                        RS.jlim[half + s] = jlim;
+                        RS.jl[half + s] = r;
+                        queued = true;
+                    }
+                    continue;
+                }
+                // queue full: the wavefront finishes it
+                r = lcp_wave_direct(en.A, en.B, jx, jy, jlim, r);
+            }
+        }
+        if (lane == src) l = r;
+    }
+}
+
 // One round over diagonals [i_begin, i_end) (any i outside [max(-t,-m),
 // min(t,n)] is written as kNone).  Diagonal i of a row lives at
 // row[i + ofs]; every index formed here is inside the row, so no pointer
@@ -139,7 +182,7 @@ template <typename PrevPtr, typename CurPtr>
 __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr prev, CurPtr cur,
                                             int32_t ofs, int32_t i_begin, int32_t i_end, RoundShared& RS,
                                             JobCursor& jc, int32_t* dump_row, int32_t dlo, int32_t dhi,
-                                            CountersDev& cnt) {
+                                            Cnt& cnt) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & 63;
     const int32_t n = en.A.len, m = en.B.len;
@@ -150,12 +193,18 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
     const int half = par * kJobHalf;
     const int32_t jstart = jc.start[par];
     bool found = false;
+    // first thread of this wavefront, as a uniform value: a slot whose
+    // diagonals all lie past i_end is skipped by the whole wavefront
+    const int32_t wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
+    const int32_t qmask = (1 << en.A.lcpw) - 1;
     for (int32_t base = i_begin; base < i_end; base += nthr * kU) {
         int32_t iv[kU], c[kU], l[kU], lim[kU];
-        bool val[kU], act[kU], pend[kU], queued[kU];
+        bool val[kU], act[kU], pend[kU], queued[kU], slot[kU];
         uint64_t d0[kU], d1[kU];
+        uint64_t wa[kU][3], wb[kU][3];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
+            slot[u] = base + u * nthr + wbase < i_end;
             const int32_t i = base + u * nthr + tid;
             iv[u] = i;
             act[u] = i < i_end;
@@ -174,22 +223,40 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
             val[u] = inr && cc >= 0;
             lim[u] = val[u] ? imin(n - cc, m - (cc - i)) : 0;
         }
-        // (1) first two words of every diagonal, all loads in flight together
+        // (1) three words of A and of B per diagonal (the first 2 cpw
+        // characters from any offset), issued for every slot before any use:
+        // one memory latency per pass.  Idle lanes read word 0 (always there).
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
+            if (!slot[u]) continue;
             const bool go = lim[u] > 0;
-            const int32_t xs = go ? c[u] : 0;
-            const int32_t ys = go ? c[u] - iv[u] : 0;
-            const bool two = lim[u] > cpw;
-            d0[u] = fetch(en.A, xs) ^ fetch(en.B, ys);
-            d1[u] = two ? (fetch(en.A, xs + cpw) ^ fetch(en.B, ys + cpw)) : 0;
+            const int32_t qa = go ? c[u] >> en.A.lcpw : 0;
+            const int32_t qb = go ? (c[u] - iv[u]) >> en.A.lcpw : 0;
+            wa[u][0] = en.A.w[qa];
+            wa[u][1] = en.A.w[qa + 1];
+            wa[u][2] = en.A.w[qa + 2];
+            wb[u][0] = en.B.w[qb];
+            wb[u][1] = en.B.w[qb + 1];
+            wb[u][2] = en.B.w[qb + 2];
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             l[u] = 0;
             pend[u] = false;
             queued[u] = false;
-            if (lim[u] > 0) {
+            d0[u] = d1[u] = 0;
+            if (!slot[u]) continue;
+            const bool go = lim[u] > 0;
+            const uint32_t sa = go ? static_cast<uint32_t>(c[u] & qmask) * en.A.bpc : 0;
+            const uint32_t sb = go ? static_cast<uint32_t>((c[u] - iv[u]) & qmask) * en.A.bpc : 0;
+            // (hi << 1) << (63 - sh) equals hi << (64 - sh) and is 0 for sh = 0
+            const uint64_t a0 = (wa[u][0] >> sa) | ((wa[u][1] << 1) << (63 - sa));
+            const uint64_t a1 = (wa[u][1] >> sa) | ((wa[u][2] << 1) << (63 - sa));
+            const uint64_t b0 = (wb[u][0] >> sb) | ((wb[u][1] << 1) << (63 - sb));
+            const uint64_t b1 = (wb[u][1] >> sb) | ((wb[u][2] << 1) << (63 - sb));
+            d0[u] = a0 ^ b0;
+            d1[u] = a1 ^ b1;
+            if (go) {
                 if (d0[u]) {
                     l[u] = imin(ctz64(d0[u]) / en.A.bpc, lim[u]);
                 } else if (lim[u] <= cpw) {
@@ -207,39 +274,8 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
         // (2)/(3) the wavefront extends its lanes' long LCPs
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-            uint64_t pm = ballot(pend[u]);
-            while (pm) {
-                const int src = ctz64(pm);
-                pm &= pm - 1;
-                const int32_t jx = shfl_i32(c[u], src), jy = shfl_i32(c[u] - iv[u], src);
-                const int32_t jlim = shfl_i32(lim[u], src), jl = shfl_i32(l[u], src);
-                bool done = false;
-                int32_t r = lcp_wave_steps(en.A, en.B, jx, jy, jlim, jl, kWaveSteps, done);
-                if (lane == 0) cnt.wave_lcps++;
-                if (!done) {
-                    if (en.kind == 1) {
-                        r = lcp_wave_hash(en.A, en.B, en.TA, en.TB, en.q, jx, jy, jlim, r, cnt);
-                    } else {
-                        int32_t s = 0;
-                        if (lane == 0) s = atomicAdd(&RS.jcount[par], 1) - jstart;
-                        s = shfl_i32(s, 0);
-                        if (s < kJobHalf) {
-                            if (lane == src) {
-                                RS.ji[half + s] = iv[u];
-                                RS.jx[half + s] = jx;
-                                RS.jy[half + s] = jy;
-                                RS.jlim[half + s] = jlim;
-                                RS.jl[half + s] = r;
-                                queued[u] = true;
-                            }
-                            continue;
-                        }
-                        // queue full: the wavefront finishes it
-                        r = lcp_wave_direct(en.A, en.B, jx, jy, jlim, r);
-                    }
-                }
-                if (lane == src) l[u] = r;
-            }
+            if (!slot[u]) continue;
+            wave_extend(en, pend[u], c[u], iv[u], lim[u], l[u], queued[u], RS, par, half, jstart, lane, cnt);
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
@@ -273,7 +309,7 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
                 cur[i + ofs] = f;
                 if (dump_row && i >= dlo && i <= dhi) dump_row[i + t] = f;
                 cnt.updates++;
-                cnt.grid_lcps++;
+                atomicAdd(&cnt.sh->grid_lcps, 1ull);
                 cnt.lcp_chars += static_cast<unsigned long long>(r);
                 if (i == target && f == n) {
                     found = true;
@@ -309,19 +345,41 @@ __device__ __forceinline__ void grid_sync(FrontierCtl* ctl, unsigned int* bar, u
     __syncthreads();
 }
 
+// Values every lane holds alike, marked uniform so that they live in scalar
+// registers (fields loaded from device memory would otherwise take vector
+// registers in every lane).
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+template <typename T>
+__device__ __forceinline__ const T* uni(const T* p) {
+    return reinterpret_cast<const T*>(uni(reinterpret_cast<uint64_t>(p)));
+}
+
 __device__ __forceinline__ Engine make_engine(const PairDev& p, const HashDev& h, int engine,
                                               int lane_words, const uint64_t* lut4) {
     Engine en;
     const uint32_t alpha = *p.alpha;
     pair_views(p, alpha, en.A, en.B);
-    en.TA = p.a.tab;
-    en.TB = p.b.tab;
-    en.q.h = h;
-    en.q.r4 = engine == 1 ? mp_mul(mp_mul(h.r, h.r), mp_mul(h.r, h.r)) : 0;
+    en.A.w = uni(en.A.w);
+    en.B.w = uni(en.B.w);
+    en.A.len = uni(en.A.len);
+    en.B.len = uni(en.B.len);
+    en.A.lcpw = en.B.lcpw = uni(en.A.lcpw);
+    en.A.bpc = en.B.bpc = uni(en.A.bpc);
+    en.TA = uni(p.a.tab);
+    en.TB = uni(p.b.tab);
+    en.q.h.r = uni(h.r);
+    en.q.h.pow0 = uni(h.pow0);
+    en.q.h.pow1 = uni(h.pow1);
+    en.q.r4 = engine == 1 ? mp_mul(mp_mul(en.q.h.r, en.q.h.r), mp_mul(en.q.h.r, en.q.h.r)) : 0;
     en.q.lut4 = lut4;
-    en.q.log2b = p.log2b;
-    en.kind = engine;
-    en.lane_words = lane_words;
+    en.q.log2b = uni(p.log2b);
+    en.kind = uni(engine);
+    en.lane_words = uni(lane_words);
     return en;
 }
 
@@ -404,7 +462,7 @@ __device__ void schedule_superstep(const TaskParams& P, TaskPair* S, int32_t pi)
                       (static_cast<long long>(c + 1) << 32), base + c);
 }
 
-__device__ void solo_task(const TaskParams& P, int32_t pi, LdsState& L, JobCursor& jc, CountersDev& cnt) {
+__device__ void solo_task(const TaskParams& P, int32_t pi, LdsState& L, JobCursor& jc, Cnt& cnt) {
     TaskPair* S = P.pairs + pi;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const Engine en = make_engine(S->p, P.h, P.engine, P.lane_words, L.lut4);
@@ -414,9 +472,9 @@ __device__ void solo_task(const TaskParams& P, int32_t pi, LdsState& L, JobCurso
     int32_t* la = L.row[0];
     int32_t* lb = L.row[1];
     RoundShared& RS = L.rs;
-    int32_t t = S->t;
-    const int32_t K = S->K, cur = S->cur, t_limit = S->t_limit;
-    int32_t* g = cur ? S->f1 : S->f0;
+    int32_t t = uni(S->t);
+    const int32_t K = uni(S->K), cur = uni(S->cur), t_limit = uni(S->t_limit);
+    int32_t* g = const_cast<int32_t*>(uni(static_cast<const int32_t*>(cur ? S->f1 : S->f0)));
     if (tid == 0) RS.flag = 0;
     __syncthreads();
     if (t == 0) {
@@ -459,15 +517,16 @@ __device__ void solo_task(const TaskParams& P, int32_t pi, LdsState& L, JobCurso
 }
 
 __device__ void chunk_task(const TaskParams& P, int32_t pi, int32_t c, LdsState& L, JobCursor& jc,
-                           CountersDev& cnt) {
+                           Cnt& cnt) {
     TaskPair* S = P.pairs + pi;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const Engine en = make_engine(S->p, P.h, P.engine, P.lane_words, L.lut4);
     RoundShared& RS = L.rs;
-    const int32_t t = S->t, H = S->H, T = S->T, C = S->chunk, K = S->K, cur = S->cur;
+    const int32_t t = uni(S->t), H = uni(S->H), T = uni(S->T), C = uni(S->chunk), K = uni(S->K),
+                  cur = uni(S->cur);
     const int32_t gofs = K + 2;
-    const int32_t* gp = cur ? S->f1 : S->f0;
-    int32_t* gc = cur ? S->f0 : S->f1;
+    const int32_t* gp = uni(static_cast<const int32_t*>(cur ? S->f1 : S->f0));
+    int32_t* gc = const_cast<int32_t*>(uni(static_cast<const int32_t*>(cur ? S->f0 : S->f1)));
     const int32_t total = 2 * T + 5;
     const int32_t eb = c * C;
     const int32_t ee = imin(total, eb + C);
@@ -536,7 +595,9 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
     __shared__ LdsState L;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int G = gridDim.x;
-    CountersDev cnt = {};
+    Cnt cnt;
+    cnt_bind(cnt, &L.cnt);
+    cnt_init_shared(&L.cnt);
     JobCursor jc;
     rs_init(L.rs, jc);
     if (P.engine == 1) build_lut4(L.lut4, P.h.r, tid, nthr);
@@ -690,7 +751,9 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
 __global__ __launch_bounds__(kFrontierThreads) void task_kernel(TaskParams P) {
     __shared__ LdsState L;
     const int tid = threadIdx.x;
-    CountersDev cnt = {};
+    Cnt cnt;
+    cnt_bind(cnt, &L.cnt);
+    cnt_init_shared(&L.cnt);
     JobCursor jc;
     rs_init(L.rs, jc);
     if (P.engine == 1) build_lut4(L.lut4, P.h.r, tid, blockDim.x);
@@ -698,7 +761,7 @@ __global__ __launch_bounds__(kFrontierThreads) void task_kernel(TaskParams P) {
         __syncthreads();
         if (tid == 0) L.rs.task = q_pop(P);
         __syncthreads();
-        const long long task = L.rs.task;
+        const long long task = static_cast<long long>(uni(static_cast<uint64_t>(L.rs.task)));
         if (task < 0) break;
         const int32_t pi = static_cast<int32_t>(task & 0xFFFFFFFFll);
         const uint32_t c = static_cast<uint32_t>(static_cast<unsigned long long>(task) >> 32);
@@ -712,7 +775,10 @@ __global__ __launch_bounds__(kFrontierThreads) void task_kernel(TaskParams P) {
 
 __global__ __launch_bounds__(256) void lcp_query_kernel(LcpQueryParams Q) {
     __shared__ uint64_t lut4[256];
-    CountersDev cnt = {};
+    __shared__ CountersDev sh;
+    Cnt cnt;
+    cnt_bind(cnt, &sh);
+    cnt_init_shared(&sh);
     if (Q.engine == 1) build_lut4(lut4, Q.h.r, threadIdx.x, blockDim.x);
     __syncthreads();
     const Engine en = make_engine(Q.p, Q.h, Q.engine, Q.lane_words, lut4);
@@ -730,7 +796,6 @@ __global__ __launch_bounds__(256) void lcp_query_kernel(LcpQueryParams Q) {
 // Workgroup-tier LCP queries: one workgroup per query (tests of the tier).
 __global__ __launch_bounds__(kFrontierThreads) void lcp_query_wg_kernel(LcpQueryParams Q) {
     __shared__ int32_t wmin;
-    CountersDev cnt = {};
     const Engine en = make_engine(Q.p, Q.h, 0, Q.lane_words, nullptr);
     for (int64_t qi = blockIdx.x; qi < Q.count; qi += gridDim.x) {
         const int32_t x = static_cast<int32_t>(Q.x[qi]);
@@ -740,7 +805,6 @@ __global__ __launch_bounds__(kFrontierThreads) void lcp_query_wg_kernel(LcpQuery
         const int32_t l = lcp_wg_direct(en.A, en.B, x, y, lim, 0, wmin);
         if (threadIdx.x == 0) Q.out[qi] = l;
     }
-    (void)cnt;
 }
 
 hipError_t launch_ctl_init(FrontierCtl* ctl, CountersDev* cnt, unsigned int* bar, hipStream_t s) {

@@ -97,7 +97,9 @@ int tasks_run(ed_ctx* c, std::vector<TaskPair>& st, const std::vector<long long>
 long long task_solo(int32_t pi);
 long long task_chunk(int32_t pi, int32_t c);
 int32_t block_rounds_of(const ed_ctx* c);
-bool schedule_on_host(TaskPair& tp, int32_t pi, int32_t block_rounds, int64_t k_max,
+uint32_t task_solo_rounds(const ed_ctx* c);
+int32_t chunk_diags_of(const ed_ctx* c);
+bool schedule_on_host(TaskPair& tp, int32_t pi, int32_t block_rounds, int32_t chunk, int64_t k_max,
                       std::vector<long long>& tasks);
 int64_t batch_row_capacity(int64_t maxnm, int64_t k_max, uint32_t lds_rounds);
 }  // namespace ed

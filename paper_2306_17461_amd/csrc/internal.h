@@ -21,6 +21,11 @@ constexpr int kSegChars = 64;
 constexpr int kTileChars = kPrepThreads * kSegChars;  // 16384
 constexpr int kTileWords2 = kTileChars / 32;          // 512 packed words per tile
 constexpr int kTileWords8 = kTileChars / 8;           // 2048 byte-words per tile
+// Streaming pass: one wavefront per chunk of 64 lanes x 64 characters.
+constexpr int kChunkChars = 64 * kSegChars;           // 4096
+constexpr int kTileChunks = kTileChars / kChunkChars;  // 4
+constexpr int kChunkWords2 = kChunkChars / 32;        // 128
+constexpr int kChunkWords8 = kChunkChars / 8;         // 512
 // Words of zero padding after the last tile of every packed buffer.
 constexpr int kPadWords = 256;
 
@@ -32,7 +37,7 @@ constexpr uint64_t kTileValMask = (1ull << 61) - 1;
 
 // One string as the kernels see it.
 struct StrDev {
-    const uint64_t* w2;   // 2-bit packed words (always written)
+    const uint64_t* w2;   // 2-bit packed words (complete when the pair is packable)
     const uint64_t* w8;   // 8-bit copy as words (written when not packable)
     const uint64_t* tab;  // prefix table (hash engine) or nullptr
     int32_t len;
@@ -172,7 +177,7 @@ struct PrepParams {
     uint64_t* tile_status; // total_tiles entries, zeroed before launch
     unsigned int* ticket;  // tile ticket counter, zeroed before launch
     uint32_t* alpha;       // OR of all characters (atomicOr), zeroed before launch
-    uint8_t* tile_big;     // per tile: 1 if the tile has a character > 3
+    uint8_t* chunk_big;    // per chunk (kTileChunks per tile): 1 if it has a character > 3
     const uint64_t* rtab;  // r^0..r^64 | r^(64k), k = 0..256 | R^d, d = 0..64, R = r^kTileChars
 };
 
@@ -190,8 +195,9 @@ struct LcpQueryParams {
 
 // Kernel launchers (defined in the .hip files).
 hipError_t launch_prep_clear(const PrepParams& pp, hipStream_t s);
-hipError_t launch_prepare(const PrepParams& pp, int grid, hipStream_t s);
-hipError_t launch_copy8_rest(const PrepParams& pp, hipStream_t s);
+hipError_t launch_pack(const PrepParams& pp, int grid, hipStream_t s);
+hipError_t launch_table(const PrepParams& pp, int grid, hipStream_t s);
+hipError_t launch_copy8_rest(const PrepParams& pp, int grid, hipStream_t s);
 hipError_t launch_ctl_init(FrontierCtl* ctl, CountersDev* cnt, unsigned int* bar, hipStream_t s);
 hipError_t launch_frontier(const FrontierParams& fp, int grid, hipStream_t s);
 hipError_t frontier_max_grid(int device, int* grid_out);

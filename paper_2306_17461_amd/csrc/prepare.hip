@@ -1,13 +1,16 @@
-// Prepare: one pass over the input bytes of both strings of a pair.
-//   * alphabet detection: bitwise OR of every character (2-bit packing is
-//     possible when the OR is <= 3);
-//   * 2-bit packing (speculative: always written, used only when packable);
-//   * 8-bit copy of every tile holding a character > 3 (the rest of the copy,
-//     if needed, is written by a second, small kernel);
-//   * prefix table T[j] = h(S[0..jb)) mod 2^61-1 (sections 3.2 and 3.3,
-//     Algorithm 2 "Build"): block hashes from LDS lookup tables (h is linear in
-//     the characters), then a single-pass scan over tiles with decoupled
-//     look-back under the concatenation h(S1 S2) = h(S1) r^|S2| + h(S2).
+// Prepare a pair: the input bytes of both strings are read once.
+//   pack_kernel   streaming, one wavefront per 4096-character chunk, no LDS:
+//                 alphabet detection (bitwise OR of every character; 2-bit
+//                 packing is possible when the OR is <= 3), 2-bit packing of
+//                 every chunk without a character > 3, and an 8-bit copy of
+//                 every chunk with one (the rest of the copy, when the pair
+//                 cannot be packed, is written by copy8_rest_kernel);
+//   table_kernel  (hash engine) prefix table T[j] = h(S[0..jb)) mod 2^61-1
+//                 (sections 3.2 and 3.3, Algorithm 2 "Build") from the packed
+//                 words (or the 8-bit copy): block hashes from LDS lookup
+//                 tables (h is linear in the characters), then a single-pass
+//                 scan over tiles with decoupled look-back under the
+//                 concatenation h(S1 S2) = h(S1) r^|S2| + h(S2).
 #include "device.h"
 
 namespace ed {
@@ -26,7 +29,6 @@ struct PrepShared {
     uint64_t wsum[kPrepThreads / 64];
     uint64_t excl;
     int32_t tile;
-    uint32_t tor;
 };
 
 __device__ __forceinline__ uint32_t pack_dword(uint32_t d) {
@@ -66,7 +68,7 @@ __device__ __forceinline__ uint64_t seg_pass(const PrepShared& S, const uint32_t
             }
         } else {  // single characters
             for (int c = 0; c < 64; ++c) {
-                const uint64_t ch = (dw[c >> 2] >> (8 * (c & 3))) & 0xFFu;
+                const uint64_t ch = (pk[c >> 5] >> (2 * (c & 31))) & 3u;
                 h = mp_add(mp_mul(h, S.rp[1]), ch);
                 emit(c + 1);
             }
@@ -103,60 +105,29 @@ __device__ __forceinline__ uint64_t wave_sum_mod(uint64_t v) {
 
 __global__ void prep_clear_kernel(PrepParams P) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < P.total_tiles) {
-        P.tile_status[i] = 0;
-        P.tile_big[i] = 0;
-    }
+    if (i < P.total_tiles) P.tile_status[i] = 0;
     if (i == 0) {
         *P.ticket = 0u;
         *P.alpha = 0u;
     }
 }
 
-__global__ __launch_bounds__(kPrepThreads) void prepare_kernel(PrepParams P, const uint64_t* rtab) {
-    __shared__ PrepShared S;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-
-    if (P.build_table) {
-        // rtab: r^0..r^64 | r^(64k), k = 0..256 | R^d, d = 0..64
-        for (int i = tid; i < 65; i += kPrepThreads) S.rp[i] = rtab[i];
-        for (int i = tid; i < 257; i += kPrepThreads) S.rseg[i] = rtab[65 + i];
-        for (int i = tid; i < 65; i += kPrepThreads) S.tilepow[i] = rtab[65 + 257 + i];
-        __syncthreads();
-        for (int e = tid; e < 8 * 256; e += kPrepThreads) {
-            const int k = e >> 8, v = e & 255;
-            uint64_t h = 0;
-            for (int j = 0; j < 4; ++j)
-                h = mp_add(h, mp_mul(static_cast<uint64_t>((v >> (2 * j)) & 3), S.rp[31 - 4 * k - j]));
-            S.lut32[k][v] = h;
-            S.lut8[k][v] = mp_mul(static_cast<uint64_t>(v), S.rp[7 - k]);
-        }
-        for (int v = tid; v < 256; v += kPrepThreads) {
-            uint64_t h = 0;
-            for (int j = 0; j < 4; ++j)
-                h = mp_add(h, mp_mul(static_cast<uint64_t>((v >> (2 * j)) & 3), S.rp[3 - j]));
-            S.lut4[v] = h;
-        }
-    }
-
-    for (;;) {
-        __syncthreads();
-        if (tid == 0) {
-            S.tile = static_cast<int32_t>(atomicAdd(P.ticket, 1u));
-            S.tor = 0u;
-        }
-        __syncthreads();
-        const int32_t g = S.tile;
-        if (g >= P.total_tiles) break;
-        const int si = g >= P.s[1].tile0 ? 1 : 0;
+// Streaming pass: wavefront w takes chunks w, w + W, ... (W wavefronts in the
+// grid); lane l holds characters [64 l, 64 l + 64) of its chunk.  Chunk slots
+// past the end of a string are written as zeros (padding the last tile).
+__global__ __launch_bounds__(kPrepThreads) void pack_kernel(PrepParams P) {
+    const int lane = threadIdx.x & 63;
+    const int32_t wave = static_cast<int32_t>((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int32_t nwaves = static_cast<int32_t>((gridDim.x * blockDim.x) >> 6);
+    const int32_t total = P.total_tiles * kTileChunks;
+    const int32_t split = P.s[1].tile0 * kTileChunks;
+    uint32_t orr = 0;
+    for (int32_t g = wave; g < total; g += nwaves) {
+        const int si = g >= split ? 1 : 0;
         const PrepString& str = P.s[si];
-        const int32_t t = g - str.tile0;
-        const int32_t seg_start = t * kTileChars + tid * kSegChars;
+        const int32_t c = g - str.tile0 * kTileChunks;
+        const int32_t seg_start = c * kChunkChars + lane * kSegChars;
         const int32_t len = str.len;
-
-        // ---- load 64 characters (zero beyond the string) ----
         uint32_t dw[16];
         if (seg_start + kSegChars <= len) {
             const u32x4* src = reinterpret_cast<const u32x4*>(str.raw + seg_start);
@@ -179,46 +150,113 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(PrepParams P, con
                 dw[k] = d;
             }
         }
-
-        // ---- alphabet OR ----
         uint32_t o = 0;
 #pragma unroll
         for (int k = 0; k < 16; ++k) o |= dw[k];
-        o |= o >> 16;
-        o |= o >> 8;
-        o &= 0xFFu;
-        for (int s = 32; s > 0; s >>= 1) o |= __shfl_xor(o, s);
-        if (lane == 0) atomicOr(&S.tor, o);
-
-        // ---- 2-bit pack: 32 characters per word ----
-        uint64_t pk[2];
+        orr |= o;
+        const bool big = ballot((o & 0xFCFCFCFCu) != 0u) != 0;
+        if (!big) {
+            uint64_t pk[2];
 #pragma unroll
-        for (int w = 0; w < 2; ++w) {
-            uint64_t v = 0;
+            for (int w = 0; w < 2; ++w) {
+                uint64_t v = 0;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) v |= static_cast<uint64_t>(pack_dword(dw[8 * w + k])) << (8 * k);
-            pk[w] = v;
+                for (int k = 0; k < 8; ++k) v |= static_cast<uint64_t>(pack_dword(dw[8 * w + k])) << (8 * k);
+                pk[w] = v;
+            }
+            u32x4 st;
+            st.x = static_cast<uint32_t>(pk[0]);
+            st.y = static_cast<uint32_t>(pk[0] >> 32);
+            st.z = static_cast<uint32_t>(pk[1]);
+            st.w = static_cast<uint32_t>(pk[1] >> 32);
+            *reinterpret_cast<u32x4*>(str.w2 + static_cast<int64_t>(c) * kChunkWords2 + lane * 2) = st;
         }
-        {
-            uint64_t* dst = str.w2 + static_cast<int64_t>(t) * kTileWords2 + tid * 2;
-            dst[0] = pk[0];
-            dst[1] = pk[1];
-        }
-        __syncthreads();
-        const uint32_t tor = S.tor;
-        const bool big = tor > 3u;
-        if (tid == 0) {
-            if (tor) atomicOr(P.alpha, tor);
-            P.tile_big[g] = big ? 1 : 0;
-        }
-        // ---- 8-bit copy of tiles that cannot be packed ----
         if (big || P.force8) {
-            uint64_t* dst = str.w8 + static_cast<int64_t>(t) * kTileWords8 + tid * 8;
+            u32x4* dst = reinterpret_cast<u32x4*>(str.w8 + static_cast<int64_t>(c) * kChunkWords8 + lane * 8);
 #pragma unroll
-            for (int k = 0; k < 8; ++k)
-                dst[k] = static_cast<uint64_t>(dw[2 * k]) | (static_cast<uint64_t>(dw[2 * k + 1]) << 32);
+            for (int k = 0; k < 4; ++k) {
+                u32x4 v;
+                v.x = dw[4 * k + 0];
+                v.y = dw[4 * k + 1];
+                v.z = dw[4 * k + 2];
+                v.w = dw[4 * k + 3];
+                dst[k] = v;
+            }
         }
-        if (!P.build_table) continue;
+        if (lane == 0) P.chunk_big[g] = big ? 1 : 0;
+    }
+    orr |= orr >> 16;
+    orr |= orr >> 8;
+    orr &= 0xFFu;
+    for (int s = 32; s > 0; s >>= 1) orr |= __shfl_xor(orr, s);
+    if (lane == 0 && orr) atomicOr(P.alpha, orr);
+}
+
+// Prefix tables of both strings (hash engine), after pack_kernel (and
+// copy8_rest_kernel): reads the 2-bit words when the pair is packable, the
+// 8-bit copy otherwise.  Tiles of 16384 characters are taken in ticket order,
+// so every tile that a look-back waits on is already running.
+__global__ __launch_bounds__(kPrepThreads) void table_kernel(PrepParams P, const uint64_t* rtab) {
+    __shared__ PrepShared S;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const bool two = *P.alpha <= 3u;
+
+    // rtab: r^0..r^64 | r^(64k), k = 0..256 | R^d, d = 0..64
+    for (int i = tid; i < 65; i += kPrepThreads) S.rp[i] = rtab[i];
+    for (int i = tid; i < 257; i += kPrepThreads) S.rseg[i] = rtab[65 + i];
+    for (int i = tid; i < 65; i += kPrepThreads) S.tilepow[i] = rtab[65 + 257 + i];
+    __syncthreads();
+    for (int e = tid; e < 8 * 256; e += kPrepThreads) {
+        const int k = e >> 8, v = e & 255;
+        uint64_t h = 0;
+        for (int j = 0; j < 4; ++j)
+            h = mp_add(h, mp_mul(static_cast<uint64_t>((v >> (2 * j)) & 3), S.rp[31 - 4 * k - j]));
+        S.lut32[k][v] = h;
+        S.lut8[k][v] = mp_mul(static_cast<uint64_t>(v), S.rp[7 - k]);
+    }
+    for (int v = tid; v < 256; v += kPrepThreads) {
+        uint64_t h = 0;
+        for (int j = 0; j < 4; ++j)
+            h = mp_add(h, mp_mul(static_cast<uint64_t>((v >> (2 * j)) & 3), S.rp[3 - j]));
+        S.lut4[v] = h;
+    }
+
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) S.tile = static_cast<int32_t>(atomicAdd(P.ticket, 1u));
+        __syncthreads();
+        const int32_t g = S.tile;
+        if (g >= P.total_tiles) break;
+        const int si = g >= P.s[1].tile0 ? 1 : 0;
+        const PrepString& str = P.s[si];
+        const int32_t t = g - str.tile0;
+        const int32_t seg_start = t * kTileChars + tid * kSegChars;
+        const int32_t len = str.len;
+        const bool big = !two;
+
+        // the 64 characters of this thread (zero past the string)
+        uint32_t dw[16];
+        uint64_t pk[2];
+        if (two) {
+            const u32x4 v = *reinterpret_cast<const u32x4*>(str.w2 + static_cast<int64_t>(t) * kTileWords2 + tid * 2);
+            pk[0] = static_cast<uint64_t>(v.x) | (static_cast<uint64_t>(v.y) << 32);
+            pk[1] = static_cast<uint64_t>(v.z) | (static_cast<uint64_t>(v.w) << 32);
+#pragma unroll
+            for (int k = 0; k < 16; ++k) dw[k] = 0;
+        } else {
+            const u32x4* src = reinterpret_cast<const u32x4*>(str.w8 + static_cast<int64_t>(t) * kTileWords8 + tid * 8);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const u32x4 v = src[k];
+                dw[4 * k + 0] = v.x;
+                dw[4 * k + 1] = v.y;
+                dw[4 * k + 2] = v.z;
+                dw[4 * k + 3] = v.w;
+            }
+            pk[0] = pk[1] = 0;
+        }
 
         // ---- segment hash, block-scan within the tile ----
         const uint64_t hseg = seg_pass<false>(S, dw, pk, big, P.log2b, 0, seg_start, len, nullptr);
@@ -282,25 +320,31 @@ __global__ __launch_bounds__(kPrepThreads) void prepare_kernel(PrepParams P, con
     }
 }
 
-// Second pass for strings that cannot be packed: 8-bit copy of the tiles the
-// first pass skipped.  One workgroup per tile; exits at once when packable.
+// Second pass for pairs that cannot be packed: 8-bit copy of the chunks the
+// first pass packed instead.  Exits at once when the pair is packable.
 __global__ __launch_bounds__(kPrepThreads) void copy8_rest_kernel(PrepParams P) {
     const uint32_t alpha = *P.alpha;
     if (alpha <= 3u || P.force8) return;
-    const int32_t g = blockIdx.x;
-    if (g >= P.total_tiles || P.tile_big[g]) return;
-    const int si = g >= P.s[1].tile0 ? 1 : 0;
-    const PrepString& str = P.s[si];
-    const int32_t t = g - str.tile0;
-    const int32_t seg_start = t * kTileChars + threadIdx.x * kSegChars;
-    uint64_t* dst = str.w8 + static_cast<int64_t>(t) * kTileWords8 + threadIdx.x * 8;
-    for (int k = 0; k < 8; ++k) {
-        uint64_t v = 0;
-        for (int j = 0; j < 8; ++j) {
-            const int32_t p = seg_start + 8 * k + j;
-            if (p < str.len) v |= static_cast<uint64_t>(str.raw[p]) << (8 * j);
+    const int lane = threadIdx.x & 63;
+    const int32_t wave = static_cast<int32_t>((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int32_t nwaves = static_cast<int32_t>((gridDim.x * blockDim.x) >> 6);
+    const int32_t total = P.total_tiles * kTileChunks;
+    const int32_t split = P.s[1].tile0 * kTileChunks;
+    for (int32_t g = wave; g < total; g += nwaves) {
+        if (P.chunk_big[g]) continue;
+        const int si = g >= split ? 1 : 0;
+        const PrepString& str = P.s[si];
+        const int32_t c = g - str.tile0 * kTileChunks;
+        const int32_t seg_start = c * kChunkChars + lane * kSegChars;
+        uint64_t* dst = str.w8 + static_cast<int64_t>(c) * kChunkWords8 + lane * 8;
+        for (int k = 0; k < 8; ++k) {
+            uint64_t v = 0;
+            for (int j = 0; j < 8; ++j) {
+                const int32_t p = seg_start + 8 * k + j;
+                if (p < str.len) v |= static_cast<uint64_t>(str.raw[p]) << (8 * j);
+            }
+            dst[k] = v;
         }
-        dst[k] = v;
     }
 }
 
@@ -322,13 +366,18 @@ hipError_t launch_prep_clear(const PrepParams& pp, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_prepare(const PrepParams& pp, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(prepare_kernel, dim3(grid), dim3(kPrepThreads), 0, s, pp, pp.rtab);
+hipError_t launch_pack(const PrepParams& pp, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(pack_kernel, dim3(grid), dim3(kPrepThreads), 0, s, pp);
     return hipGetLastError();
 }
 
-hipError_t launch_copy8_rest(const PrepParams& pp, hipStream_t s) {
-    hipLaunchKernelGGL(copy8_rest_kernel, dim3(pp.total_tiles), dim3(kPrepThreads), 0, s, pp);
+hipError_t launch_table(const PrepParams& pp, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(table_kernel, dim3(grid), dim3(kPrepThreads), 0, s, pp, pp.rtab);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy8_rest(const PrepParams& pp, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(copy8_rest_kernel, dim3(grid), dim3(kPrepThreads), 0, s, pp);
     return hipGetLastError();
 }
 

@@ -94,7 +94,7 @@ uint64_t request_bytes(const ed_ctx* c, uint64_t n, uint64_t m, int64_t K) {
 }
 
 int64_t serve_rows(const ed_ctx* c, int64_t maxnm) {
-    const int64_t solo = c->opt.lds_rounds ? c->opt.lds_rounds : kDefaultLdsRounds;
+    const int64_t solo = task_solo_rounds(c);
     // every slot can save its frontier at any round up to the whole-pair limit
     int64_t K = std::max<int64_t>(std::min<int64_t>(maxnm, 2 * solo), maxnm / 16);
     return std::max<int64_t>(1, std::min<int64_t>(K, maxnm));
@@ -187,7 +187,7 @@ int serve_step(ed_server* S, std::vector<Request>& admitted_now) {
     }
     if (S->slots.empty()) return ED_OK;
     // one launch over every active slot
-    const int32_t solo = static_cast<int32_t>(c->opt.lds_rounds ? c->opt.lds_rounds : kDefaultLdsRounds);
+    const int32_t solo = static_cast<int32_t>(task_solo_rounds(c));
     const int32_t br = block_rounds_of(c);
     std::vector<TaskPair> st;
     std::vector<long long> tasks;
@@ -207,7 +207,7 @@ int serve_step(ed_server* S, std::vector<Request>& admitted_now) {
         const int32_t pi = static_cast<int32_t>(st.size());
         if (tp.t <= solo && tp.t <= kLdsRoundsMax) {
             tasks.push_back(task_solo(pi));
-        } else if (!schedule_on_host(tp, pi, br, -1, tasks)) {
+        } else if (!schedule_on_host(tp, pi, br, chunk_diags_of(c), -1, tasks)) {
             sl.st.status = 4;
             continue;
         }

@@ -59,7 +59,8 @@ def unpack2(words_u8, n):
 # ---------------------------------------------------------------------------
 # pack, copy, alphabet detection
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("n", [0, 1, 31, 32, 33, 1000, 16383, 16384, 16385, 100003])
+@pytest.mark.parametrize("n", [0, 1, 31, 32, 33, 1000, 4095, 4096, 4097, 8193, 16383, 16384, 16385,
+                               100003])
 def test_pack_roundtrip(ed, make_ctx, n):
     say("pack", n)
     ctx = make_ctx()
@@ -73,7 +74,7 @@ def test_pack_roundtrip(ed, make_ctx, n):
     ed.ed_release(p)
 
 
-@pytest.mark.parametrize("case", ["sigma256", "mixed", "force8"])
+@pytest.mark.parametrize("case", ["sigma256", "mixed", "mixed_tail", "force8"])
 def test_byte_copy(ed, make_ctx, case):
     say("bytes", case)
     n = 50000
@@ -87,6 +88,13 @@ def test_byte_copy(ed, make_ctx, case):
         A = synth.random_string(n, synth.CharDist("uniform", 4), 3)
         B = synth.random_string(n, synth.CharDist("uniform", 4), 4)
         B[40000] = 200
+    elif case == "mixed_tail":
+        # large characters only in the last, partial chunk of A and the first chunk of B
+        ctx = make_ctx()
+        A = synth.random_string(n + 17, synth.CharDist("uniform", 4), 9)
+        B = synth.random_string(n - 3, synth.CharDist("uniform", 4), 10)
+        A[-1] = 4
+        B[0] = 255
     else:
         ctx = make_ctx(pack_bits=8)
         A = synth.random_string(n, synth.CharDist("uniform", 4), 5)
@@ -342,6 +350,35 @@ def test_batch_matches_oracle_and_single(ed, make_ctx, orc, engine):
     # k_max cutoff inside the batch
     got5, _ = ed.ed_batch(ctx, pairs, k_max=50)
     assert got5 == [min(w, 51) for w in want]
+    for p in pairs:
+        ed.ed_release(p)
+
+
+@pytest.mark.parametrize("engine", [0, 1])
+def test_autotune_batch(ed, make_ctx, orc, engine):
+    # the tuner times every candidate, keeps the distances identical and
+    # leaves the winner in the context; the batch still matches the oracle
+    ctx = make_ctx(engine=engine)
+    specs = synth.batch_specs(96, 17, lo_exp=2.0, hi_exp=4.5, kfrac=0.05)
+    pairs, want = [], []
+    for n, k, ps in specs:
+        A, B, _ = synth.single_pair(n, k, ps)
+        pairs.append(ed.ed_prepare(ctx, A, B))
+        want.append(orc.lv_omp(A, B))
+    say("autotune", engine, len(pairs))
+    r = ed.ed_autotune_batch(ctx, pairs, passes=1)
+    kn = r["knobs"]
+    assert r["evaluated"] >= 3 and r["best_ms"] > 0 and r["best_ms"] <= r["default_ms"] * 1.0001
+    assert kn["chunk_diags"] + 2 * kn["task_block_rounds"] <= 2 * 4096 + 5
+    opts = ed.ed_get_options(ctx)
+    assert {k: opts[k] for k in kn} == kn
+    got, st = ed.ed_batch(ctx, pairs)
+    assert st == [0] * len(pairs) and got == want
+    # k_max is honoured while tuning
+    r2 = ed.ed_autotune_batch(ctx, pairs[:20], k_max=5, passes=1)
+    assert r2["evaluated"] >= 3
+    got2, _ = ed.ed_batch(ctx, pairs[:20], k_max=5)
+    assert got2 == [min(w, 6) for w in want[:20]]
     for p in pairs:
         ed.ed_release(p)
 
