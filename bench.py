@@ -103,6 +103,40 @@ def batch_leg(ed, ctx, count=4096, seed=0):
             "speedup": tp / tb, "equal_to_stored_oracle": exact}
 
 
+def lcp_leg(ed, n=10 ** 9):
+    """LCP extension bandwidth: one LCP over n equal characters on the direct
+    engine's grid tier, at 2 and 8 bits per character.  Bytes = both strings'
+    packed words over the matched length, per query."""
+    import numpy as np
+    import torch
+    import synth
+    out = []
+    for bits, dist in ((2, synth.CharDist("uniform", 4)), (8, synth.CharDist("zipf", 256))):
+        A = synth.periodic_string(n, dist, 7, period=4096)
+        B = A.copy()
+        B[n - 1] ^= 1  # the single mismatch: LCP(0, 0) = n - 1
+        tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        del A, B
+        ctx = ed.ed_init(0, pack_bits=bits, flags=ed.FLAG_TIMING)
+        p = ed.ed_prepare(ctx, tA, tB)
+        del tA, tB
+        ed.ed_debug_lcp(ctx, p, [0], [0], engine=3)  # warm-up
+        best = None
+        for _ in range(3):
+            got = ed.ed_debug_lcp(ctx, p, [0], [0], engine=3)
+            ns = ed.ed_pair_stats(p)["gpu_ns_lcp_kernel"]
+            best = ns if best is None else min(best, ns)
+        if int(got[0]) != n - 1:
+            raise SystemExit("grid LCP returned %d, want %d" % (int(got[0]), n - 1))
+        byts = 2 * (n - 1) * bits / 8
+        out.append({"bits_per_char": bits, "lcp_chars": n - 1, "bytes": byts, "kernel_ms": round(best / 1e6, 4),
+                    "achieved_GBs": round(byts / best, 1), "frac_of_hbm_peak": round(byts / best / PEAK_HBM_GBS, 4)})
+        ed.ed_release(p)
+        ed.ed_shutdown(ctx)
+        torch.cuda.empty_cache()
+    return out
+
+
 def serve_leg(ed, ctx, count, seed=0, warmup=0):
     """Served workload: Poisson arrivals, n = floor(10^U), U ~ U[2, 7], alphabet 4
     or 20, k ~ U{0..floor(0.05 n)}.  The arrival rate is 0.7x the batched
@@ -196,6 +230,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-other-engine", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 4096-pair batch leg")
+    ap.add_argument("--no-lcp", action="store_true", help="skip the long-LCP bandwidth leg")
     ap.add_argument("--serve", type=int, default=0, metavar="N",
                     help="also run the serving leg with N requests")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -275,7 +310,8 @@ def main():
             "rounds": st["rounds"], "updates": st["updates"],
             "us_per_round": round(front_ns[i] / 1e3 / max(1, st["rounds"]), 4),
             "updates_per_s": st["updates"] / (front_ns[i] / 1e9) if front_ns[i] else None,
-            "lcp_chars": st["lcp_chars"], "wave_lcps": st["wave_lcps"], "wg_lcps": st["grid_lcps"],
+            "lcp_chars": st["lcp_chars"], "wave_lcps": st["wave_lcps"], "wg_lcps": st["wg_lcps"],
+            "grid_lcps": st["grid_lcps"],
             "rounds_phase_a": st["rounds_phase_a"], "us_phase_a": round(st["us_phase_a"], 2),
             "us_phase_b": round(st["us_phase_b"], 2),
             "chars_per_s": n / (wall / 1e3) if wall else None,
@@ -348,6 +384,10 @@ def main():
     batch = None
     if not args.no_batch:
         batch = batch_leg(ed, ctxs["direct"])
+    lcp = None
+    if not args.no_lcp:
+        log("lcp leg: one LCP of 1e9 characters on the grid tier")
+        lcp = lcp_leg(ed)
     serve = None
     if args.serve > 0:
         serve = serve_leg(ed, ctxs["direct"], args.serve)
@@ -385,6 +425,7 @@ def main():
         "cpu_baseline": cpu,
         "other_engine": other,
         "batch": batch,
+        "lcp_extension": lcp,
         "serve": serve,
     }
     print(json.dumps(line))

@@ -157,7 +157,7 @@ typedef struct ed_stats {
     uint64_t updates;         /* diagonal updates over all rounds */
     uint64_t lcp_chars;       /* sum of all slides */
     uint64_t wave_lcps;       /* LCPs handed from a lane to a whole wave */
-    uint64_t grid_lcps;       /* LCPs handed to the whole grid */
+    uint64_t grid_lcps;       /* LCPs handed to the whole grid (grid tier) */
     uint64_t hash_queries;    /* LCPs answered by the hash engine */
     uint64_t hash_probes;     /* hash equality tests */
     uint64_t collisions;      /* detected collisions (fell back to the direct engine) */
@@ -171,6 +171,10 @@ typedef struct ed_stats {
      * in the one-workgroup phase and in the grid-wide phase */
     uint64_t rounds_phase_a;
     double us_phase_a, us_phase_b;
+    /* with ED_FLAG_TIMING: HIP-event time of the last ed_debug_lcp call on the
+     * grid tier (engine 3), all its queries */
+    double gpu_ns_lcp_kernel;
+    uint64_t wg_lcps;         /* LCPs extended by a whole workgroup (workgroup tier) */
 } ed_stats;
 
 int ed_pair_stats(const ed_pair *pair, ed_stats *out);
@@ -206,10 +210,15 @@ int ed_pair_buffer(ed_ctx *ctx, const ed_pair *pair, int which, int kind, void *
                    uint64_t *len_out);
 
 /* Runs the pair's LCP engine on `count` queries (x[i], y[i]) (host arrays) and
- * writes LCP(A, B, x[i], y[i]) to out[i].  engine overrides the prepared
- * engine when it is 0 or 1 (1 needs tables), or uses it when -1.  Each query
- * runs on one wavefront, through the same lane, wave and hash code as the
- * frontier kernels. */
+ * writes LCP(A, B, x[i], y[i]) to out[i] (section 2's LCP; 0 <= x[i] <= n,
+ * 0 <= y[i] <= m, else ED_EINVAL).  engine: -1 = the prepared engine; 0 = the
+ * direct engine's lane and wave tiers, one wavefront per query; 1 = the hash
+ * engine (needs tables), one wavefront per query; 2 = the direct engine's
+ * workgroup tier, one workgroup per query; 3 = the direct engine's grid tier,
+ * every workgroup of the device on one query at a time (segments taken in
+ * order from a ticket, first mismatch by a shared minimum), timed with
+ * ED_FLAG_TIMING into ed_stats.gpu_ns_lcp_kernel.  The same device code as
+ * the frontier kernels. */
 int ed_debug_lcp(ed_ctx *ctx, ed_pair *pair, int engine, const int64_t *x, const int64_t *y,
                  uint64_t count, int64_t *out, void *hip_stream);
 

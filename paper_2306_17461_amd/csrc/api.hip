@@ -222,7 +222,7 @@ int ed_init(ed_ctx** out, int device, const ed_options* opt) {
     if (task_max_grid(device, &tg) != hipSuccess || tg < 1) tg = c->num_cu;
     c->task_grid_max = tg;
     if (hipMalloc(&c->d_ctl, sizeof(FrontierCtl)) != hipSuccess ||
-        hipMalloc(&c->d_cnt, sizeof(CountersDev)) != hipSuccess ||
+        hipMalloc(&c->d_cnt, sizeof(CountersDev) * (kMaxGrid + 1)) != hipSuccess ||
         hipHostMalloc(&c->h_ctl, sizeof(FrontierCtl)) != hipSuccess ||
         hipHostMalloc(&c->h_cnt, sizeof(CountersDev)) != hipSuccess ||
         hipMalloc(&c->d_bar, static_cast<size_t>(kMaxGrid) * kBarStride * 4) != hipSuccess) {
@@ -364,7 +364,11 @@ int ed::prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B
         }
     }
     const int32_t total = tiles[0] + tiles[1];
-    p->misc = c->pool.get(kMiscAlpha + 64 + static_cast<size_t>(total) * (8 + kTileChunks));
+    // alphabet word | tile hashes | chunk flags | tile prefixes
+    const size_t agg_off = kMiscAlpha + 64;
+    const size_t big_off = agg_off + static_cast<size_t>(total) * 8;
+    const size_t pre_off = big_off + ((static_cast<size_t>(total) * kTileChunks + 7) & ~size_t(7));
+    p->misc = c->pool.get(pre_off + static_cast<size_t>(total) * 8);
     if (!p->misc) {
         pair_free(p);
         delete p;
@@ -413,14 +417,14 @@ int ed::prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B
     pp.force8 = p->force8;
     pp.build_table = table ? 1 : 0;
     pp.r = c->r;
-    pp.tile_status = reinterpret_cast<uint64_t*>(misc + kMiscAlpha + 64);
-    pp.ticket = reinterpret_cast<unsigned int*>(misc + kMiscTicket);
+    pp.tile_agg = reinterpret_cast<uint64_t*>(misc + agg_off);
+    pp.tile_prefix = reinterpret_cast<uint64_t*>(misc + pre_off);
     pp.alpha = reinterpret_cast<uint32_t*>(misc + kMiscAlpha);
-    pp.chunk_big = reinterpret_cast<uint8_t*>(misc + kMiscAlpha + 64 + static_cast<size_t>(total) * 8);
+    pp.chunk_big = reinterpret_cast<uint8_t*>(misc + big_off);
     pp.rtab = c->d_pow + 2 * 65536;
     // streaming kernels: enough wavefronts to keep every CU full, each taking
     // several chunks; the table kernel: a few tiles in flight per CU
-    const int stream_grid = std::max(1, std::min(total, c->num_cu * 8));
+    const int stream_grid = std::max(1, std::min(total, c->num_cu * 2));
     const int table_grid = std::max(1, std::min(total, c->num_cu * 4));
     HIP_TRY(launch_prep_clear(pp, s));
     if (c->opt.flags & ED_FLAG_TIMING) {
@@ -430,7 +434,8 @@ int ed::prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B
         p->prep_timed = true;
     }
     HIP_TRY(launch_pack(pp, stream_grid, s));
-    if (c->opt.pack_bits != 2) HIP_TRY(launch_copy8_rest(pp, stream_grid, s));
+    // usually exits at once (packable pair): a small grid keeps that cheap
+    if (c->opt.pack_bits != 2) HIP_TRY(launch_copy8_rest(pp, std::max(1, std::min(total, c->num_cu)), s));
     if (table) HIP_TRY(launch_table(pp, table_grid, s));
     if (p->prep_timed) HIP_TRY(hipEventRecord(p->ev_prep[1], s));
     p->launches_prepare = 2 + (c->opt.pack_bits != 2 ? 1 : 0) + (table ? 1 : 0);
@@ -552,8 +557,10 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
         if (e == hipSuccess && timed) e = hipEventRecord(c->ev[0], s);
         if (e == hipSuccess) e = launch_frontier(fp, frontier_grid(c), s);
         if (e == hipSuccess && timed) e = hipEventRecord(c->ev[1], s);
+        if (e == hipSuccess) e = launch_counters_sum(c->d_cnt, s);
         if (e == hipSuccess) e = hipMemcpyAsync(c->h_ctl, c->d_ctl, sizeof(FrontierCtl), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(c->h_cnt, c->d_cnt, sizeof(CountersDev), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->h_cnt, c->d_cnt + kMaxGrid, sizeof(CountersDev), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) {
             set_error("ed_distance: frontier launch failed: %s", hipGetErrorString(e));
@@ -570,6 +577,7 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
         total.lcp_chars += cd.lcp_chars;
         total.wave_lcps += cd.wave_lcps;
         total.grid_lcps += cd.grid_lcps;
+        total.wg_lcps += cd.wg_lcps;
         total.hash_queries += cd.hash_queries;
         total.hash_probes += cd.hash_probes;
         total.hash_eq_len += cd.hash_eq_len;
@@ -693,6 +701,7 @@ int ed_pair_stats(const ed_pair* p, ed_stats* o) {
     o->lcp_chars = p->counters.lcp_chars;
     o->wave_lcps = p->counters.wave_lcps;
     o->grid_lcps = p->counters.grid_lcps;
+    o->wg_lcps = p->counters.wg_lcps;
     o->hash_queries = p->counters.hash_queries;
     o->hash_probes = p->counters.hash_probes;
     o->collisions = p->counters.collisions;
@@ -703,6 +712,7 @@ int ed_pair_stats(const ed_pair* p, ed_stats* o) {
     o->ns_prepare = p->ns_prepare;
     o->ns_distance = p->ns_distance;
     o->gpu_ns_frontier_kernel = p->gpu_ns_frontier;
+    o->gpu_ns_lcp_kernel = p->gpu_ns_lcp;
     o->rounds_phase_a = p->rounds_phase_a;
     o->us_phase_a = p->us_phase_a;
     o->us_phase_b = p->us_phase_b;
@@ -753,7 +763,7 @@ int ed_pair_buffer(ed_ctx* c, const ed_pair* p, int which, int kind, void* out, 
 int ed_debug_lcp(ed_ctx* c, ed_pair* p, int engine, const int64_t* x, const int64_t* y,
                  uint64_t count, int64_t* out, void* hip_stream) {
     if (!c || !p || (count && (!x || !y || !out))) return ED_EINVAL;
-    if (engine < -1 || engine > 2) return ED_EINVAL;
+    if (engine < -1 || engine > 3) return ED_EINVAL;
     std::lock_guard<std::mutex> lk(c->mu);
     HIP_TRY(hipSetDevice(c->device));
     const int eng = engine < 0 ? static_cast<int>(p->engine) : engine;
@@ -774,11 +784,12 @@ int ed_debug_lcp(ed_ctx* c, ed_pair* p, int engine, const int64_t* x, const int6
         if (rc != ED_OK) return rc;
     }
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    void* buf = c->pool.get(count * 24);
+    void* buf = c->pool.get(count * 28);
     if (!buf) return ED_ENOMEM;
     int64_t* dx = static_cast<int64_t*>(buf);
     int64_t* dy = dx + count;
     int64_t* dout = dy + count;
+    int32_t* dresult = reinterpret_cast<int32_t*>(dout + count);
     LcpQueryParams q;
     std::memset(&q, 0, sizeof q);
     q.p = pair_dev(p);
@@ -790,14 +801,39 @@ int ed_debug_lcp(ed_ctx* c, ed_pair* p, int engine, const int64_t* x, const int6
     q.engine = eng;
     q.lane_words = c->opt.lane_words ? static_cast<int32_t>(c->opt.lane_words) : (eng == 1 ? 1 : 2);
     q.counters = c->d_cnt;
+    q.result = dresult;
     hipError_t e = hipMemcpyAsync(dx, x, count * 8, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(dy, y, count * 8, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_ctl_init(c->d_ctl, c->d_cnt, nullptr, s);
-    if (e == hipSuccess) e = launch_lcp_queries(q, s);
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    const bool timed = (c->opt.flags & ED_FLAG_TIMING) != 0;
+    if (eng == 3) {
+        // grid tier: one launch per query over the whole grid
+        if (e == hipSuccess) e = launch_fill_i32(dresult, static_cast<int64_t>(count), INT32_MAX, s);
+        if (e == hipSuccess && timed) e = hipEventCreate(&ev[0]);
+        if (e == hipSuccess && timed) e = hipEventCreate(&ev[1]);
+        if (e == hipSuccess && timed) e = hipEventRecord(ev[0], s);
+        for (uint64_t i = 0; i < count && e == hipSuccess; ++i) {
+            q.query = static_cast<int64_t>(i);
+            e = launch_lcp_grid(q, c->num_cu, s);
+        }
+        if (e == hipSuccess && timed) e = hipEventRecord(ev[1], s);
+        if (e == hipSuccess) e = launch_lcp_grid_finish(q, s);
+    } else if (e == hipSuccess) {
+        e = launch_lcp_queries(q, s);
+    }
     if (e == hipSuccess) e = hipMemcpyAsync(out, dout, count * 8, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(c->h_cnt, c->d_cnt, sizeof(CountersDev), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = launch_counters_sum(c->d_cnt, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->h_cnt, c->d_cnt + kMaxGrid, sizeof(CountersDev), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     c->pool.put(buf);
+    if (e == hipSuccess && timed && ev[1]) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) p->gpu_ns_lcp = 1e6 * ms;
+    }
+    for (hipEvent_t v : ev)
+        if (v) hipEventDestroy(v);
     if (e != hipSuccess) {
         set_error("ed_debug_lcp: %s", hipGetErrorString(e));
         return ED_EDEVICE;

@@ -126,6 +126,15 @@ __device__ __forceinline__ int32_t lcp_wave_direct(const SView& A, const SView& 
     return lim;
 }
 
+// Minimum over the 64 lanes of a wavefront.
+__device__ __forceinline__ int32_t wave_min(int32_t v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const int32_t u = __shfl_xor(v, o);
+        v = u < v ? u : v;
+    }
+    return v;
+}
+
 // Engine (a), wave tier with a step budget: at most `steps` steps of 4 words
 // per lane (8192 characters at 2-bit, 2048 at 8-bit per step).  Returns the
 // matched length; `done` tells whether the LCP is complete.
@@ -136,12 +145,11 @@ __device__ __forceinline__ int32_t lcp_wave_steps(const SView& A, const SView& B
     const int32_t cpw = 1 << A.lcpw;
     for (int s = 0; s < steps && l < lim; ++s) {
         uint64_t d[W];
-        int32_t p[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-            p[w] = l + (w * 64 + lane) * cpw;
-            const bool ok = p[w] < lim;
-            const int32_t q = ok ? p[w] : 0;
+            const int32_t p = l + (w * 64 + lane) * cpw;
+            const bool ok = p < lim;
+            const int32_t q = ok ? p : 0;
             const uint64_t v = fetch(A, x + q) ^ fetch(B, y + q);
             d[w] = ok ? v : 0;
         }
@@ -150,7 +158,7 @@ __device__ __forceinline__ int32_t lcp_wave_steps(const SView& A, const SView& B
             const uint64_t b = ballot(d[w] != 0);
             if (b) {
                 const int s0 = ctz64(b);
-                const int32_t c = shfl_i32(p[w], s0) + ctz64(shfl_u64(d[w], s0)) / A.bpc;
+                const int32_t c = l + (w * 64 + s0) * cpw + ctz64(shfl_u64(d[w], s0)) / A.bpc;
                 done = true;
                 return c < lim ? c : lim;
             }
@@ -376,7 +384,10 @@ __device__ __forceinline__ int32_t slide(const Engine& en, bool valid, int32_t x
 }
 
 // Every thread of the workgroup: wave sums of the register counters into the
-// LDS copy, then one thread adds the LDS copy to the global counters.
+// LDS copy, then one thread adds the LDS copy to the workgroup's own slot of
+// the global counters (no address shared between workgroups: a shared
+// counter would serialise one atomic per workgroup; the slots are summed by
+// counters_sum_kernel).
 __device__ __forceinline__ void flush_counters(Cnt& c, CountersDev* g) {
     auto red = [](unsigned long long v) {
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -390,11 +401,13 @@ __device__ __forceinline__ void flush_counters(Cnt& c, CountersDev* g) {
     }
     __syncthreads();
     if (threadIdx.x == 0 && g) {
+        g += blockIdx.x % kMaxGrid;
         const CountersDev& s = *c.sh;
         if (s.updates) atomicAdd(&g->updates, s.updates);
         if (s.lcp_chars) atomicAdd(&g->lcp_chars, s.lcp_chars);
         if (s.wave_lcps) atomicAdd(&g->wave_lcps, s.wave_lcps);
         if (s.grid_lcps) atomicAdd(&g->grid_lcps, s.grid_lcps);
+        if (s.wg_lcps) atomicAdd(&g->wg_lcps, s.wg_lcps);
         if (s.hash_queries) atomicAdd(&g->hash_queries, s.hash_queries);
         if (s.hash_probes) atomicAdd(&g->hash_probes, s.hash_probes);
         if (s.hash_eq_len) atomicAdd(&g->hash_eq_len, s.hash_eq_len);

@@ -162,6 +162,47 @@ __device__ __forceinline__ void wave_extend(const Engine& en, bool pend, int32_t
     }
 }
 
+// Grid tier of engine (a): one long LCP shared by every wavefront of a launch.  Wavefront
+// w of `nw` takes the segments w, w + nw, w + 2 nw, ... of 64 x kGridWords
+// words (every load instruction covers 64 consecutive words), in increasing
+// order, and lowers *result with the first mismatch it finds; it stops at its
+// first segment that starts at or beyond min(lim, *result), so once every
+// wavefront has stopped, every segment below the answer has been compared.
+// Positions are offsets from l0 (the first l0 characters are known to
+// match).  Segments are assigned statically: a shared ticket would serialise
+// thousands of atomics on one address.  Uniform arguments; no barrier inside.
+template <int kGridWords>
+__device__ __forceinline__ void grid_segments(const SView& A, const SView& B, int32_t x, int32_t y, int32_t lim,
+                                           int32_t l0, int32_t w0, int32_t nw, int32_t* result) {
+    const int lane = lane_id();
+    const int32_t cpw = 1 << A.lcpw;
+    const int64_t span = static_cast<int64_t>(64) * kGridWords * cpw;
+    for (int64_t seg = w0;; seg += nw) {
+        const int64_t start = l0 + seg * span;
+        if (start >= lim) break;
+        int32_t best = 0;
+        if (lane == 0) best = __hip_atomic_load(result, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        best = shfl_i32(best, 0);
+        if (start >= best) break;
+        // this lane's first mismatch in the segment (the smallest word wins),
+        // then the wavefront's
+        int32_t first = INT_MAX;
+#pragma unroll
+        for (int w = kGridWords - 1; w >= 0; --w) {
+            const int32_t rel = (w * 64 + lane) * cpw;
+            const int64_t pp = start + rel;
+            const bool ok = pp < lim;
+            const int32_t q = ok ? static_cast<int32_t>(pp) : 0;
+            const uint64_t v = fetch(A, x + q) ^ fetch(B, y + q);
+            if (ok && v) first = rel + ctz64(v) / A.bpc;
+        }
+        first = wave_min(first);
+        const bool hit = first != INT_MAX;
+        if (hit && lane == 0) atomicMin(result, static_cast<int32_t>(start + first));
+        if (hit) break;  // later segments of this wavefront start beyond m
+    }
+}
+
 // One round over diagonals [i_begin, i_end) (any i outside [max(-t,-m),
 // min(t,n)] is written as kNone).  Diagonal i of a row lives at
 // row[i + ofs]; every index formed here is inside the row, so no pointer
@@ -301,15 +342,15 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
     if (nj > 0) {
         for (int j = 0; j < nj; ++j) {
             const int32_t jx = RS.jx[half + j];
-            const int32_t r = lcp_wg_direct(en.A, en.B, jx, RS.jy[half + j], RS.jlim[half + j],
-                                            RS.jl[half + j], RS.wmin);
+            const int32_t jy = RS.jy[half + j], jlim = RS.jlim[half + j], jl = RS.jl[half + j];
+            const int32_t r = lcp_wg_direct(en.A, en.B, jx, jy, jlim, jl, RS.wmin);
             if (tid == 0) {
                 const int32_t i = RS.ji[half + j];
                 const int32_t f = jx + r;
                 cur[i + ofs] = f;
                 if (dump_row && i >= dlo && i <= dhi) dump_row[i + t] = f;
                 cnt.updates++;
-                atomicAdd(&cnt.sh->grid_lcps, 1ull);
+                atomicAdd(&cnt.sh->wg_lcps, 1ull);
                 cnt.lcp_chars += static_cast<unsigned long long>(r);
                 if (i == target && f == n) {
                     found = true;
@@ -585,8 +626,9 @@ __global__ void ctl_init_kernel(FrontierCtl* ctl, CountersDev* cnt, unsigned int
         ctl->clk_switch = 0;
         ctl->clk_end = 0;
     }
-    if (cnt && tid < static_cast<int>(sizeof(CountersDev) / 8))
-        reinterpret_cast<unsigned long long*>(cnt)[tid] = 0;
+    if (cnt)
+        for (int i = tid; i < static_cast<int>((kMaxGrid + 1) * sizeof(CountersDev) / 8); i += blockDim.x)
+            reinterpret_cast<unsigned long long*>(cnt)[i] = 0;
     if (bar)
         for (int g = tid; g < kMaxGrid; g += blockDim.x) bar[g * kBarStride] = 0;
 }
@@ -657,8 +699,9 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
                 while (__hip_atomic_load(&ctl->phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
                     __builtin_amdgcn_s_sleep(64);
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                RS.flag = __hip_atomic_load(&ctl->status, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
             }
+            if (tid == 0)
+                RS.flag = __hip_atomic_load(&ctl->status, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
             __syncthreads();
             finished = RS.flag != 0;
             if (!finished) t = __hip_atomic_load(&ctl->phase_t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -793,6 +836,18 @@ __global__ __launch_bounds__(256) void lcp_query_kernel(LcpQueryParams Q) {
     flush_counters(cnt, Q.counters);
 }
 
+// Grid tier queries: one launch per query, every workgroup of the grid on it.
+__global__ __launch_bounds__(kFrontierThreads) void lcp_grid_kernel(LcpQueryParams Q) {
+    const Engine en = make_engine(Q.p, Q.h, 0, Q.lane_words, nullptr);
+    const int64_t qi = Q.query;
+    const int32_t x = static_cast<int32_t>(Q.x[qi]);
+    const int32_t y = static_cast<int32_t>(Q.y[qi]);
+    const int32_t lim = imin(en.A.len - x, en.B.len - y);
+    const int32_t waves = blockDim.x >> 6;
+    grid_segments<16>(en.A, en.B, x, y, lim, 0, static_cast<int32_t>(blockIdx.x) * waves + (threadIdx.x >> 6),
+                      static_cast<int32_t>(gridDim.x) * waves, Q.result + qi);
+}
+
 // Workgroup-tier LCP queries: one workgroup per query (tests of the tier).
 __global__ __launch_bounds__(kFrontierThreads) void lcp_query_wg_kernel(LcpQueryParams Q) {
     __shared__ int32_t wmin;
@@ -805,6 +860,24 @@ __global__ __launch_bounds__(kFrontierThreads) void lcp_query_wg_kernel(LcpQuery
         const int32_t l = lcp_wg_direct(en.A, en.B, x, y, lim, 0, wmin);
         if (threadIdx.x == 0) Q.out[qi] = l;
     }
+}
+
+// Sums the per-workgroup counter slots into slot kMaxGrid.
+__global__ __launch_bounds__(1024) void counters_sum_kernel(CountersDev* cnt) {
+    constexpr int F = sizeof(CountersDev) / 8;
+    __shared__ unsigned long long acc[F];
+    if (threadIdx.x < F) acc[threadIdx.x] = 0;
+    __syncthreads();
+    const unsigned long long* slot = reinterpret_cast<const unsigned long long*>(cnt + threadIdx.x);
+    for (int f = 0; f < F; ++f)
+        if (slot[f]) atomicAdd(&acc[f], slot[f]);
+    __syncthreads();
+    if (threadIdx.x < F) reinterpret_cast<unsigned long long*>(cnt + kMaxGrid)[threadIdx.x] = acc[threadIdx.x];
+}
+
+hipError_t launch_counters_sum(CountersDev* cnt, hipStream_t s) {
+    hipLaunchKernelGGL(counters_sum_kernel, dim3(1), dim3(kMaxGrid), 0, s, cnt);
+    return hipGetLastError();
 }
 
 hipError_t launch_ctl_init(FrontierCtl* ctl, CountersDev* cnt, unsigned int* bar, hipStream_t s) {
@@ -846,6 +919,25 @@ hipError_t task_max_grid(int device, int* grid_out) {
 
 hipError_t launch_tasks(const TaskParams& tp, int grid, hipStream_t s) {
     hipLaunchKernelGGL(task_kernel, dim3(grid), dim3(kFrontierThreads), 0, s, tp);
+    return hipGetLastError();
+}
+
+__global__ void lcp_grid_finish_kernel(LcpQueryParams Q) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < Q.count) {
+        const int32_t lim = imin(Q.p.a.len - static_cast<int32_t>(Q.x[i]), Q.p.b.len - static_cast<int32_t>(Q.y[i]));
+        Q.out[i] = imin(Q.result[i], lim);
+    }
+}
+
+hipError_t launch_lcp_grid_finish(const LcpQueryParams& qp, hipStream_t s) {
+    const int64_t blocks = (qp.count + 255) / 256;
+    hipLaunchKernelGGL(lcp_grid_finish_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, qp);
+    return hipGetLastError();
+}
+
+hipError_t launch_lcp_grid(const LcpQueryParams& qp, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(lcp_grid_kernel, dim3(grid), dim3(kFrontierThreads), 0, s, qp);
     return hipGetLastError();
 }
 

@@ -29,7 +29,6 @@ class DevPool {
 constexpr size_t kPowEntries = 2 * 65536 + 65 + 257 + 65;
 
 // layout of a pair's small device block
-constexpr size_t kMiscTicket = 0;
 constexpr size_t kMiscAlpha = 64;
 
 constexpr uint32_t kDefaultLdsRounds = 1024;
@@ -67,7 +66,7 @@ struct ed_pair {
     void* w8[2] = {nullptr, nullptr};
     void* tab[2] = {nullptr, nullptr};
     void* stage[2] = {nullptr, nullptr};
-    void* misc = nullptr;  // ticket, alphabet word, tile status, tile flags
+    void* misc = nullptr;  // alphabet word, tile hashes and prefixes, chunk flags
     void* f0 = nullptr;    // unused (rows are per call)
     void* f1 = nullptr;
     uint64_t rounds = 0;
@@ -78,6 +77,7 @@ struct ed_pair {
     hipEvent_t ev_prep[2] = {nullptr, nullptr};  // around the prepare kernel (ED_FLAG_TIMING)
     bool prep_timed = false;
     double gpu_ns_frontier = 0;
+    double gpu_ns_lcp = 0;  // last ed_debug_lcp with the grid tier (ED_FLAG_TIMING)
     uint64_t rounds_phase_a = 0;
     double us_phase_a = 0, us_phase_b = 0;
 };

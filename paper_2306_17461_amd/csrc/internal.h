@@ -29,11 +29,6 @@ constexpr int kChunkWords8 = kChunkChars / 8;         // 512
 // Words of zero padding after the last tile of every packed buffer.
 constexpr int kPadWords = 256;
 
-// Tile status of the decoupled look-back scan: value in bits 0..60, flag in
-// bits 62..63.
-constexpr uint64_t kTileAgg = 1ull << 62;
-constexpr uint64_t kTileInc = 2ull << 62;
-constexpr uint64_t kTileValMask = (1ull << 61) - 1;
 
 // One string as the kernels see it.
 struct StrDev {
@@ -64,7 +59,8 @@ struct CountersDev {
     unsigned long long updates;
     unsigned long long lcp_chars;
     unsigned long long wave_lcps;
-    unsigned long long grid_lcps;
+    unsigned long long grid_lcps;    // LCPs answered by the grid tier (ed_debug_lcp engine 3)
+    unsigned long long wg_lcps;      // LCPs extended by a whole workgroup
     unsigned long long hash_queries;
     unsigned long long hash_probes;
     unsigned long long hash_eq_len;  // sum of L over hash "equal" verdicts
@@ -174,8 +170,8 @@ struct PrepParams {
     int32_t force8;        // write 8-bit copies of every tile
     int32_t build_table;
     uint64_t r;            // hash base
-    uint64_t* tile_status; // total_tiles entries, zeroed before launch
-    unsigned int* ticket;  // tile ticket counter, zeroed before launch
+    uint64_t* tile_agg;    // total_tiles entries: hash of each tile
+    uint64_t* tile_prefix; // total_tiles entries: hash of its string before each tile
     uint32_t* alpha;       // OR of all characters (atomicOr), zeroed before launch
     uint8_t* chunk_big;    // per chunk (kTileChunks per tile): 1 if it has a character > 3
     const uint64_t* rtab;  // r^0..r^64 | r^(64k), k = 0..256 | R^d, d = 0..64, R = r^kTileChars
@@ -191,6 +187,8 @@ struct LcpQueryParams {
     int32_t engine;
     int32_t lane_words;
     CountersDev* counters;
+    int32_t* result;  // grid tier: per-query first mismatch (INT32_MAX before launch)
+    int64_t query;    // grid tier: the query this launch answers
 };
 
 // Kernel launchers (defined in the .hip files).
@@ -198,12 +196,16 @@ hipError_t launch_prep_clear(const PrepParams& pp, hipStream_t s);
 hipError_t launch_pack(const PrepParams& pp, int grid, hipStream_t s);
 hipError_t launch_table(const PrepParams& pp, int grid, hipStream_t s);
 hipError_t launch_copy8_rest(const PrepParams& pp, int grid, hipStream_t s);
+// cnt: kMaxGrid + 1 counter slots (one per workgroup, then their sum)
 hipError_t launch_ctl_init(FrontierCtl* ctl, CountersDev* cnt, unsigned int* bar, hipStream_t s);
+hipError_t launch_counters_sum(CountersDev* cnt, hipStream_t s);
 hipError_t launch_frontier(const FrontierParams& fp, int grid, hipStream_t s);
 hipError_t frontier_max_grid(int device, int* grid_out);
 hipError_t launch_tasks(const TaskParams& tp, int grid, hipStream_t s);
 hipError_t task_max_grid(int device, int* grid_out);
 hipError_t launch_lcp_queries(const LcpQueryParams& qp, hipStream_t s);
+hipError_t launch_lcp_grid(const LcpQueryParams& qp, int grid, hipStream_t s);
+hipError_t launch_lcp_grid_finish(const LcpQueryParams& qp, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t s);
 

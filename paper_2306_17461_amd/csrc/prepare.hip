@@ -5,12 +5,12 @@
 //                 every chunk without a character > 3, and an 8-bit copy of
 //                 every chunk with one (the rest of the copy, when the pair
 //                 cannot be packed, is written by copy8_rest_kernel);
-//   table_kernel  (hash engine) prefix table T[j] = h(S[0..jb)) mod 2^61-1
+//   table_*       (hash engine) prefix table T[j] = h(S[0..jb)) mod 2^61-1
 //                 (sections 3.2 and 3.3, Algorithm 2 "Build") from the packed
 //                 words (or the 8-bit copy): block hashes from LDS lookup
-//                 tables (h is linear in the characters), then a single-pass
-//                 scan over tiles with decoupled look-back under the
-//                 concatenation h(S1 S2) = h(S1) r^|S2| + h(S2).
+//                 tables (h is linear in the characters), combined under the
+//                 concatenation h(S1 S2) = h(S1) r^|S2| + h(S2) within each
+//                 tile, across tiles by a separate scan of the tile hashes.
 #include "device.h"
 
 namespace ed {
@@ -25,11 +25,28 @@ struct PrepShared {
     uint64_t lut4[256];      // packed byte (4 chars): c0 r^3 + c1 r^2 + c2 r + c3
     uint64_t rp[65];         // r^p
     uint64_t rseg[257];      // r^(64 k)
-    uint64_t tilepow[65];    // R^d, R = r^16384
     uint64_t wsum[kPrepThreads / 64];
-    uint64_t excl;
-    int32_t tile;
 };
+
+// The fields of one of the two strings, chosen by a uniform flag: a select
+// between two kernel arguments (scalar registers), not an indexed load.
+struct StrSel {
+    const uint8_t* raw;
+    uint64_t* w2;
+    uint64_t* w8;
+    uint64_t* tab;
+    int32_t len;
+    int32_t tile0;
+    __device__ __forceinline__ StrSel(const PrepParams& P, bool second)
+        : raw(second ? P.s[1].raw : P.s[0].raw),
+          w2(second ? P.s[1].w2 : P.s[0].w2),
+          w8(second ? P.s[1].w8 : P.s[0].w8),
+          tab(second ? P.s[1].tab : P.s[0].tab),
+          len(second ? P.s[1].len : P.s[0].len),
+          tile0(second ? P.s[1].tile0 : P.s[0].tile0) {}
+};
+
+__device__ __forceinline__ int32_t imin32(int32_t a, int32_t b) { return a < b ? a : b; }
 
 __device__ __forceinline__ uint32_t pack_dword(uint32_t d) {
     // four 8-bit characters -> four 2-bit codes (low bits of each byte)
@@ -105,98 +122,91 @@ __device__ __forceinline__ uint64_t wave_sum_mod(uint64_t v) {
 
 __global__ void prep_clear_kernel(PrepParams P) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < P.total_tiles) P.tile_status[i] = 0;
-    if (i == 0) {
-        *P.ticket = 0u;
-        *P.alpha = 0u;
-    }
+    if (i == 0) *P.alpha = 0u;
 }
 
 // Streaming pass: wavefront w takes chunks w, w + W, ... (W wavefronts in the
-// grid); lane l holds characters [64 l, 64 l + 64) of its chunk.  Chunk slots
-// past the end of a string are written as zeros (padding the last tile).
+// grid).  Every load and store instruction covers a contiguous range: lane l
+// holds the 16-character pieces at chunk offsets 1024 k + 16 l (k = 0..3),
+// packs each into 32 bits (the low or high half of a packed word) and writes
+// them at 32-bit index 64 k + l of the chunk.  Chunk slots past the end of a
+// string are written as zeros (padding the last tile).
 __global__ __launch_bounds__(kPrepThreads) void pack_kernel(PrepParams P) {
     const int lane = threadIdx.x & 63;
-    const int32_t wave = static_cast<int32_t>((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int32_t wave = __builtin_amdgcn_readfirstlane(static_cast<int32_t>((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
     const int32_t nwaves = static_cast<int32_t>((gridDim.x * blockDim.x) >> 6);
     const int32_t total = P.total_tiles * kTileChunks;
     const int32_t split = P.s[1].tile0 * kTileChunks;
     uint32_t orr = 0;
     for (int32_t g = wave; g < total; g += nwaves) {
-        const int si = g >= split ? 1 : 0;
-        const PrepString& str = P.s[si];
+        const StrSel str(P, g >= split);
         const int32_t c = g - str.tile0 * kTileChunks;
-        const int32_t seg_start = c * kChunkChars + lane * kSegChars;
+        const int32_t cbase = c * kChunkChars;
         const int32_t len = str.len;
-        uint32_t dw[16];
-        if (seg_start + kSegChars <= len) {
-            const u32x4* src = reinterpret_cast<const u32x4*>(str.raw + seg_start);
+        u32x4 v[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const u32x4 v = __builtin_nontemporal_load(src + k);
-                dw[4 * k + 0] = v.x;
-                dw[4 * k + 1] = v.y;
-                dw[4 * k + 2] = v.z;
-                dw[4 * k + 3] = v.w;
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                uint32_t d = 0;
-                for (int j = 0; j < 4; ++j) {
-                    const int32_t p = seg_start + 4 * k + j;
-                    if (p < len) d |= static_cast<uint32_t>(str.raw[p]) << (8 * j);
-                }
-                dw[k] = d;
+        for (int k = 0; k < 4; ++k) {
+            const int32_t pos = cbase + k * 1024 + lane * 16;
+            if (pos + 16 <= len) {
+                v[k] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(str.raw + pos));
+            } else {
+                uint32_t d[4] = {0, 0, 0, 0};
+                for (int j = 0; j < 16; ++j)
+                    if (pos + j < len) d[j >> 2] |= static_cast<uint32_t>(str.raw[pos + j]) << (8 * (j & 3));
+                v[k].x = d[0];
+                v[k].y = d[1];
+                v[k].z = d[2];
+                v[k].w = d[3];
             }
         }
         uint32_t o = 0;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) o |= dw[k];
+        for (int k = 0; k < 4; ++k) o |= v[k].x | v[k].y | v[k].z | v[k].w;
         orr |= o;
         const bool big = ballot((o & 0xFCFCFCFCu) != 0u) != 0;
         if (!big) {
-            uint64_t pk[2];
+            uint32_t* dst = reinterpret_cast<uint32_t*>(str.w2 + static_cast<int64_t>(c) * kChunkWords2);
 #pragma unroll
-            for (int w = 0; w < 2; ++w) {
-                uint64_t v = 0;
-#pragma unroll
-                for (int k = 0; k < 8; ++k) v |= static_cast<uint64_t>(pack_dword(dw[8 * w + k])) << (8 * k);
-                pk[w] = v;
-            }
-            u32x4 st;
-            st.x = static_cast<uint32_t>(pk[0]);
-            st.y = static_cast<uint32_t>(pk[0] >> 32);
-            st.z = static_cast<uint32_t>(pk[1]);
-            st.w = static_cast<uint32_t>(pk[1] >> 32);
-            *reinterpret_cast<u32x4*>(str.w2 + static_cast<int64_t>(c) * kChunkWords2 + lane * 2) = st;
+            for (int k = 0; k < 4; ++k)
+                dst[k * 64 + lane] = pack_dword(v[k].x) | (pack_dword(v[k].y) << 8) | (pack_dword(v[k].z) << 16) |
+                                     (pack_dword(v[k].w) << 24);
         }
         if (big || P.force8) {
-            u32x4* dst = reinterpret_cast<u32x4*>(str.w8 + static_cast<int64_t>(c) * kChunkWords8 + lane * 8);
+            u32x4* dst = reinterpret_cast<u32x4*>(str.w8 + static_cast<int64_t>(c) * kChunkWords8);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                u32x4 v;
-                v.x = dw[4 * k + 0];
-                v.y = dw[4 * k + 1];
-                v.z = dw[4 * k + 2];
-                v.w = dw[4 * k + 3];
-                dst[k] = v;
-            }
+            for (int k = 0; k < 4; ++k) dst[k * 64 + lane] = v[k];
         }
         if (lane == 0) P.chunk_big[g] = big ? 1 : 0;
     }
+    // one atomic per workgroup at most, and none when the bits are already
+    // there: atomics on one address from every wavefront serialise
+    __shared__ uint32_t wor[kPrepThreads / 64];
     orr |= orr >> 16;
     orr |= orr >> 8;
     orr &= 0xFFu;
     for (int s = 32; s > 0; s >>= 1) orr |= __shfl_xor(orr, s);
-    if (lane == 0 && orr) atomicOr(P.alpha, orr);
+    if (lane == 0) wor[threadIdx.x >> 6] = orr;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t o = 0;
+        for (int w = 0; w < kPrepThreads / 64; ++w) o |= wor[w];
+        const uint32_t cur = __hip_atomic_load(P.alpha, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((cur | o) != cur) atomicOr(P.alpha, o);
+    }
 }
 
 // Prefix tables of both strings (hash engine), after pack_kernel (and
-// copy8_rest_kernel): reads the 2-bit words when the pair is packable, the
-// 8-bit copy otherwise.  Tiles of 16384 characters are taken in ticket order,
-// so every tile that a look-back waits on is already running.
-__global__ __launch_bounds__(kPrepThreads) void table_kernel(PrepParams P, const uint64_t* rtab) {
+// copy8_rest_kernel), in three passes with no shared counter: tiles of 16384
+// characters are assigned statically to workgroups.
+//   table_tiles_kernel<false>  hash of every tile -> tile_agg[g]
+//   table_scan_kernel          per string, prefix hash before every tile ->
+//                              tile_prefix[g] (Horner over tiles, R = r^16384)
+//   table_tiles_kernel<true>   block-scan of each tile from its prefix and
+//                              T[j] at every block end inside it
+// The characters come from the 2-bit words when the pair is packable, from the
+// 8-bit copy otherwise.
+template <bool EMIT>
+__global__ __launch_bounds__(kPrepThreads) void table_tiles_kernel(PrepParams P, const uint64_t* rtab) {
     __shared__ PrepShared S;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -206,7 +216,6 @@ __global__ __launch_bounds__(kPrepThreads) void table_kernel(PrepParams P, const
     // rtab: r^0..r^64 | r^(64k), k = 0..256 | R^d, d = 0..64
     for (int i = tid; i < 65; i += kPrepThreads) S.rp[i] = rtab[i];
     for (int i = tid; i < 257; i += kPrepThreads) S.rseg[i] = rtab[65 + i];
-    for (int i = tid; i < 65; i += kPrepThreads) S.tilepow[i] = rtab[65 + 257 + i];
     __syncthreads();
     for (int e = tid; e < 8 * 256; e += kPrepThreads) {
         const int k = e >> 8, v = e & 255;
@@ -223,14 +232,9 @@ __global__ __launch_bounds__(kPrepThreads) void table_kernel(PrepParams P, const
         S.lut4[v] = h;
     }
 
-    for (;;) {
-        __syncthreads();
-        if (tid == 0) S.tile = static_cast<int32_t>(atomicAdd(P.ticket, 1u));
-        __syncthreads();
-        const int32_t g = S.tile;
-        if (g >= P.total_tiles) break;
-        const int si = g >= P.s[1].tile0 ? 1 : 0;
-        const PrepString& str = P.s[si];
+    for (int32_t g = blockIdx.x; g < P.total_tiles; g += gridDim.x) {
+        __syncthreads();  // tables ready; wsum of the previous tile consumed
+        const StrSel str(P, g >= P.s[1].tile0);
         const int32_t t = g - str.tile0;
         const int32_t seg_start = t * kTileChars + tid * kSegChars;
         const int32_t len = str.len;
@@ -267,56 +271,76 @@ __global__ __launch_bounds__(kPrepThreads) void table_kernel(PrepParams P, const
         }
         if (lane == 63) S.wsum[wave] = x;
         __syncthreads();
-        uint64_t pre = 0;  // hash of the waves before this one
-        for (int v = 0; v < wave; ++v) pre = mp_add(mp_mul(pre, S.rseg[64]), S.wsum[v]);
-        const uint64_t xprev = __shfl_up(static_cast<unsigned long long>(x), 1);
-        const uint64_t excl_thread = lane == 0 ? pre : mp_add(mp_mul(pre, S.rseg[lane]), xprev);
-
-        // ---- decoupled look-back over tiles (wave 0) ----
-        if (wave == 0) {
-            uint64_t agg = 0;
-            for (int v = 0; v < kPrepThreads / 64; ++v) agg = mp_add(mp_mul(agg, S.rseg[64]), S.wsum[v]);
-            uint64_t* status = P.tile_status + str.tile0;
-            uint64_t excl = 0;
-            if (t == 0) {
-                if (lane == 0)
-                    __hip_atomic_store(status + t, kTileInc | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                if (lane == 0)
-                    __hip_atomic_store(status + t, kTileAgg | agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                uint64_t acc = 0, mul = 1;
-                int32_t base = t - 1;
-                for (;;) {
-                    const int32_t pidx = base - lane;
-                    uint64_t st;
-                    if (pidx < 0) {
-                        st = kTileInc;  // the prefix before the first tile is h(empty) = 0
-                    } else {
-                        do {
-                            st = __hip_atomic_load(status + pidx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        } while ((st >> 62) == 0);
-                    }
-                    const uint64_t incm = ballot((st >> 62) == 2);
-                    const int f = incm ? ctz64(incm) : 64;
-                    const uint64_t term = lane <= f ? mp_mul(st & kTileValMask, S.tilepow[lane]) : 0;
-                    const uint64_t sum = wave_sum_mod(term);
-                    acc = mp_add(acc, mp_mul(sum, mul));
-                    if (incm) break;
-                    mul = mp_mul(mul, S.tilepow[64]);
-                    base -= 64;
-                }
-                excl = acc;
-                if (lane == 0)
-                    __hip_atomic_store(status + t, kTileInc | mp_add(mp_mul(excl, S.tilepow[1]), agg),
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!EMIT) {
+            if (tid == 0) {
+                uint64_t agg = 0;
+                for (int v = 0; v < kPrepThreads / 64; ++v) agg = mp_add(mp_mul(agg, S.rseg[64]), S.wsum[v]);
+                P.tile_agg[g] = agg;
             }
-            if (lane == 0) S.excl = excl;
+        } else {
+            uint64_t pre = 0;  // hash of the waves before this one
+            for (int v = 0; v < wave; ++v) pre = mp_add(mp_mul(pre, S.rseg[64]), S.wsum[v]);
+            const uint64_t xprev = __shfl_up(static_cast<unsigned long long>(x), 1);
+            const uint64_t excl_thread = lane == 0 ? pre : mp_add(mp_mul(pre, S.rseg[lane]), xprev);
+            // emit T at block ends: prefix at segment start, then the units
+            const uint64_t tp = P.tile_prefix[g];
+            const uint64_t hstart = mp_add(mp_mul(tp, S.rseg[tid]), excl_thread);
+            if (seg_start < len) seg_pass<true>(S, dw, pk, big, P.log2b, hstart, seg_start, len, str.tab);
+            if (t == 0 && tid == 0) str.tab[0] = 0;
+        }
+    }
+}
+
+// Pass 2: one workgroup per string.  prefix[t] = h(S[0 .. 16384 t)) from the
+// tile hashes by Horner's rule with R = r^16384: each thread folds a run of
+// consecutive tiles, the runs are combined by a scan under
+// (a, na) . (b, nb) = (a R^nb + b, na + nb), and each thread writes the
+// prefixes of its run.
+__global__ __launch_bounds__(1024) void table_scan_kernel(PrepParams P, const uint64_t* rtab) {
+    __shared__ uint64_t Rp[32];  // R^(2^k)
+    __shared__ uint64_t hs[1024];
+    __shared__ int32_t ns[1024];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const StrSel str(P, blockIdx.x == 1);
+    const int32_t tiles = (blockIdx.x == 1 ? P.total_tiles : P.s[1].tile0) - str.tile0;
+    if (tid == 0) {
+        Rp[0] = rtab[65 + 257 + 1];
+        for (int k = 1; k < 32; ++k) Rp[k] = mp_mul(Rp[k - 1], Rp[k - 1]);
+    }
+    __syncthreads();
+    auto powR = [&](int32_t e) {
+        uint64_t r = 1;
+        for (int k = 0; e; ++k, e >>= 1)
+            if (e & 1) r = mp_mul(r, Rp[k]);
+        return r;
+    };
+    const int32_t blk = (tiles + nthr - 1) / nthr;
+    const int32_t lo = imin32(tiles, tid * blk), hi = imin32(tiles, lo + blk);
+    const uint64_t R = Rp[0];
+    const uint64_t* agg = P.tile_agg + str.tile0;
+    uint64_t h = 0;
+    for (int32_t u = lo; u < hi; ++u) h = mp_add(mp_mul(h, R), agg[u]);
+    int32_t n = hi - lo;
+    // inclusive scan over threads (Hillis-Steele through LDS)
+    for (int d = 1; d < nthr; d <<= 1) {
+        hs[tid] = h;
+        ns[tid] = n;
+        __syncthreads();
+        if (tid >= d) {
+            const uint64_t a = hs[tid - d];
+            const int32_t na = ns[tid - d];
+            h = mp_add(mp_mul(a, powR(n)), h);
+            n += na;
         }
         __syncthreads();
-        // ---- emit T at block ends: prefix at segment start, then the units ----
-        const uint64_t hstart = mp_add(mp_mul(S.excl, S.rseg[tid]), excl_thread);
-        if (seg_start < len) seg_pass<true>(S, dw, pk, big, P.log2b, hstart, seg_start, len, str.tab);
-        if (t == 0 && tid == 0) str.tab[0] = 0;
+    }
+    hs[tid] = h;
+    __syncthreads();
+    uint64_t p = tid == 0 ? 0 : hs[tid - 1];
+    uint64_t* pre = P.tile_prefix + str.tile0;
+    for (int32_t u = lo; u < hi; ++u) {
+        pre[u] = p;
+        p = mp_add(mp_mul(p, R), agg[u]);
     }
 }
 
@@ -326,14 +350,13 @@ __global__ __launch_bounds__(kPrepThreads) void copy8_rest_kernel(PrepParams P) 
     const uint32_t alpha = *P.alpha;
     if (alpha <= 3u || P.force8) return;
     const int lane = threadIdx.x & 63;
-    const int32_t wave = static_cast<int32_t>((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int32_t wave = __builtin_amdgcn_readfirstlane(static_cast<int32_t>((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
     const int32_t nwaves = static_cast<int32_t>((gridDim.x * blockDim.x) >> 6);
     const int32_t total = P.total_tiles * kTileChunks;
     const int32_t split = P.s[1].tile0 * kTileChunks;
     for (int32_t g = wave; g < total; g += nwaves) {
         if (P.chunk_big[g]) continue;
-        const int si = g >= split ? 1 : 0;
-        const PrepString& str = P.s[si];
+        const StrSel str(P, g >= split);
         const int32_t c = g - str.tile0 * kTileChunks;
         const int32_t seg_start = c * kChunkChars + lane * kSegChars;
         uint64_t* dst = str.w8 + static_cast<int64_t>(c) * kChunkWords8 + lane * 8;
@@ -372,7 +395,13 @@ hipError_t launch_pack(const PrepParams& pp, int grid, hipStream_t s) {
 }
 
 hipError_t launch_table(const PrepParams& pp, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(table_kernel, dim3(grid), dim3(kPrepThreads), 0, s, pp, pp.rtab);
+    hipLaunchKernelGGL(table_tiles_kernel<false>, dim3(grid), dim3(kPrepThreads), 0, s, pp, pp.rtab);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(table_scan_kernel, dim3(2), dim3(1024), 0, s, pp, pp.rtab);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(table_tiles_kernel<true>, dim3(grid), dim3(kPrepThreads), 0, s, pp, pp.rtab);
     return hipGetLastError();
 }
 

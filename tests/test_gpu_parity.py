@@ -163,11 +163,11 @@ def _lcp_cases():
     yield "zeros", Z, Z.copy()
 
 
-@pytest.mark.parametrize("engine", [0, 1, 2])
+@pytest.mark.parametrize("engine", [0, 1, 2, 3])
 @pytest.mark.parametrize("pack_bits", [0, 8])
 @pytest.mark.parametrize("block", [32, 1, 4, 256])
 def test_lcp_engines(ed, make_ctx, orc, engine, pack_bits, block):
-    """engine 0: lane + wave tiers; 1: hash search; 2: direct workgroup tier."""
+    """engine 0: lane + wave tiers; 1: hash search; 2: direct workgroup tier; 3: grid tier."""
     if engine != 1 and block != 32:
         pytest.skip("block size only matters for the hash engine")
     rng = np.random.default_rng(engine * 100 + pack_bits + block)
@@ -197,8 +197,32 @@ def test_lcp_engines(ed, make_ctx, orc, engine, pack_bits, block):
         ed.ed_release(p)
 
 
+@pytest.mark.parametrize("pack_bits", [0, 8])
+def test_lcp_grid_tier_long(ed, make_ctx, orc, pack_bits):
+    # one mismatch planted around segment boundaries of the grid tier (1024
+    # threads x 8 words: 262144 characters at 2 bits, 65536 at 8 bits)
+    n = 3_000_000
+    seg = 1024 * 8 * (32 if pack_bits == 0 else 8)
+    A = synth.random_string(n, synth.CharDist("uniform", 4), 31)
+    ctx = make_ctx(pack_bits=pack_bits, flags=ed.FLAG_TIMING)
+    spots = [0, 1, seg - 1, seg, seg + 1, 3 * seg + 17, 7 * seg - 1, n - 2, n - 1]
+    for pos in spots + [None]:
+        B = A.copy()
+        if pos is not None:
+            B[pos] ^= 1
+        say("grid lcp", pack_bits, pos)
+        p = ed.ed_prepare(ctx, A, B)
+        xs = [0, 5, 0, 1000]
+        ys = [0, 5, 3, 1000]
+        got = ed.ed_debug_lcp(ctx, p, xs, ys, engine=3)
+        want = [orc.lcp(A, B, x, y) for x, y in zip(xs, ys)]
+        assert list(got) == want
+        assert ed.ed_pair_stats(p)["gpu_ns_lcp_kernel"] > 0
+        ed.ed_release(p)
+
+
 # ---------------------------------------------------------------------------
-# frontier rows: every f_t[i] against R_t from the DP matrix (T2)
+# frontier rows: every f_t[i] against R_t from the DP matrix
 # ---------------------------------------------------------------------------
 FRONTIER_MODES = [
     ("lds", dict()),
@@ -310,6 +334,30 @@ def test_medium_pairs(ed, make_ctx, orc, engine, mode):
         A, B, _ = synth.single_pair(n, k, seed, sigma=sigma)
         say("medium", engine, mode, n, k, sigma)
         assert gpu_ed(ed, ctx, A, B) == orc.lv_omp(A, B)
+
+
+@pytest.mark.parametrize("case", ["sigma4", "sigma256", "force8"])
+def test_long_lcps_in_phase_a(ed, make_ctx, orc, case):
+    # few edits on long strings: the one-workgroup phase meets LCPs of many
+    # workgroup-tier steps (and, with k = 0, one LCP over the whole string)
+    if case == "sigma4":
+        ctx = make_ctx(flags=ed.FLAG_TIMING)
+        specs = [(4_000_000, 3, 4, 1), (3_000_000, 6, 4, 2), (2_500_000, 0, 4, 3)]
+    elif case == "sigma256":
+        ctx = make_ctx(flags=ed.FLAG_TIMING)
+        specs = [(1_000_000, 5, 256, 4), (800_000, 9, 256, 5)]
+    else:
+        ctx = make_ctx(pack_bits=8, flags=ed.FLAG_TIMING)
+        specs = [(1_200_000, 4, 4, 6)]
+    for n, k, sigma, seed in specs:
+        A, B, _ = synth.single_pair(n, k, seed, sigma=sigma)
+        say("long lcps", case, n, k)
+        p = ed.ed_prepare(ctx, A, B)
+        got = ed.ed_distance(ctx, p)
+        st = ed.ed_pair_stats(p)
+        ed.ed_release(p)
+        assert got == orc.lv_omp(A, B)
+        assert st["wg_lcps"] > 0
 
 
 # ---------------------------------------------------------------------------
