@@ -422,10 +422,10 @@ int ed::prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B
     pp.alpha = reinterpret_cast<uint32_t*>(misc + kMiscAlpha);
     pp.chunk_big = reinterpret_cast<uint8_t*>(misc + big_off);
     pp.rtab = c->d_pow + 2 * 65536;
-    // streaming kernels: enough wavefronts to keep every CU full, each taking
-    // several chunks; the table kernel: a few tiles in flight per CU
+    // pack: two workgroups per CU, each taking many chunks (more workgroups
+    // measured slower); table passes: as many workgroups as fit by LDS
     const int stream_grid = std::max(1, std::min(total, c->num_cu * 2));
-    const int table_grid = std::max(1, std::min(total, c->num_cu * 4));
+    const int table_grid = std::max(1, std::min(total, c->num_cu * 6));
     HIP_TRY(launch_prep_clear(pp, s));
     if (c->opt.flags & ED_FLAG_TIMING) {
         HIP_TRY(hipEventCreate(&p->ev_prep[0]));

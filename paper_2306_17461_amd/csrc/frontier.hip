@@ -400,8 +400,11 @@ __device__ __forceinline__ const T* uni(const T* p) {
     return reinterpret_cast<const T*>(uni(reinterpret_cast<uint64_t>(p)));
 }
 
-__device__ __forceinline__ Engine make_engine(const PairDev& p, const HashDev& h, int engine,
-                                              int lane_words, const uint64_t* lut4) {
+// KIND (0 direct, 1 hash) is a compile-time constant in every kernel that
+// runs rounds, so the other engine's code and fields drop out of it.
+template <int KIND>
+__device__ __forceinline__ Engine make_engine(const PairDev& p, const HashDev& h, int lane_words,
+                                              const uint64_t* lut4) {
     Engine en;
     const uint32_t alpha = *p.alpha;
     pair_views(p, alpha, en.A, en.B);
@@ -411,15 +414,24 @@ __device__ __forceinline__ Engine make_engine(const PairDev& p, const HashDev& h
     en.B.len = uni(en.B.len);
     en.A.lcpw = en.B.lcpw = uni(en.A.lcpw);
     en.A.bpc = en.B.bpc = uni(en.A.bpc);
-    en.TA = uni(p.a.tab);
-    en.TB = uni(p.b.tab);
-    en.q.h.r = uni(h.r);
-    en.q.h.pow0 = uni(h.pow0);
-    en.q.h.pow1 = uni(h.pow1);
-    en.q.r4 = engine == 1 ? mp_mul(mp_mul(en.q.h.r, en.q.h.r), mp_mul(en.q.h.r, en.q.h.r)) : 0;
-    en.q.lut4 = lut4;
-    en.q.log2b = uni(p.log2b);
-    en.kind = uni(engine);
+    if (KIND == 1) {
+        en.TA = uni(p.a.tab);
+        en.TB = uni(p.b.tab);
+        en.q.h.r = uni(h.r);
+        en.q.h.pow0 = uni(h.pow0);
+        en.q.h.pow1 = uni(h.pow1);
+        en.q.r4 = mp_mul(mp_mul(en.q.h.r, en.q.h.r), mp_mul(en.q.h.r, en.q.h.r));
+        en.q.lut4 = lut4;
+        en.q.log2b = uni(p.log2b);
+    } else {
+        en.TA = en.TB = nullptr;
+        en.q.h.r = 0;
+        en.q.h.pow0 = en.q.h.pow1 = nullptr;
+        en.q.r4 = 0;
+        en.q.lut4 = nullptr;
+        en.q.log2b = 0;
+    }
+    en.kind = KIND;
     en.lane_words = uni(lane_words);
     return en;
 }
@@ -503,10 +515,11 @@ __device__ void schedule_superstep(const TaskParams& P, TaskPair* S, int32_t pi)
                       (static_cast<long long>(c + 1) << 32), base + c);
 }
 
+template <int KIND>
 __device__ void solo_task(const TaskParams& P, int32_t pi, LdsState& L, JobCursor& jc, Cnt& cnt) {
     TaskPair* S = P.pairs + pi;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const Engine en = make_engine(S->p, P.h, P.engine, P.lane_words, L.lut4);
+    const Engine en = make_engine<KIND>(S->p, P.h, P.lane_words, L.lut4);
     const int32_t n = en.A.len, m = en.B.len;
     const int32_t maxnm = imax(n, m);
     const int32_t off = kLdsRoundsMax + 2;  // diagonal i at row[i + off]
@@ -557,11 +570,12 @@ __device__ void solo_task(const TaskParams& P, int32_t pi, LdsState& L, JobCurso
     }
 }
 
+template <int KIND>
 __device__ void chunk_task(const TaskParams& P, int32_t pi, int32_t c, LdsState& L, JobCursor& jc,
                            Cnt& cnt) {
     TaskPair* S = P.pairs + pi;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const Engine en = make_engine(S->p, P.h, P.engine, P.lane_words, L.lut4);
+    const Engine en = make_engine<KIND>(S->p, P.h, P.lane_words, L.lut4);
     RoundShared& RS = L.rs;
     const int32_t t = uni(S->t), H = uni(S->H), T = uni(S->T), C = uni(S->chunk), K = uni(S->K),
                   cur = uni(S->cur);
@@ -633,6 +647,7 @@ __global__ void ctl_init_kernel(FrontierCtl* ctl, CountersDev* cnt, unsigned int
         for (int g = tid; g < kMaxGrid; g += blockDim.x) bar[g * kBarStride] = 0;
 }
 
+template <int KIND, bool DUMP>
 __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierParams P) {
     __shared__ LdsState L;
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -642,9 +657,10 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
     cnt_init_shared(&L.cnt);
     JobCursor jc;
     rs_init(L.rs, jc);
-    if (P.engine == 1) build_lut4(L.lut4, P.h.r, tid, nthr);
+    if (KIND == 1) build_lut4(L.lut4, P.h.r, tid, nthr);
     __syncthreads();
-    const Engine en = make_engine(P.p, P.h, P.engine, P.lane_words, L.lut4);
+    const Engine en = make_engine<KIND>(P.p, P.h, P.lane_words, L.lut4);
+    int32_t* const dump = DUMP ? P.dump : nullptr;
     RoundShared& RS = L.rs;
     const int32_t n = en.A.len, m = en.B.len;
     const int32_t maxnm = imax(n, m);
@@ -664,7 +680,7 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
             const int32_t off = kLdsRoundsMax + 2;  // diagonal i at row[i + off]
             int32_t* la = L.row[0];
             int32_t* lb = L.row[1];
-            round_range(en, 0, la, la, off, -2, 3, RS, jc, P.dump && P.dump_cap >= 1 ? P.dump : nullptr, 0, 0, cnt);
+            round_range(en, 0, la, la, off, -2, 3, RS, jc, dump && P.dump_cap >= 1 ? dump : nullptr, 0, 0, cnt);
             const int32_t lr = imin(imin(P.lds_rounds, kLdsRoundsMax), K);
             int32_t status = 0, result = 0;
             for (;;) {
@@ -673,7 +689,7 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
                 if (t > maxnm) { status = 4; result = t; break; }
                 if (t >= lr) break;
                 ++t;
-                round_range(en, t, la, lb, off, -(t + 2), t + 3, RS, jc, dump_row_for(P.dump, P.dump_cap, t), -t, t, cnt);
+                round_range(en, t, la, lb, off, -(t + 2), t + 3, RS, jc, dump_row_for(dump, P.dump_cap, t), -t, t, cnt);
                 int32_t* tmp = la;
                 la = lb;
                 lb = tmp;
@@ -747,7 +763,7 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
                 const int32_t e1 = imin(total1, e0 + c1);
                 if (e0 < e1 &&
                     round_range(en, t1, gp, gc, gofs, e0 - (t1 + 2), e1 - (t1 + 2), RS, jc,
-                                dump_row_for(P.dump, P.dump_cap, t1), -t1, t1, cnt))
+                                dump_row_for(dump, P.dump_cap, t1), -t1, t1, cnt))
                     atomicMin(&ctl->found_t, t1);
                 grid_sync(ctl, P.bar, ++epoch);
                 int32_t* tmp = gp;
@@ -772,7 +788,7 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
                 for (int32_t s = 1; s <= H; ++s) {
                     const int32_t tt = t + s;
                     if (round_range(en, tt, rp, rc, wofs, a - (H - s), b + (H - s) + 1, RS, jc,
-                                    dump_row_for(P.dump, P.dump_cap, tt), imax(a, -tt), imin(b, tt), cnt))
+                                    dump_row_for(dump, P.dump_cap, tt), imax(a, -tt), imin(b, tt), cnt))
                         atomicMin(&ctl->found_t, tt);
                     int32_t* tmp = rp;
                     rp = rc;
@@ -791,6 +807,7 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
     flush_counters(cnt, P.counters);
 }
 
+template <int KIND>
 __global__ __launch_bounds__(kFrontierThreads) void task_kernel(TaskParams P) {
     __shared__ LdsState L;
     const int tid = threadIdx.x;
@@ -799,7 +816,7 @@ __global__ __launch_bounds__(kFrontierThreads) void task_kernel(TaskParams P) {
     cnt_init_shared(&L.cnt);
     JobCursor jc;
     rs_init(L.rs, jc);
-    if (P.engine == 1) build_lut4(L.lut4, P.h.r, tid, blockDim.x);
+    if (KIND == 1) build_lut4(L.lut4, P.h.r, tid, blockDim.x);
     for (;;) {
         __syncthreads();
         if (tid == 0) L.rs.task = q_pop(P);
@@ -809,9 +826,9 @@ __global__ __launch_bounds__(kFrontierThreads) void task_kernel(TaskParams P) {
         const int32_t pi = static_cast<int32_t>(task & 0xFFFFFFFFll);
         const uint32_t c = static_cast<uint32_t>(static_cast<unsigned long long>(task) >> 32);
         if (c == kTaskSolo)
-            solo_task(P, pi, L, jc, cnt);
+            solo_task<KIND>(P, pi, L, jc, cnt);
         else
-            chunk_task(P, pi, static_cast<int32_t>(c - 1), L, jc, cnt);
+            chunk_task<KIND>(P, pi, static_cast<int32_t>(c - 1), L, jc, cnt);
     }
     flush_counters(cnt, P.counters);
 }
@@ -824,7 +841,8 @@ __global__ __launch_bounds__(256) void lcp_query_kernel(LcpQueryParams Q) {
     cnt_init_shared(&sh);
     if (Q.engine == 1) build_lut4(lut4, Q.h.r, threadIdx.x, blockDim.x);
     __syncthreads();
-    const Engine en = make_engine(Q.p, Q.h, Q.engine, Q.lane_words, lut4);
+    const Engine en = Q.engine == 1 ? make_engine<1>(Q.p, Q.h, Q.lane_words, lut4)
+                                    : make_engine<0>(Q.p, Q.h, Q.lane_words, lut4);
     const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
     for (int64_t qi = wave; qi < Q.count; qi += nwaves) {
@@ -838,7 +856,7 @@ __global__ __launch_bounds__(256) void lcp_query_kernel(LcpQueryParams Q) {
 
 // Grid tier queries: one launch per query, every workgroup of the grid on it.
 __global__ __launch_bounds__(kFrontierThreads) void lcp_grid_kernel(LcpQueryParams Q) {
-    const Engine en = make_engine(Q.p, Q.h, 0, Q.lane_words, nullptr);
+    const Engine en = make_engine<0>(Q.p, Q.h, Q.lane_words, nullptr);
     const int64_t qi = Q.query;
     const int32_t x = static_cast<int32_t>(Q.x[qi]);
     const int32_t y = static_cast<int32_t>(Q.y[qi]);
@@ -851,7 +869,7 @@ __global__ __launch_bounds__(kFrontierThreads) void lcp_grid_kernel(LcpQueryPara
 // Workgroup-tier LCP queries: one workgroup per query (tests of the tier).
 __global__ __launch_bounds__(kFrontierThreads) void lcp_query_wg_kernel(LcpQueryParams Q) {
     __shared__ int32_t wmin;
-    const Engine en = make_engine(Q.p, Q.h, 0, Q.lane_words, nullptr);
+    const Engine en = make_engine<0>(Q.p, Q.h, Q.lane_words, nullptr);
     for (int64_t qi = blockIdx.x; qi < Q.count; qi += gridDim.x) {
         const int32_t x = static_cast<int32_t>(Q.x[qi]);
         const int32_t y = static_cast<int32_t>(Q.y[qi]);
@@ -889,9 +907,18 @@ hipError_t frontier_max_grid(int device, int* grid_out) {
     int cus = 0, per = 0;
     hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(frontier_kernel),
-                                                     kFrontierThreads, 0);
-    if (e != hipSuccess) return e;
+    // the smallest occupancy over the instantiations (all run the same grid)
+    const void* kernels[] = {reinterpret_cast<const void*>(frontier_kernel<0, false>),
+                             reinterpret_cast<const void*>(frontier_kernel<0, true>),
+                             reinterpret_cast<const void*>(frontier_kernel<1, false>),
+                             reinterpret_cast<const void*>(frontier_kernel<1, true>)};
+    per = 1 << 30;
+    for (const void* k : kernels) {
+        int q = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, k, kFrontierThreads, 0);
+        if (e != hipSuccess) return e;
+        per = q < per ? q : per;
+    }
     if (per < 1) per = 1;
     int g = cus * per;
     *grid_out = g < kMaxGrid ? g : kMaxGrid;
@@ -901,24 +928,35 @@ hipError_t frontier_max_grid(int device, int* grid_out) {
 hipError_t launch_frontier(const FrontierParams& fp, int grid, hipStream_t s) {
     FrontierParams arg = fp;
     void* args[] = {&arg};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(frontier_kernel), dim3(grid),
-                                      dim3(kFrontierThreads), args, 0, s);
+    const void* k = fp.engine == 1 ? (fp.dump ? reinterpret_cast<const void*>(frontier_kernel<1, true>)
+                                              : reinterpret_cast<const void*>(frontier_kernel<1, false>))
+                                   : (fp.dump ? reinterpret_cast<const void*>(frontier_kernel<0, true>)
+                                              : reinterpret_cast<const void*>(frontier_kernel<0, false>));
+    return hipLaunchCooperativeKernel(k, dim3(grid), dim3(kFrontierThreads), args, 0, s);
 }
 
 hipError_t task_max_grid(int device, int* grid_out) {
     int cus = 0, per = 0;
     hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(task_kernel),
+    int per1 = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(task_kernel<0>),
                                                      kFrontierThreads, 0);
     if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per1, reinterpret_cast<const void*>(task_kernel<1>),
+                                                     kFrontierThreads, 0);
+    if (e != hipSuccess) return e;
+    per = per1 < per ? per1 : per;
     if (per < 1) per = 1;
     *grid_out = cus * per;
     return hipSuccess;
 }
 
 hipError_t launch_tasks(const TaskParams& tp, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(task_kernel, dim3(grid), dim3(kFrontierThreads), 0, s, tp);
+    if (tp.engine == 1)
+        hipLaunchKernelGGL(task_kernel<1>, dim3(grid), dim3(kFrontierThreads), 0, s, tp);
+    else
+        hipLaunchKernelGGL(task_kernel<0>, dim3(grid), dim3(kFrontierThreads), 0, s, tp);
     return hipGetLastError();
 }
 

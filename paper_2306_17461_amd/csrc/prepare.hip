@@ -20,8 +20,11 @@ namespace {
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 struct PrepShared {
-    uint64_t lut32[8][256];  // packed byte k of a 2-bit word: sum_j c_j r^(31-4k-j)
-    uint64_t lut8[8][256];   // byte k of an 8-char word: v r^(7-k)
+    // one of the two, by the pair's packing (halves the LDS per workgroup)
+    union {
+        uint64_t lut32[8][256];  // packed byte k of a 2-bit word: sum_j c_j r^(31-4k-j)
+        uint64_t lut8[8][256];   // byte k of an 8-char word: v r^(7-k)
+    };
     uint64_t lut4[256];      // packed byte (4 chars): c0 r^3 + c1 r^2 + c2 r + c3
     uint64_t rp[65];         // r^p
     uint64_t rseg[257];      // r^(64 k)
@@ -219,11 +222,14 @@ __global__ __launch_bounds__(kPrepThreads) void table_tiles_kernel(PrepParams P,
     __syncthreads();
     for (int e = tid; e < 8 * 256; e += kPrepThreads) {
         const int k = e >> 8, v = e & 255;
-        uint64_t h = 0;
-        for (int j = 0; j < 4; ++j)
-            h = mp_add(h, mp_mul(static_cast<uint64_t>((v >> (2 * j)) & 3), S.rp[31 - 4 * k - j]));
-        S.lut32[k][v] = h;
-        S.lut8[k][v] = mp_mul(static_cast<uint64_t>(v), S.rp[7 - k]);
+        if (two) {
+            uint64_t h = 0;
+            for (int j = 0; j < 4; ++j)
+                h = mp_add(h, mp_mul(static_cast<uint64_t>((v >> (2 * j)) & 3), S.rp[31 - 4 * k - j]));
+            S.lut32[k][v] = h;
+        } else {
+            S.lut8[k][v] = mp_mul(static_cast<uint64_t>(v), S.rp[7 - k]);
+        }
     }
     for (int v = tid; v < 256; v += kPrepThreads) {
         uint64_t h = 0;
