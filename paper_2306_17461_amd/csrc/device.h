@@ -43,8 +43,12 @@ __device__ __forceinline__ int shfl_i32(int v, int src) { return __shfl(v, src);
 // returns the 64 bits holding characters pos, pos+1, ... (little-endian:
 // character pos in the lowest bits).  Words past the string are zero padding.
 // ---------------------------------------------------------------------------
+// Device-global words: loads through this type are global (not flat)
+// instructions, which LDS operations do not have to wait for.
+typedef const uint64_t __attribute__((address_space(1))) gword;
+
 struct SView {
-    const uint64_t* w;
+    gword* w;
     int32_t len;
     int32_t lcpw;  // 5 (2-bit) or 3 (8-bit)
     int32_t bpc;   // 2 or 8
@@ -61,8 +65,8 @@ __device__ __forceinline__ uint64_t fetch(const SView& s, int32_t pos) {
 
 __device__ __forceinline__ void pair_views(const PairDev& p, uint32_t alpha, SView& A, SView& B) {
     const bool two = (alpha <= 3u) && !p.force8;
-    A.w = two ? p.a.w2 : p.a.w8;
-    B.w = two ? p.b.w2 : p.b.w8;
+    A.w = (gword*)(two ? p.a.w2 : p.a.w8);
+    B.w = (gword*)(two ? p.b.w2 : p.b.w8);
     A.len = p.a.len;
     B.len = p.b.len;
     A.lcpw = B.lcpw = two ? 5 : 3;
@@ -202,14 +206,16 @@ __device__ __forceinline__ void cnt_init_shared(CountersDev* sh) {
 // concatenation of section 2.
 // ---------------------------------------------------------------------------
 struct HashQ {
-    HashDev h;
+    HashDev h;             // r (h.pow0 / h.pow1 as global pointers below)
+    gword* pow0;           // r^a, a < 65536
+    gword* pow1;           // r^(65536 a), a < 65536
     uint64_t r4;           // r^4
     const uint64_t* lut4;  // LDS: hash of the 4 characters of a packed byte
     int32_t log2b;
 };
 
 __device__ __forceinline__ uint64_t pow_r(const HashQ& q, int32_t L) {
-    return mp_mul(q.h.pow0[L & 0xFFFF], q.h.pow1[static_cast<uint32_t>(L) >> 16]);
+    return mp_mul(q.pow0[L & 0xFFFF], q.pow1[static_cast<uint32_t>(L) >> 16]);
 }
 
 // h(S[s .. s+e)), s a multiple of the block size.
@@ -243,12 +249,12 @@ __device__ __forceinline__ uint64_t partial_hash(const SView& S, const HashQ& q,
     return h;
 }
 
-__device__ __forceinline__ uint64_t get_hash(const SView& S, const uint64_t* T, const HashQ& q,
+__device__ __forceinline__ uint64_t get_hash(const SView& S, gword* T, const HashQ& q,
                                              int32_t p) {
     const int32_t j = p >> q.log2b;
     const int32_t e = p & ((1 << q.log2b) - 1);
     uint64_t h = T[j];
-    if (e) h = mp_add(mp_mul(h, q.h.pow0[e]), partial_hash(S, q, j << q.log2b, e));
+    if (e) h = mp_add(mp_mul(h, q.pow0[e]), partial_hash(S, q, j << q.log2b, e));
     return h;
 }
 
@@ -259,8 +265,8 @@ __device__ __forceinline__ uint64_t get_hash(const SView& S, const uint64_t* T, 
 // direct step finds the mismatch character, which confirms the answer.  When
 // the direct step finds no mismatch below hi, a hash collision made some
 // "equal" verdict wrong: the LCP is recomputed directly (counted).
-__device__ __forceinline__ int32_t lcp_wave_hash(const SView& A, const SView& B, const uint64_t* TA,
-                                 const uint64_t* TB, const HashQ& q, int32_t x, int32_t y,
+__device__ __forceinline__ int32_t lcp_wave_hash(const SView& A, const SView& B, gword* TA,
+                                 gword* TB, const HashQ& q, int32_t x, int32_t y,
                                  int32_t lim, int32_t l0, Cnt& cnt) {
     const int lane = lane_id();
     const int32_t cpw = 1 << A.lcpw;
@@ -349,8 +355,8 @@ __device__ __forceinline__ void build_lut4(uint64_t* lut4, uint64_t r, int tid, 
 // ---------------------------------------------------------------------------
 struct Engine {
     SView A, B;
-    const uint64_t* TA;
-    const uint64_t* TB;
+    gword* TA;
+    gword* TB;
     HashQ q;
     int32_t kind;        // 0 direct, 1 hash
     int32_t lane_words;

@@ -41,6 +41,8 @@ namespace {
 constexpr int kU = 2;          // diagonals per thread per pass
 constexpr int kJobHalf = 128;  // queued LCPs per round (a ring of two halves)
 constexpr int kWaveSteps = 2;  // wavefront steps before the hash search / workgroup tier
+constexpr int kWgWords = 8;      // words per thread per workgroup-tier step (single pair)
+constexpr int kWgWordsTask = 4;  // ... in the many-pair kernel (register budget)
 
 struct RoundShared {
     int32_t ji[2 * kJobHalf];
@@ -80,41 +82,58 @@ __device__ __forceinline__ void rs_init(RoundShared& RS, JobCursor& jc) {
     jc.start[1] = 0;
 }
 
-// Engine (a), workgroup tier: every thread of the workgroup compares 4 words
-// per step (131072 characters per step at 2 bits, 32768 at 8 bits); the first
-// mismatch is the minimum over wavefronts.  Uniform arguments; returns LCP.
-__device__ __forceinline__ int32_t lcp_wg_direct(const SView& A, const SView& B, int32_t x, int32_t y,
-                                                 int32_t lim, int32_t l, int32_t& wmin) {
-    constexpr int W = 4;
+// Engine (a), workgroup tier: every thread of the workgroup compares 4 words in
+// the first step and W in each later one (W = 8: 262144 characters per step at
+// 2 bits, 65536 at 8 bits); the first mismatch is the minimum over
+// wavefronts.  Uniform arguments; returns the LCP.
+// One workgroup step of W words per thread from offset l: the first mismatch
+// below lim (INT_MAX if none).  Every thread calls it.
+template <int W>
+__device__ __forceinline__ int32_t wg_step(const SView& A, const SView& B, int32_t x, int32_t y, int32_t lim,
+                                           int32_t l, int32_t& wmin) {
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int32_t cpw = 1 << A.lcpw;
+    if (tid == 0) wmin = INT_MAX;
+    __syncthreads();
+    // every word first (all loads in flight together), then this lane's
+    // first mismatch (the smallest word wins), the wavefront's and the
+    // workgroup's
+    uint64_t d[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const int32_t p = l + (w * nthr + tid) * cpw;
+        const int32_t q = p < lim ? p : 0;
+        d[w] = fetch(A, x + q) ^ fetch(B, y + q);
+    }
+    int32_t first = INT_MAX;
+#pragma unroll
+    for (int w = W - 1; w >= 0; --w) {
+        const int32_t p = l + (w * nthr + tid) * cpw;
+        if (p < lim && d[w]) first = p + ctz64(d[w]) / A.bpc;
+    }
+    first = wave_min(first);
+    if (lane_id() == 0 && first != INT_MAX) atomicMin(&wmin, first);
+    __syncthreads();
+    const int32_t m = wmin;
+    __syncthreads();
+    return m;
+}
+
+// The first step takes 4 words per thread (most LCPs that reach this tier end
+// there), later steps W words per thread.
+template <int W>
+__device__ __forceinline__ int32_t lcp_wg_direct(const SView& A, const SView& B, int32_t x, int32_t y,
+                                                 int32_t lim, int32_t l, int32_t& wmin) {
+    const int32_t nthr = blockDim.x;
+    const int32_t cpw = 1 << A.lcpw;
+    if (l < lim) {
+        const int32_t m = wg_step<4>(A, B, x, y, lim, l, wmin);
+        if (m != INT_MAX) return m < lim ? m : lim;
+        l += 4 * nthr * cpw;
+    }
     while (l < lim) {
-        if (tid == 0) wmin = INT_MAX;
-        __syncthreads();
-        uint64_t d[W];
-        int32_t p[W];
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-            p[w] = l + (w * nthr + tid) * cpw;
-            const bool ok = p[w] < lim;
-            const int32_t q = ok ? p[w] : 0;
-            const uint64_t v = fetch(A, x + q) ^ fetch(B, y + q);
-            d[w] = ok ? v : 0;
-        }
-        int32_t best = INT_MAX;
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-            const uint64_t b = ballot(d[w] != 0);
-            if (b && best == INT_MAX) {
-                const int s = ctz64(b);
-                best = shfl_i32(p[w], s) + ctz64(shfl_u64(d[w], s)) / A.bpc;
-            }
-        }
-        if (lane_id() == 0 && best != INT_MAX) atomicMin(&wmin, best);
-        __syncthreads();
-        const int32_t mres = wmin;
-        __syncthreads();
-        if (mres != INT_MAX) return mres < lim ? mres : lim;
+        const int32_t m = wg_step<W>(A, B, x, y, lim, l, wmin);
+        if (m != INT_MAX) return m < lim ? m : lim;
         l += W * nthr * cpw;
     }
     return lim;
@@ -219,7 +238,7 @@ __device__ __forceinline__ void grid_segments(const SView& A, const SView& B, in
 // direct engine queues the LCP and the whole workgroup extends it after the
 // round barrier (the queue and its counter alternate with the round parity,
 // so the next round's pushes never meet this round's reads).
-template <typename PrevPtr, typename CurPtr>
+template <int WGW, typename PrevPtr, typename CurPtr>
 __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr prev, CurPtr cur,
                                             int32_t ofs, int32_t i_begin, int32_t i_end, RoundShared& RS,
                                             JobCursor& jc, int32_t* dump_row, int32_t dlo, int32_t dhi,
@@ -339,11 +358,11 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
     const int32_t jend = RS.jcount[par];
     const int32_t nj = imin(jend - jstart, kJobHalf);
     jc.start[par] = jend;
-    if (nj > 0) {
+    if (en.kind == 0 && nj > 0) {  // only the direct engine queues LCPs
         for (int j = 0; j < nj; ++j) {
             const int32_t jx = RS.jx[half + j];
             const int32_t jy = RS.jy[half + j], jlim = RS.jlim[half + j], jl = RS.jl[half + j];
-            const int32_t r = lcp_wg_direct(en.A, en.B, jx, jy, jlim, jl, RS.wmin);
+            const int32_t r = lcp_wg_direct<WGW>(en.A, en.B, jx, jy, jlim, jl, RS.wmin);
             if (tid == 0) {
                 const int32_t i = RS.ji[half + j];
                 const int32_t f = jx + r;
@@ -399,6 +418,7 @@ template <typename T>
 __device__ __forceinline__ const T* uni(const T* p) {
     return reinterpret_cast<const T*>(uni(reinterpret_cast<uint64_t>(p)));
 }
+__device__ __forceinline__ gword* uni(gword* p) { return (gword*)uni(reinterpret_cast<uint64_t>(p)); }
 
 // KIND (0 direct, 1 hash) is a compile-time constant in every kernel that
 // runs rounds, so the other engine's code and fields drop out of it.
@@ -415,11 +435,12 @@ __device__ __forceinline__ Engine make_engine(const PairDev& p, const HashDev& h
     en.A.lcpw = en.B.lcpw = uni(en.A.lcpw);
     en.A.bpc = en.B.bpc = uni(en.A.bpc);
     if (KIND == 1) {
-        en.TA = uni(p.a.tab);
-        en.TB = uni(p.b.tab);
+        en.TA = uni((gword*)p.a.tab);
+        en.TB = uni((gword*)p.b.tab);
         en.q.h.r = uni(h.r);
-        en.q.h.pow0 = uni(h.pow0);
-        en.q.h.pow1 = uni(h.pow1);
+        en.q.h.pow0 = en.q.h.pow1 = nullptr;
+        en.q.pow0 = uni((gword*)h.pow0);
+        en.q.pow1 = uni((gword*)h.pow1);
         en.q.r4 = mp_mul(mp_mul(en.q.h.r, en.q.h.r), mp_mul(en.q.h.r, en.q.h.r));
         en.q.lut4 = lut4;
         en.q.log2b = uni(p.log2b);
@@ -427,6 +448,7 @@ __device__ __forceinline__ Engine make_engine(const PairDev& p, const HashDev& h
         en.TA = en.TB = nullptr;
         en.q.h.r = 0;
         en.q.h.pow0 = en.q.h.pow1 = nullptr;
+        en.q.pow0 = en.q.pow1 = nullptr;
         en.q.r4 = 0;
         en.q.lut4 = nullptr;
         en.q.log2b = 0;
@@ -532,7 +554,7 @@ __device__ void solo_task(const TaskParams& P, int32_t pi, LdsState& L, JobCurso
     if (tid == 0) RS.flag = 0;
     __syncthreads();
     if (t == 0) {
-        round_range(en, 0, la, la, off, -2, 3, RS, jc, nullptr, 0, -1, cnt);
+        round_range<kWgWordsTask>(en, 0, la, la, off, -2, 3, RS, jc, nullptr, 0, -1, cnt);
     } else {
         for (int32_t e = tid; e < 2 * t + 5; e += nthr) la[off + e - (t + 2)] = g[K + 2 + e - (t + 2)];
         __syncthreads();
@@ -546,7 +568,7 @@ __device__ void solo_task(const TaskParams& P, int32_t pi, LdsState& L, JobCurso
         if (t >= t_limit) { status = 5; break; }
         if (t >= lr) break;
         ++t;
-        round_range(en, t, la, lb, off, -(t + 2), t + 3, RS, jc, nullptr, 0, -1, cnt);
+        round_range<kWgWordsTask>(en, t, la, lb, off, -(t + 2), t + 3, RS, jc, nullptr, 0, -1, cnt);
         int32_t* tmp = la;
         la = lb;
         lb = tmp;
@@ -598,7 +620,7 @@ __device__ void chunk_task(const TaskParams& P, int32_t pi, int32_t c, LdsState&
     int32_t* rc = L.row[1];
     for (int32_t s = 1; s <= H; ++s) {
         const int32_t tt = t + s;
-        if (round_range(en, tt, rp, rc, wofs, a - (H - s), b + (H - s) + 1, RS, jc, nullptr, 0, -1, cnt))
+        if (round_range<kWgWordsTask>(en, tt, rp, rc, wofs, a - (H - s), b + (H - s) + 1, RS, jc, nullptr, 0, -1, cnt))
             atomicMin(&S->found_t, tt);
         int32_t* tmp = rp;
         rp = rc;
@@ -680,7 +702,7 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
             const int32_t off = kLdsRoundsMax + 2;  // diagonal i at row[i + off]
             int32_t* la = L.row[0];
             int32_t* lb = L.row[1];
-            round_range(en, 0, la, la, off, -2, 3, RS, jc, dump && P.dump_cap >= 1 ? dump : nullptr, 0, 0, cnt);
+            round_range<kWgWords>(en, 0, la, la, off, -2, 3, RS, jc, dump && P.dump_cap >= 1 ? dump : nullptr, 0, 0, cnt);
             const int32_t lr = imin(imin(P.lds_rounds, kLdsRoundsMax), K);
             int32_t status = 0, result = 0;
             for (;;) {
@@ -689,7 +711,7 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
                 if (t > maxnm) { status = 4; result = t; break; }
                 if (t >= lr) break;
                 ++t;
-                round_range(en, t, la, lb, off, -(t + 2), t + 3, RS, jc, dump_row_for(dump, P.dump_cap, t), -t, t, cnt);
+                round_range<kWgWords>(en, t, la, lb, off, -(t + 2), t + 3, RS, jc, dump_row_for(dump, P.dump_cap, t), -t, t, cnt);
                 int32_t* tmp = la;
                 la = lb;
                 lb = tmp;
@@ -762,7 +784,7 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
                 const int32_t e0 = imin(total1, static_cast<int32_t>(blockIdx.x) * c1);
                 const int32_t e1 = imin(total1, e0 + c1);
                 if (e0 < e1 &&
-                    round_range(en, t1, gp, gc, gofs, e0 - (t1 + 2), e1 - (t1 + 2), RS, jc,
+                    round_range<kWgWords>(en, t1, gp, gc, gofs, e0 - (t1 + 2), e1 - (t1 + 2), RS, jc,
                                 dump_row_for(dump, P.dump_cap, t1), -t1, t1, cnt))
                     atomicMin(&ctl->found_t, t1);
                 grid_sync(ctl, P.bar, ++epoch);
@@ -787,7 +809,7 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
                 int32_t* rc = L.row[1];
                 for (int32_t s = 1; s <= H; ++s) {
                     const int32_t tt = t + s;
-                    if (round_range(en, tt, rp, rc, wofs, a - (H - s), b + (H - s) + 1, RS, jc,
+                    if (round_range<kWgWords>(en, tt, rp, rc, wofs, a - (H - s), b + (H - s) + 1, RS, jc,
                                     dump_row_for(dump, P.dump_cap, tt), imax(a, -tt), imin(b, tt), cnt))
                         atomicMin(&ctl->found_t, tt);
                     int32_t* tmp = rp;
@@ -875,7 +897,7 @@ __global__ __launch_bounds__(kFrontierThreads) void lcp_query_wg_kernel(LcpQuery
         const int32_t y = static_cast<int32_t>(Q.y[qi]);
         const int32_t la = en.A.len - x, lb = en.B.len - y;
         const int32_t lim = la < lb ? la : lb;
-        const int32_t l = lcp_wg_direct(en.A, en.B, x, y, lim, 0, wmin);
+        const int32_t l = lcp_wg_direct<kWgWords>(en.A, en.B, x, y, lim, 0, wmin);
         if (threadIdx.x == 0) Q.out[qi] = l;
     }
 }
