@@ -52,11 +52,12 @@ struct SView {
     int32_t len;
     int32_t lcpw;  // 5 (2-bit) or 3 (8-bit)
     int32_t bpc;   // 2 or 8
+    int32_t lbpc;  // log2(bpc): shifts instead of divisions
 };
 
 __device__ __forceinline__ uint64_t fetch(const SView& s, int32_t pos) {
     const int32_t q = pos >> s.lcpw;
-    const uint32_t sh = static_cast<uint32_t>((pos & ((1 << s.lcpw) - 1)) * s.bpc);
+    const uint32_t sh = static_cast<uint32_t>((pos & ((1 << s.lcpw) - 1)) << s.lbpc);
     const uint64_t lo = s.w[q];
     const uint64_t hi = s.w[q + 1];
     // (hi << 1) << (63 - sh) equals hi << (64 - sh) and is 0 for sh = 0
@@ -71,6 +72,7 @@ __device__ __forceinline__ void pair_views(const PairDev& p, uint32_t alpha, SVi
     B.len = p.b.len;
     A.lcpw = B.lcpw = two ? 5 : 3;
     A.bpc = B.bpc = two ? 2 : 8;
+    A.lbpc = B.lbpc = two ? 1 : 3;
 }
 
 // ---------------------------------------------------------------------------
@@ -86,7 +88,7 @@ __device__ __forceinline__ int32_t lcp_lane(const SView& A, const SView& B, int3
         if (l >= lim) return lim;
         const uint64_t d = fetch(A, x + l) ^ fetch(B, y + l);
         if (d) {
-            const int32_t c = l + ctz64(d) / A.bpc;
+            const int32_t c = l + (ctz64(d) >> A.lbpc);
             return c < lim ? c : lim;
         }
         l += cpw;
@@ -104,10 +106,9 @@ __device__ __forceinline__ int32_t lcp_lane(const SView& A, const SView& B, int3
 __device__ __forceinline__ int32_t lcp_wave_direct(const SView& A, const SView& B, int32_t x,
                                                    int32_t y, int32_t lim, int32_t l) {
     const int lane = lane_id();
-    const int32_t cpw = 1 << A.lcpw;
     while (l < lim) {
-        const int32_t p0 = l + lane * cpw;
-        const int32_t p1 = p0 + 64 * cpw;
+        const int32_t p0 = l + (lane << A.lcpw);
+        const int32_t p1 = p0 + (64 << A.lcpw);
         uint64_t d0 = 0, d1 = 0;
         if (p0 < lim) d0 = fetch(A, x + p0) ^ fetch(B, y + p0);
         if (p1 < lim) d1 = fetch(A, x + p1) ^ fetch(B, y + p1);
@@ -115,17 +116,17 @@ __device__ __forceinline__ int32_t lcp_wave_direct(const SView& A, const SView& 
         if (b0) {
             const int s = ctz64(b0);
             const uint64_t dd = shfl_u64(d0, s);
-            const int32_t c = l + s * cpw + ctz64(dd) / A.bpc;
+            const int32_t c = l + (s << A.lcpw) + (ctz64(dd) >> A.lbpc);
             return c < lim ? c : lim;
         }
         const uint64_t b1 = ballot(d1 != 0);
         if (b1) {
             const int s = ctz64(b1);
             const uint64_t dd = shfl_u64(d1, s);
-            const int32_t c = l + (64 + s) * cpw + ctz64(dd) / A.bpc;
+            const int32_t c = l + ((64 + s) << A.lcpw) + (ctz64(dd) >> A.lbpc);
             return c < lim ? c : lim;
         }
-        l += 128 * cpw;
+        l += 128 << A.lcpw;
     }
     return lim;
 }
@@ -146,12 +147,11 @@ __device__ __forceinline__ int32_t lcp_wave_steps(const SView& A, const SView& B
                                                   int32_t lim, int32_t l, int steps, bool& done) {
     constexpr int W = 4;
     const int lane = lane_id();
-    const int32_t cpw = 1 << A.lcpw;
     for (int s = 0; s < steps && l < lim; ++s) {
         uint64_t d[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-            const int32_t p = l + (w * 64 + lane) * cpw;
+            const int32_t p = l + ((w * 64 + lane) << A.lcpw);
             const bool ok = p < lim;
             const int32_t q = ok ? p : 0;
             const uint64_t v = fetch(A, x + q) ^ fetch(B, y + q);
@@ -162,12 +162,12 @@ __device__ __forceinline__ int32_t lcp_wave_steps(const SView& A, const SView& B
             const uint64_t b = ballot(d[w] != 0);
             if (b) {
                 const int s0 = ctz64(b);
-                const int32_t c = l + (w * 64 + s0) * cpw + ctz64(shfl_u64(d[w], s0)) / A.bpc;
+                const int32_t c = l + ((w * 64 + s0) << A.lcpw) + (ctz64(shfl_u64(d[w], s0)) >> A.lbpc);
                 done = true;
                 return c < lim ? c : lim;
             }
         }
-        l += W * 64 * cpw;
+        l += (W * 64) << A.lcpw;
     }
     done = l >= lim;
     return l < lim ? l : lim;
@@ -318,14 +318,14 @@ __device__ __forceinline__ int32_t lcp_wave_hash(const SView& A, const SView& B,
     }
     // direct step over [lo, hi): hi is certainly unequal (different hashes
     // mean different strings), so a mismatch lies in [0, hi)
-    const int32_t p = lo + lane * cpw;
+    const int32_t p = lo + (lane << A.lcpw);
     uint64_t d = 0;
     if (p < hi) d = fetch(A, x + p) ^ fetch(B, y + p);
     const uint64_t bm = ballot(d != 0);
     if (bm) {
         const int s = ctz64(bm);
         const uint64_t dd = shfl_u64(d, s);
-        const int32_t c = lo + s * cpw + ctz64(dd) / A.bpc;
+        const int32_t c = lo + (s << A.lcpw) + (ctz64(dd) >> A.lbpc);
         if (c < hi) return c;
     }
     // no mismatch in [lo, hi): a collision hid one below lo

@@ -91,8 +91,8 @@ __device__ __forceinline__ void rs_init(RoundShared& RS, JobCursor& jc) {
 template <int W>
 __device__ __forceinline__ int32_t wg_step(const SView& A, const SView& B, int32_t x, int32_t y, int32_t lim,
                                            int32_t l, int32_t& wmin) {
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    const int32_t cpw = 1 << A.lcpw;
+    const int tid = threadIdx.x;
+    constexpr int nthr = kFrontierThreads;  // every launch of these kernels
     if (tid == 0) wmin = INT_MAX;
     __syncthreads();
     // every word first (all loads in flight together), then this lane's
@@ -101,15 +101,15 @@ __device__ __forceinline__ int32_t wg_step(const SView& A, const SView& B, int32
     uint64_t d[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-        const int32_t p = l + (w * nthr + tid) * cpw;
+        const int32_t p = l + ((w * nthr + tid) << A.lcpw);
         const int32_t q = p < lim ? p : 0;
         d[w] = fetch(A, x + q) ^ fetch(B, y + q);
     }
     int32_t first = INT_MAX;
 #pragma unroll
     for (int w = W - 1; w >= 0; --w) {
-        const int32_t p = l + (w * nthr + tid) * cpw;
-        if (p < lim && d[w]) first = p + ctz64(d[w]) / A.bpc;
+        const int32_t p = l + ((w * nthr + tid) << A.lcpw);
+        if (p < lim && d[w]) first = p + (ctz64(d[w]) >> A.lbpc);
     }
     first = wave_min(first);
     if (lane_id() == 0 && first != INT_MAX) atomicMin(&wmin, first);
@@ -124,17 +124,16 @@ __device__ __forceinline__ int32_t wg_step(const SView& A, const SView& B, int32
 template <int W>
 __device__ __forceinline__ int32_t lcp_wg_direct(const SView& A, const SView& B, int32_t x, int32_t y,
                                                  int32_t lim, int32_t l, int32_t& wmin) {
-    const int32_t nthr = blockDim.x;
-    const int32_t cpw = 1 << A.lcpw;
+    constexpr int32_t nthr = kFrontierThreads;
     if (l < lim) {
         const int32_t m = wg_step<4>(A, B, x, y, lim, l, wmin);
         if (m != INT_MAX) return m < lim ? m : lim;
-        l += 4 * nthr * cpw;
+        l += (4 * nthr) << A.lcpw;
     }
     while (l < lim) {
         const int32_t m = wg_step<W>(A, B, x, y, lim, l, wmin);
         if (m != INT_MAX) return m < lim ? m : lim;
-        l += W * nthr * cpw;
+        l += (W * nthr) << A.lcpw;
     }
     return lim;
 }
@@ -208,12 +207,12 @@ __device__ __forceinline__ void grid_segments(const SView& A, const SView& B, in
         int32_t first = INT_MAX;
 #pragma unroll
         for (int w = kGridWords - 1; w >= 0; --w) {
-            const int32_t rel = (w * 64 + lane) * cpw;
+            const int32_t rel = (w * 64 + lane) << A.lcpw;
             const int64_t pp = start + rel;
             const bool ok = pp < lim;
             const int32_t q = ok ? static_cast<int32_t>(pp) : 0;
             const uint64_t v = fetch(A, x + q) ^ fetch(B, y + q);
-            if (ok && v) first = rel + ctz64(v) / A.bpc;
+            if (ok && v) first = rel + (ctz64(v) >> A.lbpc);
         }
         first = wave_min(first);
         const bool hit = first != INT_MAX;
@@ -243,7 +242,8 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
                                             int32_t ofs, int32_t i_begin, int32_t i_end, RoundShared& RS,
                                             JobCursor& jc, int32_t* dump_row, int32_t dlo, int32_t dhi,
                                             Cnt& cnt) {
-    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int tid = threadIdx.x;
+    constexpr int nthr = kFrontierThreads;  // every launch of the round kernels
     const int lane = tid & 63;
     const int32_t n = en.A.len, m = en.B.len;
     const int32_t lo = imax(-t, -m), hi = imin(t, n);
@@ -307,8 +307,8 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
             d0[u] = d1[u] = 0;
             if (!slot[u]) continue;
             const bool go = lim[u] > 0;
-            const uint32_t sa = go ? static_cast<uint32_t>(c[u] & qmask) * en.A.bpc : 0;
-            const uint32_t sb = go ? static_cast<uint32_t>((c[u] - iv[u]) & qmask) * en.A.bpc : 0;
+            const uint32_t sa = go ? static_cast<uint32_t>(c[u] & qmask) << en.A.lbpc : 0;
+            const uint32_t sb = go ? static_cast<uint32_t>((c[u] - iv[u]) & qmask) << en.A.lbpc : 0;
             // (hi << 1) << (63 - sh) equals hi << (64 - sh) and is 0 for sh = 0
             const uint64_t a0 = (wa[u][0] >> sa) | ((wa[u][1] << 1) << (63 - sa));
             const uint64_t a1 = (wa[u][1] >> sa) | ((wa[u][2] << 1) << (63 - sa));
@@ -318,11 +318,11 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
             d1[u] = a1 ^ b1;
             if (go) {
                 if (d0[u]) {
-                    l[u] = imin(ctz64(d0[u]) / en.A.bpc, lim[u]);
+                    l[u] = imin((ctz64(d0[u]) >> en.A.lbpc), lim[u]);
                 } else if (lim[u] <= cpw) {
                     l[u] = lim[u];
                 } else if (d1[u]) {
-                    l[u] = imin(cpw + ctz64(d1[u]) / en.A.bpc, lim[u]);
+                    l[u] = imin(cpw + (ctz64(d1[u]) >> en.A.lbpc), lim[u]);
                 } else if (lim[u] <= 2 * cpw) {
                     l[u] = lim[u];
                 } else {
@@ -434,6 +434,7 @@ __device__ __forceinline__ Engine make_engine(const PairDev& p, const HashDev& h
     en.B.len = uni(en.B.len);
     en.A.lcpw = en.B.lcpw = uni(en.A.lcpw);
     en.A.bpc = en.B.bpc = uni(en.A.bpc);
+    en.A.lbpc = en.B.lbpc = uni(en.A.lbpc);
     if (KIND == 1) {
         en.TA = uni((gword*)p.a.tab);
         en.TB = uni((gword*)p.b.tab);
