@@ -156,6 +156,42 @@ def lcp_leg(ed, n=10 ** 9):
     return out
 
 
+def table_leg(ed, n=10 ** 9, k=1000, reps=3):
+    """Prefix-table build at 8 bits per character: the n = 1e9 Zipf(1.0) pair
+    over 256 symbols (k = 1000 planted edits, seed 0), hash engine, b = 32.
+    Algorithmic bytes of the table kernels: both strings' 8-bit words read
+    once, both tables written; of the whole prepare: the input read, the
+    8-bit copy written, the tables written."""
+    import torch
+    import synth
+    log("table leg: generating the n=%d Zipf pair" % n)
+    A, B, _ = synth.single_pair(n, k, 0, kind="zipf")
+    lens = (len(A), len(B))
+    tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    del A, B
+    ctx = ed.ed_init(0, engine=ed.ENGINE_HASH, flags=ed.FLAG_TIMING)
+    best = None
+    for _ in range(reps + 1):
+        p = ed.ed_prepare(ctx, tA, tB)
+        st = ed.ed_pair_stats(p)
+        ed.ed_release(p)
+        cur = (st["gpu_ns_table_kernel"], st["gpu_ns_prepare_kernel"])
+        best = cur if best is None or cur[0] < best[0] else best
+    ed.ed_shutdown(ctx)
+    del tA, tB
+    torch.cuda.empty_cache()
+    tbytes = sum(L + 8 * (L // 32 + 1) for L in lens)
+    pbytes = sum(2 * L + 8 * (L // 32 + 1) for L in lens)
+    return {"workload": "n=%d Zipf(1.0) over 256 symbols, k=%d, seed 0, hash engine, b=32" % (n, k),
+            "bits_per_char": st["bits_per_char"],
+            "table_kernels_ms": round(best[0] / 1e6, 4), "table_bytes": tbytes,
+            "table_achieved_GBs": round(tbytes / best[0], 1),
+            "table_frac_of_hbm_peak": round(tbytes / best[0] / PEAK_HBM_GBS, 4),
+            "prepare_ms": round(best[1] / 1e6, 4), "prepare_bytes": pbytes,
+            "prepare_achieved_GBs": round(pbytes / best[1], 1),
+            "prepare_frac_of_hbm_peak": round(pbytes / best[1] / PEAK_HBM_GBS, 4)}
+
+
 def serve_leg(ed, ctx, count, seed=0, warmup=0):
     """Served workload: Poisson arrivals, n = floor(10^U), U ~ U[2, 7], alphabet 4
     or 20, k ~ U{0..floor(0.05 n)}.  The arrival rate is 0.7x the batched
@@ -257,6 +293,7 @@ def main():
     ap.add_argument("--no-other-engine", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 4096-pair batch leg")
     ap.add_argument("--no-lcp", action="store_true", help="skip the long-LCP bandwidth leg")
+    ap.add_argument("--no-table", action="store_true", help="skip the 8-bit table-build leg")
     ap.add_argument("--serve", type=int, default=40, metavar="N",
                     help="requests of the serving leg (0 skips it)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -369,20 +406,30 @@ def main():
                 "traffic": measured_traffic(dom, main_engine, ks, n),
                 "algorithmic_bytes_per_launch": byts, "avg_launch_ms": round(avg_ns / 1e6, 4)}
 
-    def prep_roofline(engine, prep_ms):
+    def prep_roofline(engine, prep_ms, table_ms=None):
         """Prepare kernels (pack, [table]) against the HBM peak: algorithmic
-        bytes = input read once + packed words written [+ prefix table written]."""
-        byts = 0
+        bytes = input read once + packed words written [+ prefix table written];
+        for the hash engine also the table kernels alone (packed words read
+        once, table written)."""
+        byts = tbyts = 0
         for i in range(len(ks)):
             for L in (n, host[i][2]["m"]):
                 byts += L + L * bits / 8 + (8 * (L // 32 + 1) if engine == "hash" else 0)
+                tbyts += L * bits / 8 + 8 * (L // 32 + 1)
         byts /= len(ks)
+        tbyts /= len(ks)
         avg_ns = sum(prep_ms) / len(prep_ms) * 1e6
-        return {"engine": engine, "bound": "hbm", "achieved": round(byts / avg_ns, 3), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": round(byts / avg_ns / PEAK_HBM_GBS, 4),
-                "algorithmic_bytes_per_call": byts, "avg_ms": round(avg_ns / 1e6, 4)}
+        out = {"engine": engine, "bound": "hbm", "achieved": round(byts / avg_ns, 3), "peak": PEAK_HBM_GBS,
+               "unit": "GB/s", "frac": round(byts / avg_ns / PEAK_HBM_GBS, 4),
+               "algorithmic_bytes_per_call": byts, "avg_ms": round(avg_ns / 1e6, 4)}
+        if engine == "hash" and table_ms:
+            tns = sum(table_ms) / len(table_ms) * 1e6
+            out["table_build"] = {"achieved": round(tbyts / tns, 3), "frac": round(tbyts / tns / PEAK_HBM_GBS, 4),
+                                  "algorithmic_bytes_per_call": tbyts, "avg_ms": round(tns / 1e6, 4)}
+        return out
 
-    prepare_roofline = [prep_roofline(main_engine, [x / 1e6 for x in prep_ns])]
+    table_ms = [st["gpu_ns_table_kernel"] / 1e6 for r in results for _, st in r]
+    prepare_roofline = [prep_roofline(main_engine, [x / 1e6 for x in prep_ns], table_ms)]
     gold = stored_oracle()
     exact = None
     if gold and n == N:
@@ -405,7 +452,8 @@ def main():
                 "host_wall_ms": round((st["ns_prepare"] + st["ns_distance"]) / 1e6, 4)}
             if k != last[i][0]:
                 raise SystemExit("engines disagree at k=%d: %d vs %d" % (ks[i], k, last[i][0]))
-        prepare_roofline.append(prep_roofline(oname, [st["gpu_ns_prepare_kernel"] / 1e6 for _, st in r]))
+        prepare_roofline.append(prep_roofline(oname, [st["gpu_ns_prepare_kernel"] / 1e6 for _, st in r],
+                                              [st["gpu_ns_table_kernel"] / 1e6 for _, st in r]))
 
     batch = None
     if not args.no_batch:
@@ -414,6 +462,9 @@ def main():
     if not args.no_lcp:
         log("lcp leg: one LCP of 1e9 characters on the grid tier")
         lcp = lcp_leg(ed)
+    table = None
+    if not args.no_table:
+        table = table_leg(ed)
     serve = None
     if args.serve > 0:
         serve = serve_leg(ed, ctxs["direct"], args.serve)
@@ -453,6 +504,7 @@ def main():
         "other_engine": other,
         "batch": batch,
         "lcp_extension": lcp,
+        "table_build_8bit": table,
         "serve": serve,
     }
     print(json.dumps(line))

@@ -175,6 +175,9 @@ typedef struct ed_stats {
      * grid tier (engine 3), all its queries */
     double gpu_ns_lcp_kernel;
     uint64_t wg_lcps;         /* LCPs extended by a whole workgroup (workgroup tier) */
+    /* with ED_FLAG_TIMING, hash engine: HIP-event time of the prefix-table
+     * kernels alone (part of gpu_ns_prepare_kernel; 0 for the direct engine) */
+    double gpu_ns_table_kernel;
 } ed_stats;
 
 int ed_pair_stats(const ed_pair *pair, ed_stats *out);

@@ -75,7 +75,7 @@ class ed_stats(ctypes.Structure):
                 ("gpu_ns_frontier_kernel", ctypes.c_double),
                 ("rounds_phase_a", ctypes.c_uint64), ("us_phase_a", ctypes.c_double),
                 ("us_phase_b", ctypes.c_double), ("gpu_ns_lcp_kernel", ctypes.c_double),
-                ("wg_lcps", ctypes.c_uint64)]
+                ("wg_lcps", ctypes.c_uint64), ("gpu_ns_table_kernel", ctypes.c_double)]
 
 
 class ed_result(ctypes.Structure):

@@ -52,6 +52,11 @@ static uint64_t hmul(uint64_t a, uint64_t b) {
     return s >= kP ? s - kP : s;
 }
 
+static uint64_t hadd(uint64_t a, uint64_t b) {
+    const uint64_t s = a + b;
+    return s >= kP ? s - kP : s;
+}
+
 static uint64_t hpow(uint64_t r, uint64_t e) {
     uint64_t acc = 1, b = r;
     while (e) {
@@ -170,13 +175,33 @@ int ed::ctx_set_hash(ed_ctx* c, uint64_t seed) {
     p1[0] = 1;
     for (int i = 1; i < 65536; ++i) p1[i] = hmul(p1[i - 1], r16);
     for (int i = 0; i < 65; ++i) rt[i] = p0[i];
-    for (int k = 0; k < 257; ++k) rt[65 + k] = hpow(r, 64ull * k);
+    for (int k = 0; k < 257; ++k) rt[kRtabRseg + k] = hpow(r, 64ull * k);
     const uint64_t R = hpow(r, kTileChars);
     uint64_t a = 1;
     for (int d = 0; d < 65; ++d) {
-        rt[65 + 257 + d] = a;
+        rt[kRtabR + d] = a;
         a = hmul(a, R);
     }
+    for (int k = 0; k < 8; ++k)
+        for (int v = 0; v < 256; ++v) {
+            uint64_t h = 0;
+            for (int j = 0; j < 4; ++j) h = hadd(h, hmul(static_cast<uint64_t>((v >> (2 * j)) & 3), p0[31 - 4 * k - j]));
+            rt[kRtabLut32 + 256 * k + v] = h;
+            rt[kRtabLut8 + 256 * k + v] = hmul(static_cast<uint64_t>(v), p0[7 - k]);
+        }
+    // inverse powers: r^(P-2) = r^-1 (P prime, r not 0)
+    const uint64_t rinv256 = hpow(hpow(r, kP - 2), 256);
+    a = 1;
+    for (int d = 0; d < 65; ++d) {
+        rt[kRtabRinv256 + d] = a;
+        a = hmul(a, rinv256);
+    }
+    a = hpow(R, 8);
+    for (int j = 0; j < 10; ++j) {
+        rt[kRtabR8pow2 + j] = a;
+        a = hmul(a, a);
+    }
+    for (int l = 0; l < 64; ++l) rt[kRtabR8lane + l] = hpow(R, 8ull * (l + 1));
     if (!c->d_pow) {
         HIP_TRY(hipMalloc(&c->d_pow, kPowEntries * sizeof(uint64_t)));
     }
@@ -364,11 +389,12 @@ int ed::prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B
         }
     }
     const int32_t total = tiles[0] + tiles[1];
-    // alphabet word | tile hashes | chunk flags | tile prefixes
+    // alphabet word | tile hashes | chunk flags | tile prefixes | [lane prefixes]
     const size_t agg_off = kMiscAlpha + 64;
     const size_t big_off = agg_off + static_cast<size_t>(total) * 8;
     const size_t pre_off = big_off + ((static_cast<size_t>(total) * kTileChunks + 7) & ~size_t(7));
-    p->misc = c->pool.get(pre_off + static_cast<size_t>(total) * 8);
+    const size_t lane_off = pre_off + static_cast<size_t>(total) * 8;
+    p->misc = c->pool.get(lane_off + (table ? static_cast<size_t>(total) * 64 * 8 : 0));
     if (!p->misc) {
         pair_free(p);
         delete p;
@@ -419,24 +445,31 @@ int ed::prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B
     pp.r = c->r;
     pp.tile_agg = reinterpret_cast<uint64_t*>(misc + agg_off);
     pp.tile_prefix = reinterpret_cast<uint64_t*>(misc + pre_off);
+    pp.lane_excl = table ? reinterpret_cast<uint64_t*>(misc + lane_off) : nullptr;
     pp.alpha = reinterpret_cast<uint32_t*>(misc + kMiscAlpha);
+    pp.packed_any = reinterpret_cast<uint32_t*>(misc + kMiscAlpha + 4);
     pp.chunk_big = reinterpret_cast<uint8_t*>(misc + big_off);
     pp.rtab = c->d_pow + 2 * 65536;
     // pack: two workgroups per CU, each taking many chunks (more workgroups
-    // measured slower); table passes: as many workgroups as fit by LDS
+    // measured slower); table passes: as many workgroups as fit by LDS (at
+    // most one tile per wavefront)
     const int stream_grid = std::max(1, std::min(total, c->num_cu * 2));
-    const int table_grid = std::max(1, std::min(total, c->num_cu * 6));
+    const int table_grid = c->num_cu * 4;
     HIP_TRY(launch_prep_clear(pp, s));
     if (c->opt.flags & ED_FLAG_TIMING) {
         HIP_TRY(hipEventCreate(&p->ev_prep[0]));
         HIP_TRY(hipEventCreate(&p->ev_prep[1]));
+        if (table) HIP_TRY(hipEventCreate(&p->ev_prep[2]));
         HIP_TRY(hipEventRecord(p->ev_prep[0], s));
         p->prep_timed = true;
     }
     HIP_TRY(launch_pack(pp, stream_grid, s));
     // usually exits at once (packable pair): a small grid keeps that cheap
     if (c->opt.pack_bits != 2) HIP_TRY(launch_copy8_rest(pp, std::max(1, std::min(total, c->num_cu)), s));
-    if (table) HIP_TRY(launch_table(pp, table_grid, s));
+    if (table) {
+        if (p->prep_timed) HIP_TRY(hipEventRecord(p->ev_prep[2], s));
+        HIP_TRY(launch_table(pp, table_grid, s));
+    }
     if (p->prep_timed) HIP_TRY(hipEventRecord(p->ev_prep[1], s));
     p->launches_prepare = 2 + (c->opt.pack_bits != 2 ? 1 : 0) + (table ? 1 : 0);
     if (c->opt.pack_bits == 2) {
@@ -721,6 +754,8 @@ int ed_pair_stats(const ed_pair* p, ed_stats* o) {
         if (hipEventSynchronize(p->ev_prep[1]) == hipSuccess &&
             hipEventElapsedTime(&ms, p->ev_prep[0], p->ev_prep[1]) == hipSuccess)
             o->gpu_ns_prepare_kernel = 1e6 * ms;
+        if (p->ev_prep[2] && hipEventElapsedTime(&ms, p->ev_prep[2], p->ev_prep[1]) == hipSuccess)
+            o->gpu_ns_table_kernel = 1e6 * ms;
     }
     return ED_OK;
 }
@@ -833,7 +868,7 @@ int ed_debug_lcp(ed_ctx* c, ed_pair* p, int engine, const int64_t* x, const int6
         if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) p->gpu_ns_lcp = 1e6 * ms;
     }
     for (hipEvent_t v : ev)
-        if (v) hipEventDestroy(v);
+        if (v) (void)hipEventDestroy(v);
     if (e != hipSuccess) {
         set_error("ed_debug_lcp: %s", hipGetErrorString(e));
         return ED_EDEVICE;

@@ -26,7 +26,7 @@ class DevPool {
 };
 
 // pow0 (65536) | pow1 (65536) | r^0..r^64 | r^(64k), k = 0..256 | R^d, d = 0..64
-constexpr size_t kPowEntries = 2 * 65536 + 65 + 257 + 65;
+constexpr size_t kPowEntries = 2 * 65536 + kRtabEntries;
 
 // layout of a pair's small device block
 constexpr size_t kMiscAlpha = 64;
@@ -74,7 +74,8 @@ struct ed_pair {
     int launches_prepare = 0;
     int launches_distance = 0;
     double ns_prepare = 0, ns_distance = 0;
-    hipEvent_t ev_prep[2] = {nullptr, nullptr};  // around the prepare kernel (ED_FLAG_TIMING)
+    // around the prepare kernels, and before the table kernels (ED_FLAG_TIMING)
+    hipEvent_t ev_prep[3] = {nullptr, nullptr, nullptr};
     bool prep_timed = false;
     double gpu_ns_frontier = 0;
     double gpu_ns_lcp = 0;  // last ed_debug_lcp with the grid tier (ED_FLAG_TIMING)

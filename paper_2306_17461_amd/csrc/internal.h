@@ -172,10 +172,27 @@ struct PrepParams {
     uint64_t r;            // hash base
     uint64_t* tile_agg;    // total_tiles entries: hash of each tile
     uint64_t* tile_prefix; // total_tiles entries: hash of its string before each tile
+    uint64_t* lane_excl;   // 64 per tile: hash of the tile's characters before each lane's 256
     uint32_t* alpha;       // OR of all characters (atomicOr), zeroed before launch
+    uint32_t* packed_any;  // nonzero when some chunk had no character > 3 (zeroed before launch)
     uint8_t* chunk_big;    // per chunk (kTileChunks per tile): 1 if it has a character > 3
-    const uint64_t* rtab;  // r^0..r^64 | r^(64k), k = 0..256 | R^d, d = 0..64, R = r^kTileChars
+    const uint64_t* rtab;  // the kRtab* layout below
 };
+
+// Power and lookup tables of the table passes, built on the host with the
+// other power tables (R = r^kTileChars):
+//   r^p, p = 0..64 | r^(64k), k = 0..256 | R^d, d = 0..64 |
+//   lut32[k][v] = sum_j c_j r^(31-4k-j), c_j = 2-bit code j of byte v (k = 0..7) |
+//   lut8[k][v] = v r^(7-k) (k = 0..7) | r^(-256 d), d = 0..64 |
+//   R^(8 * 2^j), j = 0..9 | R^(8 (l + 1)), l = 0..63
+constexpr int kRtabRseg = 65;
+constexpr int kRtabR = kRtabRseg + 257;
+constexpr int kRtabLut32 = kRtabR + 65;
+constexpr int kRtabLut8 = kRtabLut32 + 8 * 256;
+constexpr int kRtabRinv256 = kRtabLut8 + 8 * 256;
+constexpr int kRtabR8pow2 = kRtabRinv256 + 65;
+constexpr int kRtabR8lane = kRtabR8pow2 + 10;
+constexpr int kRtabEntries = kRtabR8lane + 64;
 
 struct LcpQueryParams {
     PairDev p;

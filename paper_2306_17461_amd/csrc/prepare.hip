@@ -19,16 +19,16 @@ namespace {
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-struct PrepShared {
-    // one of the two, by the pair's packing (halves the LDS per workgroup)
+// LDS of the table passes (one of the two lookup tables, by the pair's packing)
+struct TableShared {
     union {
         uint64_t lut32[8][256];  // packed byte k of a 2-bit word: sum_j c_j r^(31-4k-j)
         uint64_t lut8[8][256];   // byte k of an 8-char word: v r^(7-k)
     };
-    uint64_t lut4[256];      // packed byte (4 chars): c0 r^3 + c1 r^2 + c2 r + c3
-    uint64_t rp[65];         // r^p
-    uint64_t rseg[257];      // r^(64 k)
-    uint64_t wsum[kPrepThreads / 64];
+    uint64_t rp[65];       // r^p
+    uint64_t rseg[257];    // r^(64 k)
+    uint64_t rinv256[65];  // r^(-256 d)
+    uint64_t stage[kPrepThreads / 64][64 * 9];  // per wavefront: T entries of a tile, 9 slots per lane
 };
 
 // The fields of one of the two strings, chosen by a uniform flag: a select
@@ -56,76 +56,35 @@ __device__ __forceinline__ uint32_t pack_dword(uint32_t d) {
     return (d & 3u) | ((d >> 6) & 0xCu) | ((d >> 12) & 0x30u) | ((d >> 18) & 0xC0u);
 }
 
-// Hash of the 64 characters of one segment, processed in units of U chars
-// (U divides b); when EMIT, writes T at every block end inside the segment.
-// `h` enters as the prefix hash at the segment start.
-template <bool EMIT>
-__device__ __forceinline__ uint64_t seg_pass(const PrepShared& S, const uint32_t (&dw)[16],
-                                             const uint64_t (&pk)[2], bool big, int32_t log2b,
-                                             uint64_t h, int32_t seg_start, int32_t len,
-                                             uint64_t* tab) {
-    const int32_t bmask = (1 << log2b) - 1;
-    auto emit = [&](int32_t pos) {
-        if (EMIT) {
-            const int32_t e = seg_start + pos;
-            if ((e & bmask) == 0 && e <= len) tab[e >> log2b] = h;
-        }
-    };
-    if (!big) {
-        if (log2b >= 5) {  // units of 32 characters: one packed word
-            for (int w = 0; w < 2; ++w) {
-                uint64_t s = 0;
+// Hash of a unit of U characters of a packed word (U = 4, 8, 16, 32; unit u
+// of the word): sum over its bytes of lut32[8 - U/4 + k], the entries whose
+// weights r^(U-1-4k-j) match the unit's length.  At most 8 terms below 2^61
+// are added before the fold, so the sum stays below 2^64.
+template <int U>
+__device__ __forceinline__ uint64_t unit_hash2(const TableShared& S, uint64_t w, int u) {
+    constexpr int nb = U / 4;
+    uint64_t s = 0;
 #pragma unroll
-                for (int k = 0; k < 8; ++k) s += S.lut32[k][(pk[w] >> (8 * k)) & 0xFF];
-                h = mp_add(mp_mul(h, S.rp[32]), mp_fold(s));
-                emit(32 * (w + 1));
-            }
-        } else if (log2b >= 2) {  // units of 4 characters: one packed byte
-            for (int u = 0; u < 16; ++u) {
-                const uint32_t byte = static_cast<uint32_t>(pk[u >> 3] >> (8 * (u & 7))) & 0xFFu;
-                h = mp_add(mp_mul(h, S.rp[4]), S.lut4[byte]);
-                emit(4 * (u + 1));
-            }
-        } else {  // single characters
-            for (int c = 0; c < 64; ++c) {
-                const uint64_t ch = (pk[c >> 5] >> (2 * (c & 31))) & 3u;
-                h = mp_add(mp_mul(h, S.rp[1]), ch);
-                emit(c + 1);
-            }
-        }
-    } else {
-        if (log2b >= 3) {  // units of 8 characters: one 8-bit word
-            for (int w = 0; w < 8; ++w) {
-                uint64_t s = 0;
-#pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const uint32_t v = (dw[2 * w + (k >> 2)] >> (8 * (k & 3))) & 0xFFu;
-                    s += S.lut8[k][v];
-                }
-                h = mp_add(mp_mul(h, S.rp[8]), mp_fold(s));
-                emit(8 * (w + 1));
-            }
-        } else {
-            for (int c = 0; c < 64; ++c) {
-                const uint64_t ch = (dw[c >> 2] >> (8 * (c & 3))) & 0xFFu;
-                h = mp_add(mp_mul(h, S.rp[1]), ch);
-                emit(c + 1);
-            }
-        }
-    }
-    return h;
+    for (int k = 0; k < nb; ++k) s += S.lut32[8 - nb + k][(w >> (8 * (u * nb + k))) & 0xFFu];
+    return mp_fold(s);
 }
 
-__device__ __forceinline__ uint64_t wave_sum_mod(uint64_t v) {
-    for (int o = 32; o > 0; o >>= 1) v = mp_add(v, __shfl_xor(static_cast<unsigned long long>(v), o));
-    return v;
+// Hash of one 8-bit word (8 characters).
+__device__ __forceinline__ uint64_t word_hash8(const TableShared& S, uint64_t w) {
+    uint64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += S.lut8[k][(w >> (8 * k)) & 0xFFu];
+    return mp_fold(s);
 }
 
 }  // namespace
 
 __global__ void prep_clear_kernel(PrepParams P) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i == 0) *P.alpha = 0u;
+    if (i == 0) {
+        *P.alpha = 0u;
+        *P.packed_any = 0u;
+    }
 }
 
 // Streaming pass: wavefront w takes chunks w, w + W, ... (W wavefronts in the
@@ -141,6 +100,7 @@ __global__ __launch_bounds__(kPrepThreads) void pack_kernel(PrepParams P) {
     const int32_t total = P.total_tiles * kTileChunks;
     const int32_t split = P.s[1].tile0 * kTileChunks;
     uint32_t orr = 0;
+    uint32_t packed_any = 0;  // this wavefront packed a chunk (no character > 3)
     for (int32_t g = wave; g < total; g += nwaves) {
         const StrSel str(P, g >= split);
         const int32_t c = g - str.tile0 * kTileChunks;
@@ -180,6 +140,7 @@ __global__ __launch_bounds__(kPrepThreads) void pack_kernel(PrepParams P) {
             for (int k = 0; k < 4; ++k) dst[k * 64 + lane] = v[k];
         }
         if (lane == 0) P.chunk_big[g] = big ? 1 : 0;
+        packed_any |= big ? 0u : 1u;
     }
     // one atomic per workgroup at most, and none when the bits are already
     // there: atomics on one address from every wavefront serialise
@@ -188,191 +149,332 @@ __global__ __launch_bounds__(kPrepThreads) void pack_kernel(PrepParams P) {
     orr |= orr >> 8;
     orr &= 0xFFu;
     for (int s = 32; s > 0; s >>= 1) orr |= __shfl_xor(orr, s);
-    if (lane == 0) wor[threadIdx.x >> 6] = orr;
+    if (lane == 0) wor[threadIdx.x >> 6] = orr | (packed_any << 8);
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t o = 0;
         for (int w = 0; w < kPrepThreads / 64; ++w) o |= wor[w];
         const uint32_t cur = __hip_atomic_load(P.alpha, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((cur | o) != cur) atomicOr(P.alpha, o);
+        if ((cur | (o & 0xFFu)) != cur) atomicOr(P.alpha, o & 0xFFu);
+        if ((o >> 8) && !__hip_atomic_load(P.packed_any, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicOr(P.packed_any, 1u);
     }
 }
 
 // Prefix tables of both strings (hash engine), after pack_kernel (and
-// copy8_rest_kernel), in three passes with no shared counter: tiles of 16384
-// characters are assigned statically to workgroups.
-//   table_tiles_kernel<false>  hash of every tile -> tile_agg[g]
-//   table_scan_kernel          per string, prefix hash before every tile ->
-//                              tile_prefix[g] (Horner over tiles, R = r^16384)
-//   table_tiles_kernel<true>   block-scan of each tile from its prefix and
-//                              T[j] at every block end inside it
+// copy8_rest_kernel), in three passes with no shared counter.  A tile of
+// 16384 characters is one wavefront's work, 256 consecutive characters per
+// lane; tiles are assigned statically to wavefronts.
+//   table_tiles_kernel<false>  per tile: the hash of each lane's characters
+//                              (Horner over words), an inclusive scan over the
+//                              lanes under h(S1 S2) = h(S1) r^|S2| + h(S2);
+//                              stores each lane's exclusive prefix within the
+//                              tile (lane_excl) and the tile's hash (tile_agg)
+//   table_scan_kernel          per string: prefix hash before every tile
+//                              (tile_prefix), Horner over tiles with R = r^16384
+//   table_tiles_kernel<true>   per lane: the prefix hash at its first
+//                              character from the two, then Horner over its
+//                              units with T[j] written at every block end
 // The characters come from the 2-bit words when the pair is packable, from the
-// 8-bit copy otherwise.
-template <bool EMIT>
-__global__ __launch_bounds__(kPrepThreads) void table_tiles_kernel(PrepParams P, const uint64_t* rtab) {
-    __shared__ PrepShared S;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const bool two = *P.alpha <= 3u;
+// 8-bit copy otherwise.  Past the end of a string the words are zero; values
+// there are never written to T.
+constexpr int kLaneChars = kTileChars / 64;    // 256
+constexpr int kLaneWords2 = kLaneChars / 32;   // 8 packed words
+constexpr int kLaneWords8 = kLaneChars / 8;    // 32 byte-words
 
-    // rtab: r^0..r^64 | r^(64k), k = 0..256 | R^d, d = 0..64
-    for (int i = tid; i < 65; i += kPrepThreads) S.rp[i] = rtab[i];
-    for (int i = tid; i < 257; i += kPrepThreads) S.rseg[i] = rtab[65 + i];
-    __syncthreads();
-    for (int e = tid; e < 8 * 256; e += kPrepThreads) {
-        const int k = e >> 8, v = e & 255;
-        if (two) {
-            uint64_t h = 0;
-            for (int j = 0; j < 4; ++j)
-                h = mp_add(h, mp_mul(static_cast<uint64_t>((v >> (2 * j)) & 3), S.rp[31 - 4 * k - j]));
-            S.lut32[k][v] = h;
-        } else {
-            S.lut8[k][v] = mp_mul(static_cast<uint64_t>(v), S.rp[7 - k]);
+// The lane's packed words of tile g (four 16-byte loads).
+__device__ __forceinline__ void load_lane2(const PrepParams& P, int32_t g, int lane, uint64_t (&v)[kLaneWords2]) {
+    const StrSel str(P, g >= P.s[1].tile0);
+    const int32_t t = g - str.tile0;
+    const u32x4* src = reinterpret_cast<const u32x4*>(str.w2 + static_cast<int64_t>(t) * kTileWords2 + lane * kLaneWords2);
+#pragma unroll
+    for (int k = 0; k < kLaneWords2 / 2; ++k) {
+        const u32x4 q = src[k];
+        v[2 * k] = static_cast<uint64_t>(q.x) | (static_cast<uint64_t>(q.y) << 32);
+        v[2 * k + 1] = static_cast<uint64_t>(q.z) | (static_cast<uint64_t>(q.w) << 32);
+    }
+}
+
+__device__ __forceinline__ void load_lane8(const PrepParams& P, int32_t g, int lane, uint64_t (&v)[kLaneWords8]) {
+    const StrSel str(P, g >= P.s[1].tile0);
+    const int32_t t = g - str.tile0;
+    const u32x4* src = reinterpret_cast<const u32x4*>(str.w8 + static_cast<int64_t>(t) * kTileWords8 + lane * kLaneWords8);
+#pragma unroll
+    for (int k = 0; k < kLaneWords8 / 2; ++k) {
+        const u32x4 q = src[k];
+        v[2 * k] = static_cast<uint64_t>(q.x) | (static_cast<uint64_t>(q.y) << 32);
+        v[2 * k + 1] = static_cast<uint64_t>(q.z) | (static_cast<uint64_t>(q.w) << 32);
+    }
+}
+
+// Writes T at block end e (e - seg in (0, 256]) with value h: into the
+// wavefront's staging slots when `st` is set (b = 32 .. 128), else directly.
+struct TabPut {
+    uint64_t* tab;
+    uint64_t* st;  // this lane's 9 staging slots, or nullptr
+    int32_t seg, len, log2b, bmask;
+    __device__ __forceinline__ void operator()(int32_t e, uint64_t h) const {
+        if ((e & bmask) == 0 && e <= len) {
+            if (st)
+                st[((e - seg) >> log2b) - 1] = h;
+            else
+                tab[e >> log2b] = h;
         }
     }
-    for (int v = tid; v < 256; v += kPrepThreads) {
-        uint64_t h = 0;
-        for (int j = 0; j < 4; ++j)
-            h = mp_add(h, mp_mul(static_cast<uint64_t>((v >> (2 * j)) & 3), S.rp[3 - j]));
-        S.lut4[v] = h;
-    }
+};
 
-    for (int32_t g = blockIdx.x; g < P.total_tiles; g += gridDim.x) {
-        __syncthreads();  // tables ready; wsum of the previous tile consumed
-        const StrSel str(P, g >= P.s[1].tile0);
-        const int32_t t = g - str.tile0;
-        const int32_t seg_start = t * kTileChars + tid * kSegChars;
-        const int32_t len = str.len;
-        const bool big = !two;
-
-        // the 64 characters of this thread (zero past the string)
-        uint32_t dw[16];
-        uint64_t pk[2];
-        if (two) {
-            const u32x4 v = *reinterpret_cast<const u32x4*>(str.w2 + static_cast<int64_t>(t) * kTileWords2 + tid * 2);
-            pk[0] = static_cast<uint64_t>(v.x) | (static_cast<uint64_t>(v.y) << 32);
-            pk[1] = static_cast<uint64_t>(v.z) | (static_cast<uint64_t>(v.w) << 32);
+// Emission of T over the lane's characters in units of U characters of
+// packed words (U = 4, 8, 16 or 32, U <= b): h enters as the prefix hash at
+// the lane's first character.
+template <int U>
+__device__ __forceinline__ void emit_units2(const TableShared& S, const uint64_t (&v)[kLaneWords2], uint64_t h,
+                                            const TabPut& put) {
+    const uint64_t ru = S.rp[U];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) dw[k] = 0;
-        } else {
-            const u32x4* src = reinterpret_cast<const u32x4*>(str.w8 + static_cast<int64_t>(t) * kTileWords8 + tid * 8);
+    for (int q = 0; q < kLaneWords2; ++q) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const u32x4 v = src[k];
-                dw[4 * k + 0] = v.x;
-                dw[4 * k + 1] = v.y;
-                dw[4 * k + 2] = v.z;
-                dw[4 * k + 3] = v.w;
-            }
-            pk[0] = pk[1] = 0;
-        }
-
-        // ---- segment hash, block-scan within the tile ----
-        const uint64_t hseg = seg_pass<false>(S, dw, pk, big, P.log2b, 0, seg_start, len, nullptr);
-        uint64_t x = hseg;  // inclusive over the wave, Hillis-Steele
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint64_t y = __shfl_up(static_cast<unsigned long long>(x), d);
-            if (lane >= d) x = mp_add(mp_mul(y, S.rseg[d]), x);
-        }
-        if (lane == 63) S.wsum[wave] = x;
-        __syncthreads();
-        if (!EMIT) {
-            if (tid == 0) {
-                uint64_t agg = 0;
-                for (int v = 0; v < kPrepThreads / 64; ++v) agg = mp_add(mp_mul(agg, S.rseg[64]), S.wsum[v]);
-                P.tile_agg[g] = agg;
-            }
-        } else {
-            uint64_t pre = 0;  // hash of the waves before this one
-            for (int v = 0; v < wave; ++v) pre = mp_add(mp_mul(pre, S.rseg[64]), S.wsum[v]);
-            const uint64_t xprev = __shfl_up(static_cast<unsigned long long>(x), 1);
-            const uint64_t excl_thread = lane == 0 ? pre : mp_add(mp_mul(pre, S.rseg[lane]), xprev);
-            // emit T at block ends: prefix at segment start, then the units
-            const uint64_t tp = P.tile_prefix[g];
-            const uint64_t hstart = mp_add(mp_mul(tp, S.rseg[tid]), excl_thread);
-            if (seg_start < len) seg_pass<true>(S, dw, pk, big, P.log2b, hstart, seg_start, len, str.tab);
-            if (t == 0 && tid == 0) str.tab[0] = 0;
+        for (int u = 0; u < 32 / U; ++u) {
+            h = mp_add(mp_mul(h, ru), unit_hash2<U>(S, v[q], u));
+            put(put.seg + q * 32 + (u + 1) * U, h);
         }
     }
 }
 
-// Pass 2: one workgroup per string.  prefix[t] = h(S[0 .. 16384 t)) from the
-// tile hashes by Horner's rule with R = r^16384: each thread folds a run of
-// consecutive tiles, the runs are combined by a scan under
-// (a, na) . (b, nb) = (a R^nb + b, na + nb), and each thread writes the
-// prefixes of its run.
+// SMALLB: instantiation for blocks of at most 4 characters (units of 4
+// characters or single characters); the others use units of 8 to 32.
+template <bool EMIT, bool TWO, bool SMALLB>
+__device__ __forceinline__ void table_tiles(const PrepParams& P, TableShared& S, int32_t gw, int32_t W, int lane,
+                                            int wave) {
+    const int32_t total = P.total_tiles;
+    const int32_t log2b = P.log2b;
+    const int32_t bmask = (1 << log2b) - 1;
+    // b = 32 .. 128: a tile's 16384 / b entries go through LDS, so that every
+    // store instruction writes 64 consecutive entries
+    const bool staged = log2b >= 5 && log2b <= 7;
+    const int32_t lepl = 8 - log2b;  // log2 of the entries per lane when staged
+    constexpr int NW = TWO ? kLaneWords2 : kLaneWords8;
+    uint64_t cur[NW];
+    uint64_t nxt[kLaneWords2];
+    if constexpr (TWO) {
+        if (gw < total) load_lane2(P, gw, lane, cur);
+    }
+    for (int32_t g = gw; g < total; g += W) {
+        if constexpr (TWO) {
+            // the next tile's words are requested before this tile's arithmetic
+            if (g + W < total) load_lane2(P, g + W, lane, nxt);
+        } else {
+            load_lane8(P, g, lane, cur);
+        }
+        const StrSel str(P, g >= P.s[1].tile0);
+        const int32_t t = g - str.tile0;
+        const int32_t seg = t * kTileChars + lane * kLaneChars;
+        const int32_t len = str.len;
+        if constexpr (!EMIT) {
+            uint64_t h = 0;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) {
+                if constexpr (TWO)
+                    h = mp_add(mp_mul(h, S.rp[32]), unit_hash2<32>(S, cur[q], 0));
+                else
+                    h = mp_add(mp_mul(h, S.rp[8]), word_hash8(S, cur[q]));
+            }
+            // I(l) = sum over lanes l' <= l of h(l') r^(256 (63 - l')): a plain
+            // prefix sum; the tile's hash is I(63) and the hash of its
+            // characters before lane l is I(l - 1) r^(-256 (64 - l))
+            uint64_t x = mp_mul(h, S.rseg[4 * (63 - lane)]);
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint64_t y = __shfl_up(static_cast<unsigned long long>(x), d);
+                if (lane >= d) x = mp_add(x, y);
+            }
+            const uint64_t ip = __shfl_up(static_cast<unsigned long long>(x), 1);
+            P.lane_excl[static_cast<int64_t>(g) * 64 + lane] = lane == 0 ? 0 : mp_mul(ip, S.rinv256[64 - lane]);
+            if (lane == 63) P.tile_agg[g] = x;
+        } else {
+            const TabPut put{str.tab, staged ? &S.stage[wave][lane * 9] : nullptr, seg, len, log2b, bmask};
+            if (seg < len || (t == 0 && lane == 0)) {
+                // prefix hash at the lane's first character
+                uint64_t h = mp_add(mp_mul(P.tile_prefix[g], S.rseg[4 * lane]),
+                                    P.lane_excl[static_cast<int64_t>(g) * 64 + lane]);
+                if (t == 0 && lane == 0) str.tab[0] = 0;
+                if constexpr (TWO && !SMALLB) {
+                    if (log2b >= 5)
+                        emit_units2<32>(S, cur, h, put);
+                    else if (log2b == 4)
+                        emit_units2<16>(S, cur, h, put);
+                    else
+                        emit_units2<8>(S, cur, h, put);
+                } else if constexpr (TWO) {
+                    if (log2b == 2) {
+                        emit_units2<4>(S, cur, h, put);
+                    } else {  // b = 1 or 2: single characters
+#pragma unroll
+                        for (int q = 0; q < NW; ++q)
+                            for (int c = 0; c < 32; ++c) {
+                                h = mp_add(mp_mul(h, S.rp[1]), (cur[q] >> (2 * c)) & 3u);
+                                put(seg + 32 * q + c + 1, h);
+                            }
+                    }
+                } else if constexpr (!SMALLB) {  // b >= 8: 8-bit words
+#pragma unroll
+                    for (int q = 0; q < NW; ++q) {
+                        h = mp_add(mp_mul(h, S.rp[8]), word_hash8(S, cur[q]));
+                        put(seg + 8 * (q + 1), h);
+                    }
+                } else {  // b = 1, 2 or 4: single characters
+#pragma unroll
+                    for (int q = 0; q < NW; ++q)
+                        for (int c = 0; c < 8; ++c) {
+                            h = mp_add(mp_mul(h, S.rp[1]), (cur[q] >> (8 * c)) & 0xFFu);
+                            put(seg + 8 * q + c + 1, h);
+                        }
+                }
+            }
+            if (staged) {
+                // entry i (of 64 << lepl) of the tile comes from lane i >> lepl;
+                // T index t * (16384 >> log2b) + 1 + i
+                __builtin_amdgcn_wave_barrier();
+                const int32_t base = t * (kTileChars >> log2b) + 1;
+                const int32_t last = len >> log2b;
+                for (int32_t k = 0; k < (1 << lepl); ++k) {
+                    const int32_t i = k * 64 + lane;
+                    const int32_t j = base + i;
+                    if (j <= last) str.tab[j] = S.stage[wave][(i >> lepl) * 9 + (i & ((1 << lepl) - 1))];
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        if constexpr (TWO) {
+#pragma unroll
+            for (int k = 0; k < kLaneWords2; ++k) cur[k] = nxt[k];
+        }
+    }
+}
+
+template <bool EMIT, bool SMALLB>
+__global__ __launch_bounds__(kPrepThreads) void table_tiles_kernel(PrepParams P, const uint64_t* rtab) {
+    __shared__ TableShared S;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const bool two = *P.alpha <= 3u;
+    const int32_t gw = __builtin_amdgcn_readfirstlane(static_cast<int32_t>(blockIdx.x * (kPrepThreads / 64) + (tid >> 6)));
+    const int32_t W = static_cast<int32_t>(gridDim.x * (kPrepThreads / 64));
+
+    // lookup tables and powers, built on the host (kRtab* layout)
+    if (two) {
+        for (int i = tid; i < 8 * 256; i += kPrepThreads) S.lut32[i >> 8][i & 255] = rtab[kRtabLut32 + i];
+    } else {
+        for (int i = tid; i < 8 * 256; i += kPrepThreads) S.lut8[i >> 8][i & 255] = rtab[kRtabLut8 + i];
+    }
+    for (int i = tid; i < 65; i += kPrepThreads) S.rp[i] = rtab[i];
+    for (int i = tid; i < 257; i += kPrepThreads) S.rseg[i] = rtab[kRtabRseg + i];
+    for (int i = tid; i < 65; i += kPrepThreads) S.rinv256[i] = rtab[kRtabRinv256 + i];
+    __syncthreads();
+    if (two)
+        table_tiles<EMIT, true, SMALLB>(P, S, gw, W, lane, tid >> 6);
+    else
+        table_tiles<EMIT, false, SMALLB>(P, S, gw, W, lane, tid >> 6);
+}
+
+// Pass 2: one workgroup per string.  prefix[u] = h(S[0 .. 16384 u)) from the
+// tile hashes by Horner's rule with R = r^16384, over chunks of 8192 tiles
+// staged in LDS: each thread folds 8 consecutive tiles, the threads' values
+// are combined by inclusive scans under x(l) = x(l - d) R^(8 d) + x(l) within
+// each wavefront and then over the wavefronts (the string's prefix before the
+// chunk enters ahead of the first), and each thread writes the prefixes of
+// its 8 tiles.  The chunk is zero-padded; the padding only follows the last
+// real tile.  The powers of R come from the host.
 __global__ __launch_bounds__(1024) void table_scan_kernel(PrepParams P, const uint64_t* rtab) {
-    __shared__ uint64_t Rp[32];  // R^(2^k)
-    __shared__ uint64_t hs[1024];
-    __shared__ int32_t ns[1024];
-    const int tid = threadIdx.x, nthr = blockDim.x;
+    constexpr int kPer = 8, kChunk = 1024 * kPer;
+    __shared__ uint64_t buf[kChunk];
+    __shared__ uint64_t wpre[16];  // prefix before each wavefront's tiles
+    __shared__ uint64_t wtot[16];
+    __shared__ uint64_t carry_s;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const StrSel str(P, blockIdx.x == 1);
     const int32_t tiles = (blockIdx.x == 1 ? P.total_tiles : P.s[1].tile0) - str.tile0;
-    if (tid == 0) {
-        Rp[0] = rtab[65 + 257 + 1];
-        for (int k = 1; k < 32; ++k) Rp[k] = mp_mul(Rp[k - 1], Rp[k - 1]);
-    }
-    __syncthreads();
-    auto powR = [&](int32_t e) {
-        uint64_t r = 1;
-        for (int k = 0; e; ++k, e >>= 1)
-            if (e & 1) r = mp_mul(r, Rp[k]);
-        return r;
-    };
-    const int32_t blk = (tiles + nthr - 1) / nthr;
-    const int32_t lo = imin32(tiles, tid * blk), hi = imin32(tiles, lo + blk);
-    const uint64_t R = Rp[0];
+    const uint64_t R = rtab[kRtabR + 1];
+    const uint64_t* R8p = rtab + kRtabR8pow2;        // R^(8 * 2^j)
+    const uint64_t Rlane = rtab[kRtabR8lane + lane];  // R^(8 (lane + 1))
     const uint64_t* agg = P.tile_agg + str.tile0;
-    uint64_t h = 0;
-    for (int32_t u = lo; u < hi; ++u) h = mp_add(mp_mul(h, R), agg[u]);
-    int32_t n = hi - lo;
-    // inclusive scan over threads (Hillis-Steele through LDS)
-    for (int d = 1; d < nthr; d <<= 1) {
-        hs[tid] = h;
-        ns[tid] = n;
+    uint64_t* pre = P.tile_prefix + str.tile0;
+    uint64_t carry = 0;
+    for (int32_t c0 = 0; c0 < tiles; c0 += kChunk) {
+        const int32_t cn = imin32(kChunk, tiles - c0);
+        for (int i = tid; i < kChunk; i += 1024) buf[i] = i < cn ? agg[c0 + i] : 0;
         __syncthreads();
-        if (tid >= d) {
-            const uint64_t a = hs[tid - d];
-            const int32_t na = ns[tid - d];
-            h = mp_add(mp_mul(a, powR(n)), h);
-            n += na;
+        uint64_t a[kPer];
+        uint64_t h = 0;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            a[j] = buf[kPer * tid + j];
+            h = mp_add(mp_mul(h, R), a[j]);
+        }
+#pragma unroll
+        for (int d = 1, j = 0; d < 64; d <<= 1, ++j) {
+            const uint64_t y = __shfl_up(static_cast<unsigned long long>(h), d);
+            if (lane >= d) h = mp_add(mp_mul(y, R8p[j]), h);
+        }
+        if (lane == 63) wtot[wave] = h;
+        __syncthreads();
+        if (wave == 0) {
+            // over the 16 wavefronts (512 tiles each), the carry ahead of the first
+            uint64_t x = lane < 16 ? wtot[lane] : 0;
+            if (lane == 0) x = mp_add(mp_mul(carry, R8p[6]), x);
+#pragma unroll
+            for (int d = 1, j = 6; d < 16; d <<= 1, ++j) {
+                const uint64_t y = __shfl_up(static_cast<unsigned long long>(x), d);
+                if (lane >= d) x = mp_add(mp_mul(y, R8p[j]), x);
+            }
+            const uint64_t xp = __shfl_up(static_cast<unsigned long long>(x), 1);
+            if (lane < 16) wpre[lane] = lane == 0 ? carry : xp;
         }
         __syncthreads();
-    }
-    hs[tid] = h;
-    __syncthreads();
-    uint64_t p = tid == 0 ? 0 : hs[tid - 1];
-    uint64_t* pre = P.tile_prefix + str.tile0;
-    for (int32_t u = lo; u < hi; ++u) {
-        pre[u] = p;
-        p = mp_add(mp_mul(p, R), agg[u]);
+        const uint64_t pw = wpre[wave];
+        const uint64_t incl = mp_add(mp_mul(pw, Rlane), h);
+        const uint64_t ex = __shfl_up(static_cast<unsigned long long>(incl), 1);
+        uint64_t p = lane == 0 ? pw : ex;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            buf[kPer * tid + j] = p;
+            p = mp_add(mp_mul(p, R), a[j]);
+        }
+        if (tid == 1023) carry_s = incl;
+        __syncthreads();
+        for (int i = tid; i < cn; i += 1024) pre[c0 + i] = buf[i];
+        carry = carry_s;
+        __syncthreads();
     }
 }
 
 // Second pass for pairs that cannot be packed: 8-bit copy of the chunks the
-// first pass packed instead.  Exits at once when the pair is packable.
+// first pass packed instead.  Exits at once when the pair is packable, or when
+// no chunk was packed.  Each wavefront reads the flags of 64 chunks at a time.
 __global__ __launch_bounds__(kPrepThreads) void copy8_rest_kernel(PrepParams P) {
     const uint32_t alpha = *P.alpha;
-    if (alpha <= 3u || P.force8) return;
+    if (alpha <= 3u || P.force8 || *P.packed_any == 0u) return;
     const int lane = threadIdx.x & 63;
     const int32_t wave = __builtin_amdgcn_readfirstlane(static_cast<int32_t>((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
     const int32_t nwaves = static_cast<int32_t>((gridDim.x * blockDim.x) >> 6);
     const int32_t total = P.total_tiles * kTileChunks;
     const int32_t split = P.s[1].tile0 * kTileChunks;
-    for (int32_t g = wave; g < total; g += nwaves) {
-        if (P.chunk_big[g]) continue;
-        const StrSel str(P, g >= split);
-        const int32_t c = g - str.tile0 * kTileChunks;
-        const int32_t seg_start = c * kChunkChars + lane * kSegChars;
-        uint64_t* dst = str.w8 + static_cast<int64_t>(c) * kChunkWords8 + lane * 8;
-        for (int k = 0; k < 8; ++k) {
-            uint64_t v = 0;
-            for (int j = 0; j < 8; ++j) {
-                const int32_t p = seg_start + 8 * k + j;
-                if (p < str.len) v |= static_cast<uint64_t>(str.raw[p]) << (8 * j);
+    for (int32_t g0 = wave * 64; g0 < total; g0 += nwaves * 64) {
+        uint64_t todo = ballot(g0 + lane < total && !P.chunk_big[g0 + lane]);
+        while (todo) {
+            const int32_t g = g0 + ctz64(todo);
+            todo &= todo - 1;
+            const StrSel str(P, g >= split);
+            const int32_t c = g - str.tile0 * kTileChunks;
+            const int32_t seg_start = c * kChunkChars + lane * kSegChars;
+            uint64_t* dst = str.w8 + static_cast<int64_t>(c) * kChunkWords8 + lane * 8;
+            for (int k = 0; k < 8; ++k) {
+                uint64_t v = 0;
+                for (int j = 0; j < 8; ++j) {
+                    const int32_t p = seg_start + 8 * k + j;
+                    if (p < str.len) v |= static_cast<uint64_t>(str.raw[p]) << (8 * j);
+                }
+                dst[k] = v;
             }
-            dst[k] = v;
         }
     }
 }
@@ -401,13 +503,20 @@ hipError_t launch_pack(const PrepParams& pp, int grid, hipStream_t s) {
 }
 
 hipError_t launch_table(const PrepParams& pp, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(table_tiles_kernel<false>, dim3(grid), dim3(kPrepThreads), 0, s, pp, pp.rtab);
+    // one tile per wavefront at a time
+    const int need = (pp.total_tiles + kPrepThreads / 64 - 1) / (kPrepThreads / 64);
+    if (grid > need) grid = need;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL((table_tiles_kernel<false, false>), dim3(grid), dim3(kPrepThreads), 0, s, pp, pp.rtab);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(table_scan_kernel, dim3(2), dim3(1024), 0, s, pp, pp.rtab);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(table_tiles_kernel<true>, dim3(grid), dim3(kPrepThreads), 0, s, pp, pp.rtab);
+    if (pp.log2b <= 2)
+        hipLaunchKernelGGL((table_tiles_kernel<true, true>), dim3(grid), dim3(kPrepThreads), 0, s, pp, pp.rtab);
+    else
+        hipLaunchKernelGGL((table_tiles_kernel<true, false>), dim3(grid), dim3(kPrepThreads), 0, s, pp, pp.rtab);
     return hipGetLastError();
 }
 

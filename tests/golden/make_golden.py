@@ -9,12 +9,14 @@ Workloads:
   * single pairs, n = 10^8, alphabet {0,1,2,3} uniform, k in {10^2 .. 10^5}, seed 0;
   * single pairs, n = 10^9, Zipf(1.0) over 256 symbols and its period-64
     variant, k in {10^3, 10^5}, seed 0;
+  * the paper's own synthetic shape: n = 10^8 uniform over 256 symbols,
+    k in {10^2 .. 10^5}, seed 0 (the workload of its full-run table);
   * the 4096-pair batch (n log-uniform in [10^3, 10^6], k uniform in
     [0, 0.01 n], alphabet 4), seed 0;
   * the first 40 requests of the serving trace (n log-uniform in [10^2, 10^7],
     alphabet 4 or 20, k uniform in [0, 0.05 n]), seed 0.
 
-Usage: python tests/golden/make_golden.py [--only single|big|batch|serve]
+Usage: python tests/golden/make_golden.py [--only single|big|paper|batch|serve]
 (several minutes on 8 cores; the single pairs at n = 10^9 need ~10 GB of RAM).
 """
 import argparse
@@ -37,6 +39,8 @@ SINGLE = [dict(name="n1e8_sigma4_k%d" % k, n=10 ** 8, k=k, seed=0, kind="uniform
                periodic=False) for k in (100, 1000, 10000, 100000)]
 BIG = [dict(name="n1e9_zipf%s_k%d" % ("_periodic" if p else "", k), n=10 ** 9, k=k, seed=0,
             kind="zipf", sigma=256, periodic=p) for p in (False, True) for k in (1000, 100000)]
+PAPER = [dict(name="n1e8_sigma256_k%d" % k, n=10 ** 8, k=k, seed=0, kind="uniform", sigma=256,
+              periodic=False) for k in (100, 1000, 10000, 100000)]
 BATCH = dict(name="batch4096_seed0", count=4096, seed=0)
 SERVE = dict(name="serve40_seed0", count=40, seed=0)
 
@@ -93,7 +97,7 @@ def serve(spec):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--only", choices=["single", "big", "batch", "serve"])
+    ap.add_argument("--only", choices=["single", "big", "paper", "batch", "serve"])
     args = ap.parse_args()
     oracle.build(force=False)
     data = {}
@@ -105,6 +109,8 @@ def main():
         data["single"] = [single(s) for s in SINGLE]
     if args.only in (None, "big"):
         data["big"] = [single(s) for s in BIG]
+    if args.only in (None, "paper"):
+        data["paper"] = [single(s) for s in PAPER]
     if args.only in (None, "batch"):
         data["batch"] = batch(BATCH)
     if args.only in (None, "serve"):

@@ -28,10 +28,12 @@ def test_golden_file_complete(gold):
     assert {(g["periodic"], g["k"]) for g in gold["big"]} == {
         (False, 1000), (False, 100000), (True, 1000), (True, 100000)}
     assert all(g["n"] == 10 ** 9 and g["kind"] == "zipf" for g in gold["big"])
+    assert [g["k"] for g in gold["paper"]] == [100, 1000, 10000, 100000]
+    assert all(g["n"] == 10 ** 8 and g["sigma"] == 256 and g["kind"] == "uniform" for g in gold["paper"])
     assert len(gold["batch"]["eds"]) == gold["batch"]["count"] == 4096
     assert len(gold["serve"]["eds"]) == gold["serve"]["count"] == 40
     # distance bounds of planted edits: |n - m| <= ED <= k
-    for g in gold["single"] + gold["big"]:
+    for g in gold["single"] + gold["big"] + gold["paper"]:
         assert abs(g["n"] - g["m"]) <= g["ed"] <= g["k_planted"]
 
 
@@ -40,6 +42,13 @@ def test_single_pairs_recomputed(gold, orc, idx):
     g = gold["single"][idx]
     A, B, info = synth.single_pair(g["n"], g["k"], g["seed"], sigma=g["sigma"], kind=g["kind"],
                                    periodic=g["periodic"])
+    assert len(B) == g["m"] and info["k_planted"] == g["k_planted"]
+    assert orc.lv_omp(A, B) == g["ed"]
+
+
+def test_paper_shape_recomputed(gold, orc):
+    g = gold["paper"][0]
+    A, B, info = synth.single_pair(g["n"], g["k"], g["seed"], sigma=g["sigma"], kind=g["kind"])
     assert len(B) == g["m"] and info["k_planted"] == g["k_planted"]
     assert orc.lv_omp(A, B) == g["ed"]
 

@@ -101,6 +101,16 @@ def test_n1e9_zipf_and_periodic(ed, ctxs, name, engine):
         assert 0 < st["collision_bound"] < 1e-3
 
 
+@pytest.mark.parametrize("name,engine", _cases("paper"))
+def test_n1e8_alphabet256(ed, ctxs, name, engine):
+    spec = next(g for g in GOLD["paper"] if g["name"] == name)
+    say("full", name, engine)
+    k, st = run_on_stream(ed, ctxs[engine], spec)
+    assert st["bits_per_char"] == 8
+    assert k == spec["ed"]
+    assert st["rounds"] == spec["ed"]
+
+
 def _gen_pairs(specs):
     def one(s):
         n, k, ps = s

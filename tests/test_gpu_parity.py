@@ -143,6 +143,22 @@ def test_table_bit_exact(ed, make_ctx, orc, b, alpha):
         ed.ed_release(p)
 
 
+@pytest.mark.parametrize("b,sigma", [(32, 4), (4096, 4), (64, 256)])
+def test_table_bit_exact_multi_chunk_scan(ed, make_ctx, orc, b, sigma):
+    # more than 8192 tiles of 16384 characters: the scan of the tile hashes
+    # runs over several chunks and carries the prefix from one to the next
+    n = 8193 * 16384 + 77
+    say("table multi-chunk", b, sigma, n)
+    seed = 77 + b
+    ctx = make_ctx(engine=ed.ENGINE_HASH, block=b, hash_seed=seed)
+    A = synth.random_string(n, synth.CharDist("uniform", sigma), 5)
+    B = synth.random_string(1000, synth.CharDist("uniform", 4), 6)
+    p = ed.ed_prepare(ctx, A, B)
+    TA = ed.ed_pair_buffer(ctx, p, 0, ed.BUF_TABLE)
+    ed.ed_release(p)
+    np.testing.assert_array_equal(TA, orc.horner_table(A, b, orc.hash_base(seed)))
+
+
 # ---------------------------------------------------------------------------
 # LCP engines against the character loop (section 2)
 # ---------------------------------------------------------------------------
