@@ -192,6 +192,44 @@ def table_leg(ed, n=10 ** 9, k=1000, reps=3):
             "prepare_frac_of_hbm_peak": round(pbytes / best[1] / PEAK_HBM_GBS, 4)}
 
 
+def engine_matrix(ed, dev, ks, want, stream, reps=3):
+    """The single pairs on the other engine configurations: the direct engine
+    at 8 bits per character, the hash engine with b = 1, and the hash engine's
+    block size swept over b = 1 .. 64 at k = 1e5.  Kernel times (HIP events),
+    median of `reps` runs; every distance must equal the main run's."""
+    def run(ctx, i):
+        tA, tB = dev[i]
+        best = []
+        for _ in range(reps):
+            k, st = run_pair(ed, ctx, tA, tB, stream)
+            if k != want[i]:
+                raise SystemExit("engine matrix: distance %d != %d at k=%d" % (k, want[i], ks[i]))
+            best.append((st["gpu_ns_prepare_kernel"] + st["gpu_ns_frontier_kernel"], st))
+        best.sort(key=lambda x: x[0])
+        st = best[len(best) // 2][1]
+        return {"prepare_kernel_ms": round(st["gpu_ns_prepare_kernel"] / 1e6, 4),
+                "table_kernel_ms": round(st["gpu_ns_table_kernel"] / 1e6, 4),
+                "frontier_kernel_ms": round(st["gpu_ns_frontier_kernel"] / 1e6, 4),
+                "bits_per_char": st["bits_per_char"]}
+
+    out = {}
+    log("engine matrix: direct 8-bit, hash b=1")
+    for name, kw in (("direct_8bit", dict(engine=ed.ENGINE_DIRECT, pack_bits=8)),
+                     ("hash_b1", dict(engine=ed.ENGINE_HASH, block=1))):
+        ctx = ed.ed_init(0, flags=ed.FLAG_TIMING, **kw)
+        out[name] = {str(k): run(ctx, i) for i, k in enumerate(ks)}
+        ed.ed_shutdown(ctx)
+    log("engine matrix: hash block sweep at k=1e5")
+    i = ks.index(100000)
+    sweep = {}
+    for b in (1, 2, 4, 8, 16, 32, 64):
+        ctx = ed.ed_init(0, engine=ed.ENGINE_HASH, block=b, flags=ed.FLAG_TIMING)
+        sweep[str(b)] = run(ctx, i)
+        ed.ed_shutdown(ctx)
+    out["hash_block_sweep_k1e5"] = sweep
+    return out
+
+
 def serve_leg(ed, ctx, count, seed=0, warmup=0):
     """Served workload: Poisson arrivals, n = floor(10^U), U ~ U[2, 7], alphabet 4
     or 20, k ~ U{0..floor(0.05 n)}.  The arrival rate is 0.7x the batched
@@ -284,7 +322,7 @@ def run_pair(ed, ctx, tA, tB, stream):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--engine", choices=["direct", "hash"], default="direct")
     ap.add_argument("--ks", type=str, default=",".join(str(k) for k in KS))
@@ -294,6 +332,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 4096-pair batch leg")
     ap.add_argument("--no-lcp", action="store_true", help="skip the long-LCP bandwidth leg")
     ap.add_argument("--no-table", action="store_true", help="skip the 8-bit table-build leg")
+    ap.add_argument("--no-matrix", action="store_true",
+                    help="skip the engine matrix (direct 8-bit, hash b=1, hash block sweep)")
     ap.add_argument("--serve", type=int, default=40, metavar="N",
                     help="requests of the serving leg (0 skips it)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -344,14 +384,19 @@ def main():
         log("warmup", w)
         step(main_engine)
 
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    # K timed steps, each bracketed by synchronisations; the value is taken
+    # from the median step (the mean is reported beside it)
     results = []
+    times = []
     for s in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         results.append(step(main_engine))
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
         log("step", s, "done")
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
+    dt = sorted(times)[len(times) // 2]
+    dt_mean = sum(times) / len(times)
     value = n * len(ks) / dt
 
     # per-k summary from the last step
@@ -455,6 +500,10 @@ def main():
         prepare_roofline.append(prep_roofline(oname, [st["gpu_ns_prepare_kernel"] / 1e6 for _, st in r],
                                               [st["gpu_ns_table_kernel"] / 1e6 for _, st in r]))
 
+    matrix = None
+    if not args.no_matrix and n == N and 100000 in ks:
+        matrix = engine_matrix(ed, dev, ks, [r[0] for r in last], stream)
+
     batch = None
     if not args.no_batch:
         batch = batch_leg(ed, ctxs["direct"])
@@ -490,7 +539,8 @@ def main():
     line = {
         "metric": "chars/sec at n=1e8, k=1e2..1e5 (exact); batched pairs/sec + p50/p99 latency",
         "value": value, "unit": "chars/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "ms_per_step": dt * 1e3, "ms_per_step_mean": dt_mean * 1e3, "timing": "median of the timed steps",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u8", "data": "synthetic",
         "config": {"workload": "single pairs n=1e8, alphabet {0,1,2,3} uniform, B = A + k planted "
                                "uniform edits, k in %s, seed 0, one launch per pair" % ks,
@@ -502,6 +552,7 @@ def main():
         "cpu_baseline": cpu,
         "paper_context": paper_context(ks, n),
         "other_engine": other,
+        "engine_matrix": matrix,
         "batch": batch,
         "lcp_extension": lcp,
         "table_build_8bit": table,
