@@ -230,6 +230,35 @@ def engine_matrix(ed, dev, ks, want, stream, reps=3):
     return out
 
 
+def align_leg(ed, dev, ks, want, stream, only=(1000, 10000, 100000)):
+    """Checked (certified) hash-engine results: ed_align on the single pairs
+    (hash engine, b = 32): k, the edit script traced back through every
+    round's frontier row kept in device memory ((k+1)^2 * 4 bytes), and every
+    run of matches re-compared; wall time against the plain ed_distance."""
+    ctx = ed.ed_init(0, engine=ed.ENGINE_HASH)
+    out = {}
+    for i, k in enumerate(ks):
+        if k not in only:
+            continue
+        tA, tB = dev[i]
+        log("align leg: k=%d" % k)
+        p = ed.ed_prepare(ctx, tA, tB, stream=stream)
+        t0 = time.perf_counter()
+        kd = ed.ed_distance(ctx, p, stream=stream)
+        td = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        ka, script = ed.ed_align(ctx, p, stream=stream)
+        ta = time.perf_counter() - t0
+        ed.ed_release(p)
+        edits = sum(L for op, L in script if op != ed.OP_MATCH)
+        if not (kd == ka == want[i] == edits):
+            raise SystemExit("align leg: k=%d distance %d align %d edits %d want %d" % (k, kd, ka, edits, want[i]))
+        out[str(k)] = {"ed": ka, "script_runs": len(script), "distance_ms": round(td * 1e3, 3),
+                       "align_ms": round(ta * 1e3, 3), "rows_bytes": (ka + 1) ** 2 * 4, "checked": True}
+    ed.ed_shutdown(ctx)
+    return out
+
+
 def serve_leg(ed, ctx, count, seed=0, warmup=0):
     """Served workload: Poisson arrivals, n = floor(10^U), U ~ U[2, 7], alphabet 4
     or 20, k ~ U{0..floor(0.05 n)}.  The arrival rate is 0.7x the batched
@@ -332,6 +361,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 4096-pair batch leg")
     ap.add_argument("--no-lcp", action="store_true", help="skip the long-LCP bandwidth leg")
     ap.add_argument("--no-table", action="store_true", help="skip the 8-bit table-build leg")
+    ap.add_argument("--no-align", action="store_true", help="skip the checked alignment leg")
     ap.add_argument("--no-matrix", action="store_true",
                     help="skip the engine matrix (direct 8-bit, hash b=1, hash block sweep)")
     ap.add_argument("--serve", type=int, default=40, metavar="N",
@@ -504,6 +534,10 @@ def main():
     if not args.no_matrix and n == N and 100000 in ks:
         matrix = engine_matrix(ed, dev, ks, [r[0] for r in last], stream)
 
+    align = None
+    if not args.no_align and n == N:
+        align = align_leg(ed, dev, ks, [r[0] for r in last], stream)
+
     batch = None
     if not args.no_batch:
         batch = batch_leg(ed, ctxs["direct"])
@@ -553,6 +587,7 @@ def main():
         "paper_context": paper_context(ks, n),
         "other_engine": other,
         "engine_matrix": matrix,
+        "align_checked": align,
         "batch": batch,
         "lcp_extension": lcp,
         "table_build_8bit": table,

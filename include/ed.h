@@ -44,7 +44,8 @@ extern "C" {
                               a character > 3 with pack_bits = 2, bad option value */
 #define ED_ENOMEM (-2)     /* device or host allocation failed */
 #define ED_EDEVICE (-3)    /* a HIP call failed; ed_last_error() has the detail */
-#define ED_ECOLLISION (-4) /* reserved for a certified hash mode */
+#define ED_ECOLLISION (-4) /* ed_align: a run of matches on the hash engine's traced path does not
+                              match (a hash collision); the direct engine gives the exact answer */
 #define ED_EBUSY (-5)      /* serving: host queue full */
 #define ED_EINTERNAL (-6)  /* an internal consistency check failed (a bug) */
 
@@ -58,6 +59,8 @@ extern "C" {
 #define ED_FLAG_NO_PHASE_A 2u  /* run every round grid-wide (skip the one-workgroup phase) */
 #define ED_FLAG_SHUFFLE 4u     /* batch: permute the work order with hash_seed (race test) */
 #define ED_FLAG_TIMING 8u      /* time the prepare and frontier kernels with HIP events */
+#define ED_FLAG_CERTIFY 16u    /* ed_distance, hash engine, no k_max: check the result as ed_align
+                                * does, and answer with the direct engine if the check fails */
 
 typedef struct ed_options {
     uint32_t engine;    /* ED_ENGINE_DIRECT or ED_ENGINE_HASH */
@@ -138,6 +141,36 @@ int ed_distance(ed_ctx *ctx, ed_pair *pair, int64_t k_max, uint64_t *k_out, void
 int ed_distance_dump(ed_ctx *ctx, ed_pair *pair, int64_t k_max, uint64_t *k_out, int32_t *rows,
                      uint64_t rows_cap, void *hip_stream);
 
+/* ---- alignment ---------------------------------------------------------------- */
+/* One run of an edit script: `len` consecutive operations of one kind. */
+typedef struct ed_op_run {
+    uint32_t op; /* ED_OP_* */
+    uint32_t pad;
+    uint64_t len;
+} ed_op_run;
+#define ED_OP_MATCH 0u /* A[x] == B[y]; x and y advance */
+#define ED_OP_SUB 1u   /* A[x] replaced by B[y]; x and y advance */
+#define ED_OP_DEL 2u   /* A[x] deleted; x advances */
+#define ED_OP_INS 3u   /* B[y] inserted; y advances */
+
+/* Edit distance and an optimal edit script, checked.  The frontier rounds of
+ * Algorithm 1 (section 3.1) are run twice: once for k, once keeping every
+ * round's row in device memory ((k+1)^2 * 4 bytes, allocated and freed by the
+ * call); from the row of round k at diagonal n - m the path is traced back on
+ * the device (each round's start comes from one of the three neighbours of the
+ * previous round, which names the edit), and every run of matches on it is
+ * compared character by character on the device.  The script applied to A
+ * gives B and has k edits.  With the hash engine this check makes the result
+ * exact: a collision can only make an LCP too long (k too small), and a valid
+ * script of k edits shows ED <= k.  runs: caller memory for `runs_cap`
+ * entries (2k + 1 always suffice); *n_runs receives the count.  Errors:
+ * ED_EINVAL (also when runs_cap is too small; *n_runs then holds the count
+ * needed), ED_ENOMEM (the rows do not fit), ED_ECOLLISION (hash engine: a run
+ * does not match; *k_out holds the unchecked k), ED_EINTERNAL (the traced path
+ * is not a valid script: a bug), ED_EDEVICE. */
+int ed_align(ed_ctx *ctx, ed_pair *pair, uint64_t *k_out, ed_op_run *runs, uint64_t runs_cap, uint64_t *n_runs,
+             void *hip_stream);
+
 /* ---- batch ---------------------------------------------------------------- */
 /*
  * Edit distances of `count` prepared pairs in one persistent launch: the
@@ -178,6 +211,9 @@ typedef struct ed_stats {
     /* with ED_FLAG_TIMING, hash engine: HIP-event time of the prefix-table
      * kernels alone (part of gpu_ns_prepare_kernel; 0 for the direct engine) */
     double gpu_ns_table_kernel;
+    /* ED_FLAG_CERTIFY: hash-engine distances whose check failed (then answered
+     * by the direct engine) */
+    uint64_t certify_retries;
 } ed_stats;
 
 int ed_pair_stats(const ed_pair *pair, ed_stats *out);
@@ -218,12 +254,19 @@ int ed_pair_buffer(ed_ctx *ctx, const ed_pair *pair, int which, int kind, void *
  * direct engine's lane and wave tiers, one wavefront per query; 1 = the hash
  * engine (needs tables), one wavefront per query; 2 = the direct engine's
  * workgroup tier, one workgroup per query; 3 = the direct engine's grid tier,
- * every workgroup of the device on one query at a time (segments taken in
- * order from a ticket, first mismatch by a shared minimum), timed with
+ * every wavefront of the device on one query at a time (static segments taken
+ * in increasing order, first mismatch by a shared minimum), timed with
  * ED_FLAG_TIMING into ed_stats.gpu_ns_lcp_kernel.  The same device code as
  * the frontier kernels. */
 int ed_debug_lcp(ed_ctx *ctx, ed_pair *pair, int engine, const int64_t *x, const int64_t *y,
                  uint64_t count, int64_t *out, void *hip_stream);
+
+/* The check behind ed_align on runs given by the caller: compares A[x[i] ..
+ * x[i] + len[i]) with B[y[i] .. y[i] + len[i]) for i < count on the device and
+ * sets *bad to 1 if any character differs, else 0 (runs inside the strings,
+ * else ED_EINVAL). */
+int ed_debug_check_runs(ed_ctx *ctx, ed_pair *pair, const int32_t *x, const int32_t *y, const int32_t *len,
+                        uint64_t count, uint32_t *bad, void *hip_stream);
 
 /* ---- serving ---------------------------------------------------------------- */
 typedef struct ed_server ed_server;

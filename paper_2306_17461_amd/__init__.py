@@ -34,6 +34,8 @@ FLAG_DEBUG_DUMP = 1
 FLAG_NO_PHASE_A = 2
 FLAG_SHUFFLE = 4
 FLAG_TIMING = 8
+FLAG_CERTIFY = 16
+OP_MATCH, OP_SUB, OP_DEL, OP_INS = 0, 1, 2, 3
 BUF_PACKED2 = 0
 BUF_BYTES = 1
 BUF_TABLE = 2
@@ -75,7 +77,12 @@ class ed_stats(ctypes.Structure):
                 ("gpu_ns_frontier_kernel", ctypes.c_double),
                 ("rounds_phase_a", ctypes.c_uint64), ("us_phase_a", ctypes.c_double),
                 ("us_phase_b", ctypes.c_double), ("gpu_ns_lcp_kernel", ctypes.c_double),
-                ("wg_lcps", ctypes.c_uint64), ("gpu_ns_table_kernel", ctypes.c_double)]
+                ("wg_lcps", ctypes.c_uint64), ("gpu_ns_table_kernel", ctypes.c_double),
+                ("certify_retries", ctypes.c_uint64)]
+
+
+class ed_op_run(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_uint32), ("pad", ctypes.c_uint32), ("len", ctypes.c_uint64)]
 
 
 class ed_result(ctypes.Structure):
@@ -87,8 +94,9 @@ class ed_result(ctypes.Structure):
 # every symbol declared in include/ed.h
 EXPORTS = [
     "ed_default_options", "ed_hash_base", "ed_init", "ed_set_options", "ed_get_options",
-    "ed_shutdown", "ed_prepare", "ed_release", "ed_distance", "ed_distance_dump", "ed_batch",
-    "ed_autotune_batch", "ed_pair_stats", "ed_pair_buffer", "ed_debug_lcp", "ed_serve_open",
+    "ed_shutdown", "ed_prepare", "ed_release", "ed_distance", "ed_distance_dump", "ed_align", "ed_batch",
+    "ed_autotune_batch", "ed_pair_stats", "ed_pair_buffer", "ed_debug_lcp", "ed_debug_check_runs",
+    "ed_serve_open",
     "ed_serve_submit",
     "ed_serve_poll", "ed_serve_drain", "ed_serve_close", "ed_strerror", "ed_last_error",
 ]
@@ -115,11 +123,13 @@ def _load():
         "ed_release": (i32, [vp]),
         "ed_distance": (i32, [vp, vp, i64, P(u64), vp]),
         "ed_distance_dump": (i32, [vp, vp, i64, P(u64), vp, u64, vp]),
+        "ed_align": (i32, [vp, vp, P(u64), P(ed_op_run), u64, P(u64), vp]),
         "ed_batch": (i32, [vp, P(vp), u64, i64, P(u64), P(ctypes.c_int32), vp]),
         "ed_autotune_batch": (i32, [vp, P(vp), u64, i64, ctypes.c_uint32, P(ed_tune_result), vp]),
         "ed_pair_stats": (i32, [vp, P(ed_stats)]),
         "ed_pair_buffer": (i32, [vp, vp, i32, i32, vp, u64, P(u64)]),
         "ed_debug_lcp": (i32, [vp, vp, i32, vp, vp, u64, vp, vp]),
+        "ed_debug_check_runs": (i32, [vp, vp, vp, vp, vp, u64, P(ctypes.c_uint32), vp]),
         "ed_serve_open": (i32, [vp, u64, ctypes.c_uint32, P(vp)]),
         "ed_serve_submit": (i32, [vp, vp, u64, vp, u64, u64]),
         "ed_serve_poll": (i32, [vp, P(ed_result), ctypes.c_uint32, P(ctypes.c_uint32)]),
@@ -248,6 +258,33 @@ def ed_distance_dump(ctx, pair, rows_cap, k_max=-1, stream=None):
                                 _stream_handle(stream)), "ed_distance_dump")
     k = int(k.value)
     return k, rows[: (k + 1) ** 2].copy()
+
+
+def ed_align(ctx, pair, stream=None):
+    """(k, script): the edit distance and an optimal edit script, every run of
+    matches checked on the device; script = [(op, length), ...] with op one of
+    OP_MATCH, OP_SUB, OP_DEL, OP_INS."""
+    k = ctypes.c_uint64()
+    cnt = ctypes.c_uint64()
+    cap = 4096
+    while True:
+        runs = (ed_op_run * cap)()
+        rc = lib.ed_align(ctx, pair, ctypes.byref(k), runs, cap, ctypes.byref(cnt), _stream_handle(stream))
+        if rc == ED_EINVAL and cnt.value > cap:
+            cap = int(cnt.value)
+            continue
+        _check(rc, "ed_align")
+        return int(k.value), [(int(runs[i].op), int(runs[i].len)) for i in range(cnt.value)]
+
+
+def ed_debug_check_runs(ctx, pair, runs, stream=None):
+    """runs = [(x, y, length), ...]: 1 if some A[x + j] != B[y + j], else 0."""
+    r = np.asarray(runs, dtype=np.int32).reshape(-1, 3)
+    x, y, ln = (np.ascontiguousarray(r[:, j]) for j in range(3))
+    bad = ctypes.c_uint32()
+    _check(lib.ed_debug_check_runs(ctx, pair, x.ctypes.data, y.ctypes.data, ln.ctypes.data, len(r),
+                                   ctypes.byref(bad), _stream_handle(stream)), "ed_debug_check_runs")
+    return int(bad.value)
 
 
 def ed_batch(ctx, pairs, k_max=-1, stream=None, check=True):

@@ -1,0 +1,111 @@
+// Alignment output and its check (the certificate for the hash engine).
+//
+// The frontier rows f_t of every round (the per-round dump of the frontier
+// kernel) determine an optimal alignment: at round t the path's diagonal i
+// holds f_t[i] = slide(c) with c the clamped maximum of f_{t-1}[i] + 1,
+// f_{t-1}[i-1] + 1 and f_{t-1}[i+1] (Algorithm 1, section 3.1); the candidate
+// that produced c names the edit and the diagonal of round t - 1.  Walking
+// from (t = k, i = n - m) back to round 0 gives k + 1 runs of matches joined
+// by single edits.  Re-comparing every run's characters directly turns a
+// hash-engine distance into a checked one: a collision can only make an LCP
+// too long (so k too small), and a path of cost <= k whose runs all match
+// shows that the edit distance is at most k (section 3.3 notes that the
+// hash-based method is Monte Carlo; this check removes the error).
+#include "device.h"
+
+namespace ed {
+
+namespace {
+__device__ __forceinline__ int32_t amax(int32_t a, int32_t b) { return a > b ? a : b; }
+__device__ __forceinline__ int32_t amin(int32_t a, int32_t b) { return a < b ? a : b; }
+}  // namespace
+
+// One lane walks the path: each step reads three entries of the previous row.
+__global__ void traceback_kernel(const int32_t* dump, int32_t k, int32_t n, int32_t m, PathStep* out,
+                                 int32_t* status) {
+    if (threadIdx.x != 0) return;
+    int32_t i = n - m;
+    int32_t f = dump[static_cast<int64_t>(k) * k + k + i];
+    int32_t st = 0;
+    for (int32_t t = k; t >= 0; --t) {
+        PathStep s;
+        s.i = i;
+        s.f = f;
+        if (t == 0) {
+            s.c = 0;
+            s.kind = kStepStart;
+            if (i != 0) st = 1;
+            out[0] = s;
+            break;
+        }
+        const int64_t base = static_cast<int64_t>(t - 1) * (t - 1) + (t - 1);  // diagonal j at base + j
+        const int32_t fa = (i >= -(t - 1) && i <= t - 1) ? dump[base + i] : kNone;
+        const int32_t fb = (i - 1 >= -(t - 1) && i - 1 <= t - 1) ? dump[base + i - 1] : kNone;
+        const int32_t fe = (i + 1 >= -(t - 1) && i + 1 <= t - 1) ? dump[base + i + 1] : kNone;
+        int32_t C = amax(amax(fa + 1, fb + 1), fe);  // kNone + 1 stays negative
+        C = amin(amin(C, n), m + i);
+        int32_t kind, j, fj;
+        if (fa >= 0 && fa + 1 == C) {
+            kind = kStepSub, j = i, fj = fa;
+        } else if (fb >= 0 && fb + 1 == C) {
+            kind = kStepDel, j = i - 1, fj = fb;
+        } else if (fe >= 0 && fe == C) {
+            kind = kStepIns, j = i + 1, fj = fe;
+        } else if (fa >= 0 && fa == C) {
+            kind = kStepNone, j = i, fj = fa;
+        } else {
+            s.c = C;
+            s.kind = kStepFail;
+            out[t] = s;
+            st = 2;
+            break;
+        }
+        s.c = C;
+        s.kind = kind;
+        out[t] = s;
+        i = j;
+        f = fj;
+    }
+    *status = st;
+}
+
+// Each wavefront takes segments w, w + W, ...; lane l compares words l,
+// l + 64, ... of its segment (characters from any offset, the last word
+// masked to the segment's end).
+__global__ __launch_bounds__(256) void verify_kernel(PairDev p, const VerifySeg* segs, int64_t count, uint32_t* bad) {
+    SView A, B;
+    pair_views(p, *p.alpha, A, B);
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+    const int32_t cpw = 1 << A.lcpw;
+    uint64_t diff = 0;
+    for (int64_t sidx = wave; sidx < count; sidx += nwaves) {
+        const VerifySeg sg = segs[sidx];
+        for (int32_t o = lane * cpw; o < sg.len; o += 64 * cpw) {
+            uint64_t d = fetch(A, sg.x + o) ^ fetch(B, sg.y + o);
+            const int32_t rest = sg.len - o;
+            if (rest < cpw) d &= (1ull << (rest << A.lbpc)) - 1;
+            diff |= d;
+        }
+    }
+    if (ballot(diff != 0) && lane == 0) atomicOr(bad, 1u);
+}
+
+hipError_t launch_traceback(const int32_t* dump, int32_t k, int32_t n, int32_t m, PathStep* out, int32_t* status,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(traceback_kernel, dim3(1), dim3(64), 0, s, dump, k, n, m, out, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_verify(const PairDev& p, const VerifySeg* segs, int64_t count, uint32_t* bad, int grid,
+                         hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const int64_t need = (count + 3) / 4;  // four wavefronts per workgroup
+    if (grid > need) grid = static_cast<int>(need);
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(verify_kernel, dim3(grid), dim3(256), 0, s, p, segs, count, bad);
+    return hipGetLastError();
+}
+
+}  // namespace ed

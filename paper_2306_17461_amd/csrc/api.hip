@@ -521,7 +521,7 @@ static int frontier_grid(const ed_ctx* c) {
 }
 
 int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, int32_t* rows,
-                        uint64_t rows_cap, hipStream_t s) {
+                        uint64_t rows_cap, hipStream_t s, int32_t* dev_dump, uint64_t dev_cap) {
     if (p->engine == ED_ENGINE_HASH && (!p->tab[0] || !p->tab[1])) {
         set_error("ed_distance: pair has no prefix tables");
         return ED_EINVAL;
@@ -544,6 +544,9 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
         dump_buf = c->pool.get(std::max<uint64_t>(rows_cap, 1) * 4);
         if (!dump_buf) return ED_ENOMEM;
         d_dump = static_cast<int32_t*>(dump_buf);
+    } else if (dev_dump) {
+        d_dump = dev_dump;
+        rows_cap = dev_cap;
     }
     auto alloc_rows = [&](int64_t Kn, void** a, void** b) -> bool {
         *a = c->pool.get(static_cast<size_t>(2 * Kn + 5) * 4);
@@ -700,7 +703,22 @@ int ed_distance(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, void* hip
     std::lock_guard<std::mutex> lk(c->mu);
     HIP_TRY(hipSetDevice(c->device));
     const auto t0 = std::chrono::steady_clock::now();
-    int rc = distance_locked(c, p, k_max, k_out, nullptr, 0, static_cast<hipStream_t>(hip_stream));
+    const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    int rc;
+    if ((c->opt.flags & ED_FLAG_CERTIFY) && p->engine == ED_ENGINE_HASH && k_max < 0) {
+        // the hash result with its traced path checked directly; a failed check
+        // (a collision) is answered by the direct engine on the same pair
+        std::vector<PathStep> path;
+        rc = align_locked(c, p, k_out, path, s);
+        if (rc == ED_ECOLLISION) {
+            ++p->certify_retries;
+            p->engine = ED_ENGINE_DIRECT;
+            rc = distance_locked(c, p, -1, k_out, nullptr, 0, s);
+            p->engine = ED_ENGINE_HASH;
+        }
+    } else {
+        rc = distance_locked(c, p, k_max, k_out, nullptr, 0, s);
+    }
     p->ns_distance = std::chrono::duration<double, std::nano>(std::chrono::steady_clock::now() - t0).count();
     return rc;
 }
@@ -742,6 +760,7 @@ int ed_pair_stats(const ed_pair* p, ed_stats* o) {
     // probability <= (L-1)/P over a uniform base
     o->collision_bound = static_cast<double>(p->counters.hash_eq_len) / static_cast<double>(kP);
     o->launches = static_cast<uint64_t>(p->launches_distance);
+    o->certify_retries = p->certify_retries;
     o->ns_prepare = p->ns_prepare;
     o->ns_distance = p->ns_distance;
     o->gpu_ns_frontier_kernel = p->gpu_ns_frontier;

@@ -79,6 +79,7 @@ struct ed_pair {
     bool prep_timed = false;
     double gpu_ns_frontier = 0;
     double gpu_ns_lcp = 0;  // last ed_debug_lcp with the grid tier (ED_FLAG_TIMING)
+    uint64_t certify_retries = 0;  // ED_FLAG_CERTIFY: hash results whose check failed
     uint64_t rounds_phase_a = 0;
     double us_phase_a = 0, us_phase_b = 0;
 };
@@ -91,8 +92,12 @@ PairDev pair_dev(const ed_pair* p);
 HashDev ctx_hash(const ed_ctx* c);
 int prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B, uint64_t m,
                    int on_device, hipStream_t s, ed_pair** out);
+// rows: host copy of every round's frontier row (ed_distance_dump); dev_dump:
+// the same rows kept in device memory (dev_cap entries), for the traceback
 int distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, int32_t* rows,
-                    uint64_t rows_cap, hipStream_t s);
+                    uint64_t rows_cap, hipStream_t s, int32_t* dev_dump = nullptr, uint64_t dev_cap = 0);
+// k, an optimal path (k + 1 steps) and the direct check of its runs of matches
+int align_locked(ed_ctx* c, ed_pair* p, uint64_t* k_out, std::vector<PathStep>& path, hipStream_t s);
 int tasks_run(ed_ctx* c, std::vector<TaskPair>& st, const std::vector<long long>& first, int64_t k_max,
               uint32_t engine, hipStream_t s);
 long long task_solo(int32_t pi);

@@ -214,7 +214,33 @@ hipError_t launch_pack(const PrepParams& pp, int grid, hipStream_t s);
 hipError_t launch_table(const PrepParams& pp, int grid, hipStream_t s);
 hipError_t launch_copy8_rest(const PrepParams& pp, int grid, hipStream_t s);
 // cnt: kMaxGrid + 1 counter slots (one per workgroup, then their sum)
+// One step of a traced path: at round t the path is on diagonal i, its run of
+// matches is [c, f) (x = characters of A consumed), and (c, c - i) follows from
+// the path's point at round t - 1 by `kind`.
+enum StepKind : int32_t {
+    kStepStart = 0,  // t = 0: (0, 0)
+    kStepSub = 1,    // from (f', f' - i) on diagonal i: both advance
+    kStepDel = 2,    // from diagonal i - 1: x advances (A character deleted)
+    kStepIns = 3,    // from diagonal i + 1: y advances (B character inserted)
+    kStepNone = 4,   // the same point (the diagonal's end was reached before)
+    kStepFail = 5,   // no candidate produced the start (not expected)
+};
+struct PathStep {
+    int32_t i, c, f, kind;
+};
+// A run of matches to re-check: A[x .. x + len) against B[y .. y + len).
+struct VerifySeg {
+    int32_t x, y, len, pad;
+};
+
 hipError_t launch_ctl_init(FrontierCtl* ctl, CountersDev* cnt, unsigned int* bar, hipStream_t s);
+// Path of an optimal alignment from the per-round frontier rows (row t at
+// dump[t^2], diagonal i at dump[t^2 + t + i]); status 0 ok, 1 bad start, 2 no candidate.
+hipError_t launch_traceback(const int32_t* dump, int32_t k, int32_t n, int32_t m, PathStep* out, int32_t* status,
+                            hipStream_t s);
+// Sets *bad (nonzero) when some segment's characters differ.
+hipError_t launch_verify(const PairDev& p, const VerifySeg* segs, int64_t count, uint32_t* bad, int grid,
+                         hipStream_t s);
 hipError_t launch_counters_sum(CountersDev* cnt, hipStream_t s);
 hipError_t launch_frontier(const FrontierParams& fp, int grid, hipStream_t s);
 hipError_t frontier_max_grid(int device, int* grid_out);

@@ -1,0 +1,172 @@
+"""Alignment output and the checked (certified) hash-engine distance.
+
+`ed_align` returns k and an edit script traced back through the frontier rows
+(Algorithm 1, section 3.1); every run of matches on it is re-compared on the
+device.  The script is checked here independently: applied to A it must give
+B, its number of edits must equal the oracle's distance, every substitution
+must replace a character by a different one and every match must match.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ed():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2306_17461_amd as edmod
+    return edmod
+
+
+@pytest.fixture(scope="module")
+def make_ctx(ed):
+    made = []
+
+    def make(**kw):
+        c = ed.ed_init(0, **kw)
+        made.append(c)
+        return c
+
+    yield make
+    for c in made:
+        ed.ed_shutdown(c)
+
+
+def apply_script(ed, A, B, script):
+    """Number of edits of the script; asserts that it turns A into B."""
+    x = y = edits = 0
+    for op, L in script:
+        assert L > 0
+        if op == ed.OP_MATCH:
+            assert np.array_equal(A[x:x + L], B[y:y + L]), "match run at x=%d" % x
+            x += L
+            y += L
+        elif op == ed.OP_SUB:
+            assert np.all(A[x:x + L] != B[y:y + L]), "substitution of equal characters at x=%d" % x
+            x += L
+            y += L
+            edits += L
+        elif op == ed.OP_DEL:
+            x += L
+            edits += L
+        elif op == ed.OP_INS:
+            y += L
+            edits += L
+        else:
+            raise AssertionError("unknown op %d" % op)
+    assert x == len(A) and y == len(B)
+    return edits
+
+
+def _cases():
+    d4 = synth.CharDist("uniform", 4)
+    d256 = synth.CharDist("uniform", 256)
+    A, B, _ = synth.single_pair(20000, 150, 3)
+    yield "sigma4_planted", A, B
+    A, B, _ = synth.single_pair(30000, 50, 4, sigma=256)
+    yield "sigma256_planted", A, B
+    yield "unrelated_unequal", synth.random_string(3000, d4, 5), synth.random_string(2500, d4, 6)
+    P = synth.periodic_string(40000, d4, 7, period=64)
+    Q, _ = synth.plant_edits(P, 40, d4, 8)
+    yield "periodic", P, Q
+    yield "identical", synth.random_string(5000, d256, 9), None
+    A = synth.random_string(4097, d4, 10)
+    B = A.copy()
+    B[4096] ^= 1
+    yield "last_char", A, B
+    yield "empty_a", np.zeros(0, np.uint8), synth.random_string(37, d4, 11)
+    yield "empty_b", synth.random_string(41, d256, 12), np.zeros(0, np.uint8)
+    yield "both_empty", np.zeros(0, np.uint8), np.zeros(0, np.uint8)
+    yield "one_char", np.array([2], np.uint8), np.array([3], np.uint8)
+
+
+CASES = list(_cases())
+
+
+@pytest.mark.parametrize("engine", [0, 1])
+@pytest.mark.parametrize("pack_bits", [0, 8])
+@pytest.mark.parametrize("name", [c[0] for c in CASES])
+def test_align_script_is_optimal(ed, make_ctx, orc, engine, pack_bits, name):
+    A, B = next((a, b) for n, a, b in CASES if n == name)
+    if B is None:
+        B = A.copy()
+    say("align", name, engine, pack_bits, len(A), len(B))
+    ctx = make_ctx(engine=engine, pack_bits=pack_bits)
+    want = orc.lv_omp(A, B, -1, 1)
+    p = ed.ed_prepare(ctx, A, B)
+    try:
+        k, script = ed.ed_align(ctx, p)
+    finally:
+        ed.ed_release(p)
+    assert k == want
+    assert apply_script(ed, A, B, script) == k
+    # runs are merged: no two neighbours share an operation
+    assert all(script[j][0] != script[j + 1][0] for j in range(len(script) - 1))
+
+
+@pytest.mark.parametrize("block", [1, 32])
+def test_certified_hash_distance(ed, make_ctx, orc, block):
+    ctx = make_ctx(engine=ed.ENGINE_HASH, block=block, flags=ed.FLAG_CERTIFY)
+    for seed in range(4):
+        A, B, _ = synth.single_pair(12000, 100 + 40 * seed, 50 + seed)
+        say("certify", block, seed)
+        p = ed.ed_prepare(ctx, A, B)
+        k = ed.ed_distance(ctx, p)
+        st = ed.ed_pair_stats(p)
+        ed.ed_release(p)
+        assert k == orc.lv_omp(A, B, -1, 1)
+        assert st["certify_retries"] == 0
+
+
+def test_align_large_pair_both_engines(ed, make_ctx, orc):
+    # 10^6 characters, about 2000 edits: rows of 2001 rounds (16 MB) in device memory
+    A, B, _ = synth.single_pair(10 ** 6, 2000, 21)
+    want = orc.lv_omp(A, B)
+    for engine in (0, 1):
+        say("align large", engine)
+        ctx = make_ctx(engine=engine)
+        p = ed.ed_prepare(ctx, A, B)
+        k, script = ed.ed_align(ctx, p)
+        ed.ed_release(p)
+        assert k == want
+        assert apply_script(ed, A, B, script) == k
+
+
+@pytest.mark.parametrize("pack_bits", [0, 8])
+def test_run_check_finds_every_difference(ed, make_ctx, pack_bits):
+    # the check itself: equal runs pass; one differing character anywhere in a
+    # run (first, inside a word, last, far into a long run) is found; a
+    # difference just past a run's end is not counted
+    d4 = synth.CharDist("uniform", 4)
+    A = synth.random_string(50000, d4, 31)
+    B = A.copy()
+    ctx = make_ctx(pack_bits=pack_bits)
+    p = ed.ed_prepare(ctx, A, B)
+    runs = [(0, 0, 50000), (17, 17, 1000), (100, 100, 1), (49999, 49999, 1)]
+    assert ed.ed_debug_check_runs(ctx, p, runs) == 0
+    ed.ed_release(p)
+    for pos in (0, 31, 32, 33, 4095, 20000, 49999):
+        B2 = A.copy()
+        B2[pos] ^= 1
+        p = ed.ed_prepare(ctx, A, B2)
+        say("check runs", pack_bits, pos)
+        assert ed.ed_debug_check_runs(ctx, p, [(0, 0, 50000)]) == 1
+        assert ed.ed_debug_check_runs(ctx, p, [(0, 0, pos)]) == 0  # ends just before
+        if pos + 1 < 50000:
+            assert ed.ed_debug_check_runs(ctx, p, [(pos + 1, pos + 1, 50000 - pos - 1)]) == 0
+        assert ed.ed_debug_check_runs(ctx, p, [(pos, pos, 1)]) == 1
+        ed.ed_release(p)
+    # shifted runs compare A and B at different offsets
+    P = synth.periodic_string(10000, d4, 32, period=64)
+    p = ed.ed_prepare(ctx, P, P.copy())
+    assert ed.ed_debug_check_runs(ctx, p, [(64, 0, 9000), (0, 128, 9000)]) == 0
+    assert ed.ed_debug_check_runs(ctx, p, [(1, 0, 9000)]) == 1
+    ed.ed_release(p)
