@@ -154,18 +154,21 @@ typedef struct ed_op_run {
 #define ED_OP_INS 3u   /* B[y] inserted; y advances */
 
 /* Edit distance and an optimal edit script, checked.  The frontier rounds of
- * Algorithm 1 (section 3.1) are run twice: once for k, once keeping every
- * round's row in device memory ((k+1)^2 * 4 bytes, allocated and freed by the
- * call); from the row of round k at diagonal n - m the path is traced back on
+ * Algorithm 1 (section 3.1) are run twice: once for k (skipped when an
+ * unbounded ed_distance on the pair with the same engine gave it), once
+ * keeping every round's row in device memory ((k+1)^2 * 4 bytes, allocated
+ * and freed by the call); from the row of round k at diagonal n - m the path is traced back on
  * the device (each round's start comes from one of the three neighbours of the
  * previous round, which names the edit), and every run of matches on it is
  * compared character by character on the device.  The script applied to A
  * gives B and has k edits.  With the hash engine this check makes the result
  * exact: a collision can only make an LCP too long (k too small), and a valid
  * script of k edits shows ED <= k.  runs: caller memory for `runs_cap`
- * entries (2k + 1 always suffice); *n_runs receives the count.  Errors:
- * ED_EINVAL (also when runs_cap is too small; *n_runs then holds the count
- * needed), ED_ENOMEM (the rows do not fit), ED_ECOLLISION (hash engine: a run
+ * entries (2k + 1 always suffice); *n_runs receives the count.  When runs_cap
+ * is too small the call returns ED_EINVAL with *n_runs (and *k_out) set and
+ * keeps the script with the pair: the next ed_align on the pair returns it
+ * without recomputing.  Errors: ED_EINVAL, ED_ENOMEM (the rows do not fit),
+ * ED_ECOLLISION (hash engine: a run
  * does not match; *k_out holds the unchecked k), ED_EINTERNAL (the traced path
  * is not a valid script: a bug), ED_EDEVICE. */
 int ed_align(ed_ctx *ctx, ed_pair *pair, uint64_t *k_out, ed_op_run *runs, uint64_t runs_cap, uint64_t *n_runs,

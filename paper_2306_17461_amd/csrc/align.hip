@@ -20,53 +20,77 @@ __device__ __forceinline__ int32_t amax(int32_t a, int32_t b) { return a > b ? a
 __device__ __forceinline__ int32_t amin(int32_t a, int32_t b) { return a < b ? a : b; }
 }  // namespace
 
-// One lane walks the path: each step reads three entries of the previous row.
-__global__ void traceback_kernel(const int32_t* dump, int32_t k, int32_t n, int32_t m, PathStep* out,
-                                 int32_t* status) {
-    if (threadIdx.x != 0) return;
-    int32_t i = n - m;
-    int32_t f = dump[static_cast<int64_t>(k) * k + k + i];
-    int32_t st = 0;
-    for (int32_t t = k; t >= 0; --t) {
-        PathStep s;
-        s.i = i;
-        s.f = f;
-        if (t == 0) {
-            s.c = 0;
-            s.kind = kStepStart;
-            if (i != 0) st = 1;
-            out[0] = s;
-            break;
-        }
-        const int64_t base = static_cast<int64_t>(t - 1) * (t - 1) + (t - 1);  // diagonal j at base + j
-        const int32_t fa = (i >= -(t - 1) && i <= t - 1) ? dump[base + i] : kNone;
-        const int32_t fb = (i - 1 >= -(t - 1) && i - 1 <= t - 1) ? dump[base + i - 1] : kNone;
-        const int32_t fe = (i + 1 >= -(t - 1) && i + 1 <= t - 1) ? dump[base + i + 1] : kNone;
-        int32_t C = amax(amax(fa + 1, fb + 1), fe);  // kNone + 1 stays negative
-        C = amin(amin(C, n), m + i);
-        int32_t kind, j, fj;
-        if (fa >= 0 && fa + 1 == C) {
-            kind = kStepSub, j = i, fj = fa;
-        } else if (fb >= 0 && fb + 1 == C) {
-            kind = kStepDel, j = i - 1, fj = fb;
-        } else if (fe >= 0 && fe == C) {
-            kind = kStepIns, j = i + 1, fj = fe;
-        } else if (fa >= 0 && fa == C) {
-            kind = kStepNone, j = i, fj = fa;
-        } else {
-            s.c = C;
-            s.kind = kStepFail;
-            out[t] = s;
-            st = 2;
-            break;
-        }
-        s.c = C;
-        s.kind = kind;
-        out[t] = s;
-        i = j;
-        f = fj;
+// The path moves by at most one diagonal per round, so the next kTbRows
+// rounds of the walk stay within kTbRows + 1 diagonals of the current one:
+// the wavefront loads that band of the next kTbRows rows into LDS (one load
+// per lane and row, all in flight together), then one lane takes the steps.
+constexpr int kTbRows = 30;
+
+__global__ __launch_bounds__(64) void traceback_kernel(const int32_t* dump, int32_t k, int32_t n, int32_t m,
+                                                       PathStep* out, int32_t* status) {
+    __shared__ int32_t band[kTbRows][64];  // band[r][l]: row t0 - 1 - r, diagonal ic - 32 + l
+    __shared__ int32_t sh[4];              // i, f, t, finished
+    const int lane = threadIdx.x;
+    if (lane == 0) {
+        sh[0] = n - m;
+        sh[1] = dump[static_cast<int64_t>(k) * k + k + (n - m)];
+        sh[2] = k;
+        sh[3] = 0;
+        *status = 0;
     }
-    *status = st;
+    __syncthreads();
+    for (;;) {
+        const int32_t ic = sh[0], t0 = sh[2];
+        if (t0 == 0) {
+            if (lane == 0) {
+                out[0] = PathStep{sh[0], 0, sh[1], kStepStart};
+                if (sh[0] != 0) *status = 1;
+            }
+            return;
+        }
+        const int32_t R = amin(kTbRows, t0);
+        for (int32_t r = 0; r < R; ++r) {
+            const int32_t u = t0 - 1 - r;
+            const int32_t j = ic - 32 + lane;
+            band[r][lane] = (j >= -u && j <= u) ? dump[static_cast<int64_t>(u) * u + u + j] : kNone;
+        }
+        __syncthreads();
+        if (lane == 0) {
+            int32_t i = ic, f = sh[1];
+            bool failed = false;
+            for (int32_t r = 0; r < R && !failed; ++r) {
+                const int32_t t = t0 - r;  // round of the current state; row t - 1 is band[r]
+                const int32_t* row = band[r] + (32 - ic);
+                const int32_t fa = row[i], fb = row[i - 1], fe = row[i + 1];
+                int32_t C = amax(amax(fa + 1, fb + 1), fe);  // kNone + 1 stays negative
+                C = amin(amin(C, n), m + i);
+                int32_t kind, j, fj;
+                if (fa >= 0 && fa + 1 == C) {
+                    kind = kStepSub, j = i, fj = fa;
+                } else if (fb >= 0 && fb + 1 == C) {
+                    kind = kStepDel, j = i - 1, fj = fb;
+                } else if (fe >= 0 && fe == C) {
+                    kind = kStepIns, j = i + 1, fj = fe;
+                } else if (fa >= 0 && fa == C) {
+                    kind = kStepNone, j = i, fj = fa;
+                } else {
+                    out[t] = PathStep{i, C, f, kStepFail};
+                    *status = 2;
+                    failed = true;
+                    break;
+                }
+                out[t] = PathStep{i, C, f, kind};
+                i = j;
+                f = fj;
+            }
+            sh[0] = i;
+            sh[1] = f;
+            sh[2] = failed ? 0 : t0 - R;
+            sh[3] = failed ? 1 : 0;
+        }
+        __syncthreads();
+        if (sh[3]) return;
+    }
 }
 
 // Each wavefront takes segments w, w + W, ...; lane l compares words l,

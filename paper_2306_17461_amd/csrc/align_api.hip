@@ -1,5 +1,6 @@
 // ed_align and the check behind ED_FLAG_CERTIFY (host side): k from the
-// frontier, the frontier rounds again with every row kept in device memory,
+// frontier (or from the pair's last unbounded distance on the same engine),
+// the frontier rounds again with every row kept in device memory,
 // the path traced back on the device, its geometry checked here, and its runs
 // of matches re-compared on the device.
 #include <hip/hip_runtime.h>
@@ -71,7 +72,11 @@ int64_t path_cost(const std::vector<PathStep>& path, int64_t n, int64_t m) {
 
 int ed::align_locked(ed_ctx* c, ed_pair* p, uint64_t* k_out, std::vector<PathStep>& path, hipStream_t s) {
     uint64_t k = 0;
-    int rc = distance_locked(c, p, -1, &k, nullptr, 0, s);
+    int rc = ED_OK;
+    if (p->known_k >= 0 && p->known_engine == p->engine)
+        k = static_cast<uint64_t>(p->known_k);  // computed before on this pair and engine
+    else
+        rc = distance_locked(c, p, -1, &k, nullptr, 0, s);
     if (rc != ED_OK) return rc;
     const int64_t n = static_cast<int64_t>(p->len[0]), m = static_cast<int64_t>(p->len[1]);
     const uint64_t cap = (k + 1) * (k + 1);
@@ -156,31 +161,42 @@ int ed_align(ed_ctx* c, ed_pair* p, uint64_t* k_out, ed_op_run* runs, uint64_t r
         set_error("ed_align: hipSetDevice failed");
         return ED_EDEVICE;
     }
-    std::vector<PathStep> path;
-    const int rc = align_locked(c, p, k_out, path, static_cast<hipStream_t>(hip_stream));
-    if (rc != ED_OK) return rc;
-    // the edit script: the step's edit, then its run of matches (merged)
-    std::vector<ed_op_run> out;
-    auto push = [&](uint32_t op, uint64_t len) {
-        if (!len) return;
-        if (!out.empty() && out.back().op == op)
-            out.back().len += len;
-        else
-            out.push_back(ed_op_run{op, 0, len});
-    };
-    for (const PathStep& st : path) {
-        if (st.kind == kStepSub) push(ED_OP_SUB, 1);
-        if (st.kind == kStepDel) push(ED_OP_DEL, 1);
-        if (st.kind == kStepIns) push(ED_OP_INS, 1);
-        push(ED_OP_MATCH, static_cast<uint64_t>(st.f - st.c));
+    if (!p->script_kept) {
+        std::vector<PathStep> path;
+        const int rc = align_locked(c, p, &p->script_k, path, static_cast<hipStream_t>(hip_stream));
+        if (rc != ED_OK) {
+            *k_out = p->script_k;
+            return rc;
+        }
+        // the edit script: the step's edit, then its run of matches (merged)
+        std::vector<ed_op_run>& out = p->script;
+        out.clear();
+        auto push = [&](uint32_t op, uint64_t len) {
+            if (!len) return;
+            if (!out.empty() && out.back().op == op)
+                out.back().len += len;
+            else
+                out.push_back(ed_op_run{op, 0, len});
+        };
+        for (const PathStep& st : path) {
+            if (st.kind == kStepSub) push(ED_OP_SUB, 1);
+            if (st.kind == kStepDel) push(ED_OP_DEL, 1);
+            if (st.kind == kStepIns) push(ED_OP_INS, 1);
+            push(ED_OP_MATCH, static_cast<uint64_t>(st.f - st.c));
+        }
+        p->script_kept = true;
     }
-    *n_runs = out.size();
-    if (out.size() > runs_cap) {
-        set_error("ed_align: %llu runs do not fit in %llu", (unsigned long long)out.size(),
+    *k_out = p->script_k;
+    *n_runs = p->script.size();
+    if (p->script.size() > runs_cap) {
+        // kept: a call with a buffer this large returns it without recomputing
+        set_error("ed_align: %llu runs do not fit in %llu", (unsigned long long)p->script.size(),
                   (unsigned long long)runs_cap);
         return ED_EINVAL;
     }
-    if (!out.empty()) std::memcpy(runs, out.data(), out.size() * sizeof(ed_op_run));
+    if (!p->script.empty()) std::memcpy(runs, p->script.data(), p->script.size() * sizeof(ed_op_run));
+    std::vector<ed_op_run>().swap(p->script);
+    p->script_kept = false;
     return ED_OK;
 }
 

@@ -672,6 +672,10 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
     if (rc == ED_OK) {
         *k_out = result;
         p->rounds = result;
+        if (k_max < 0 && !dev_dump && !rows) {
+            p->known_k = static_cast<int64_t>(result);
+            p->known_engine = p->engine;
+        }
         p->counters = total;
         p->launches_distance = launches;
         p->gpu_ns_frontier = gpu_ns;

@@ -70,6 +70,9 @@ struct ed_pair {
     void* f0 = nullptr;    // unused (rows are per call)
     void* f1 = nullptr;
     uint64_t rounds = 0;
+    // the last unbounded distance of this pair and the engine it ran on (-1: none)
+    int64_t known_k = -1;
+    uint32_t known_engine = 0;
     ed::CountersDev counters{};
     int launches_prepare = 0;
     int launches_distance = 0;
@@ -80,6 +83,10 @@ struct ed_pair {
     double gpu_ns_frontier = 0;
     double gpu_ns_lcp = 0;  // last ed_debug_lcp with the grid tier (ED_FLAG_TIMING)
     uint64_t certify_retries = 0;  // ED_FLAG_CERTIFY: hash results whose check failed
+    // ed_align: a script that did not fit the caller's buffer, kept for the retry
+    std::vector<ed_op_run> script;
+    uint64_t script_k = 0;
+    bool script_kept = false;
     uint64_t rounds_phase_a = 0;
     double us_phase_a = 0, us_phase_b = 0;
 };

@@ -170,3 +170,25 @@ def test_run_check_finds_every_difference(ed, make_ctx, pack_bits):
     assert ed.ed_debug_check_runs(ctx, p, [(64, 0, 9000), (0, 128, 9000)]) == 0
     assert ed.ed_debug_check_runs(ctx, p, [(1, 0, 9000)]) == 1
     ed.ed_release(p)
+
+
+def test_small_buffer_then_retry_returns_the_kept_script(ed, make_ctx, orc):
+    import ctypes
+    A, B, _ = synth.single_pair(30000, 300, 41)
+    ctx = make_ctx(engine=ed.ENGINE_HASH)
+    p = ed.ed_prepare(ctx, A, B)
+    k = ctypes.c_uint64()
+    cnt = ctypes.c_uint64()
+    small = (ed.ed_op_run * 1)()
+    rc = ed.lib.ed_align(ctx, p, ctypes.byref(k), small, 1, ctypes.byref(cnt), None)
+    assert rc == ed.ED_EINVAL and cnt.value > 1 and k.value == orc.lv_omp(A, B, -1, 1)
+    runs = (ed.ed_op_run * cnt.value)()
+    cnt2 = ctypes.c_uint64()
+    assert ed.lib.ed_align(ctx, p, ctypes.byref(k), runs, cnt.value, ctypes.byref(cnt2), None) == ed.ED_OK
+    script = [(int(runs[i].op), int(runs[i].len)) for i in range(cnt2.value)]
+    assert cnt2.value == cnt.value
+    assert apply_script(ed, A, B, script) == k.value
+    # a fresh call computes the same script again
+    k3, script3 = ed.ed_align(ctx, p)
+    assert k3 == k.value and script3 == script
+    ed.ed_release(p)
