@@ -230,6 +230,49 @@ def engine_matrix(ed, dev, ks, want, stream, reps=3):
     return out
 
 
+def paper_shape_leg(ed, stream, reps=3):
+    """The paper's own synthetic workload: n = 1e8 characters uniform over 256
+    symbols, B = A + k planted edits, k = 1e2 .. 1e5 (seed 0), 8 bits per
+    character, both engines (hash: b = 32, as the paper's BFS-B-Hash).  Kernel
+    times (prepare + frontier, median of `reps`) beside the paper's full-run
+    times for the same n and k (its best of BFS-Hash and BFS-B-Hash, 96 cores).
+    Distances checked against the stored oracle values."""
+    import torch
+    import synth
+    gold = stored_oracle()
+    want = {g["k"]: g["ed"] for g in gold["paper"]} if gold and "paper" in gold else {}
+    ctxs = {"direct": ed.ed_init(0, engine=ed.ENGINE_DIRECT, flags=ed.FLAG_TIMING),
+            "hash": ed.ed_init(0, engine=ed.ENGINE_HASH, flags=ed.FLAG_TIMING)}
+    out = {}
+    for k in KS:
+        log("paper-shape leg: sigma=256 k=%d" % k)
+        A, B, _ = synth.single_pair(N, k, 0, sigma=256)
+        tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        del A, B
+        row = {}
+        for name, ctx in ctxs.items():
+            ts = []
+            for _ in range(reps):
+                kk, st = run_pair(ed, ctx, tA, tB, stream)
+                if k in want and kk != want[k]:
+                    raise SystemExit("paper-shape leg: %s k=%d gave %d, oracle %d" % (name, k, kk, want[k]))
+                ts.append((st["gpu_ns_prepare_kernel"] + st["gpu_ns_frontier_kernel"]) / 1e9)
+            row[name + "_s"] = sorted(ts)[len(ts) // 2]
+            row["ed"] = kk
+        paper = min(PAPER_N1E8_SECONDS[k].values())
+        best = min(row["direct_s"], row["hash_s"])
+        row.update({"paper_s": paper, "paper_over_this": round(paper / best, 1),
+                    "equal_to_stored_oracle": (row["ed"] == want[k]) if k in want else None})
+        out[str(k)] = row
+        del tA, tB
+        torch.cuda.empty_cache()
+    for c in ctxs.values():
+        ed.ed_shutdown(c)
+    return {"workload": "n=1e8 uniform over 256 symbols, B = A + k planted edits, seed 0, 8 bits per character",
+            "paper_hardware": "96 cores (4x Intel Xeon Gold 6252), its best of BFS-Hash and BFS-B-Hash, "
+                              "Monte Carlo hashing", "per_k": out}
+
+
 def align_leg(ed, dev, ks, want, stream, only=(1000, 10000, 100000)):
     """Checked (certified) hash-engine results: ed_align on the single pairs
     (hash engine, b = 32): k, the edit script traced back through every
@@ -362,6 +405,8 @@ def main():
     ap.add_argument("--no-lcp", action="store_true", help="skip the long-LCP bandwidth leg")
     ap.add_argument("--no-table", action="store_true", help="skip the 8-bit table-build leg")
     ap.add_argument("--no-align", action="store_true", help="skip the checked alignment leg")
+    ap.add_argument("--no-paper-shape", action="store_true",
+                    help="skip the paper's own workload shape (alphabet 256) leg")
     ap.add_argument("--no-matrix", action="store_true",
                     help="skip the engine matrix (direct 8-bit, hash b=1, hash block sweep)")
     ap.add_argument("--serve", type=int, default=40, metavar="N",
@@ -538,6 +583,10 @@ def main():
     if not args.no_align and n == N:
         align = align_leg(ed, dev, ks, [r[0] for r in last], stream)
 
+    paper_shape = None
+    if not args.no_paper_shape and n == N:
+        paper_shape = paper_shape_leg(ed, stream)
+
     batch = None
     if not args.no_batch:
         batch = batch_leg(ed, ctxs["direct"])
@@ -585,6 +634,7 @@ def main():
         "prepare_roofline": prepare_roofline,
         "cpu_baseline": cpu,
         "paper_context": paper_context(ks, n),
+        "paper_shape": paper_shape,
         "other_engine": other,
         "engine_matrix": matrix,
         "align_checked": align,

@@ -209,8 +209,11 @@ struct HashQ {
     HashDev h;             // r (h.pow0 / h.pow1 as global pointers below)
     gword* pow0;           // r^a, a < 65536
     gword* pow1;           // r^(65536 a), a < 65536
+    gword* rinv;           // r^(-d), d = 0..32
+    const uint32_t* w8;    // byte limbs of the weights of a 32-character block (8-bit strings)
     uint64_t r4;           // r^4
-    const uint64_t* lut4;  // LDS: hash of the 4 characters of a packed byte
+    uint64_t r32;          // r^32
+    const uint64_t (*lut32)[256];  // LDS: packed byte k of a 2-bit word, weights r^(31-4k-j)
     int32_t log2b;
 };
 
@@ -231,7 +234,7 @@ __device__ __forceinline__ uint64_t partial_hash(const SView& S, const HashQ& q,
                 const int32_t pos = s + i;
                 const uint64_t word = S.w[pos >> 5];
                 const uint32_t byte = static_cast<uint32_t>(word >> (((pos >> 2) & 7) * 8)) & 0xFFu;
-                h = mp_add(mp_mul(h, q.r4), q.lut4[byte]);
+                h = mp_add(mp_mul(h, q.r4), q.lut32[7][byte]);  // weights r^(3-j)
             }
         }
         for (; i < e; ++i) {
@@ -249,13 +252,55 @@ __device__ __forceinline__ uint64_t partial_hash(const SView& S, const HashQ& q,
     return h;
 }
 
+// b = 32: the block's characters past e are masked to zero and the whole
+// block is hashed with the weights r^(31-k) (table lookups at 2 bits per
+// character, byte dot products against the weights' byte limbs at 8 bits),
+// giving M = h(S[32j .. 32j+e)) r^(32-e); then
+// H = T[j] r^e + h(S[32j .. 32j+e)) = (T[j] r^32 + M) r^(e-32).
+__device__ __forceinline__ uint64_t block32_masked_hash8(gword* w8s, const uint32_t* W, int32_t j, int32_t e) {
+    uint32_t d[8];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int32_t keep = e - 8 * u;  // characters of word u inside the prefix
+        uint64_t w = w8s[4 * j + u];
+        w = keep >= 8 ? w : (keep <= 0 ? 0 : w & ((1ull << (8 * keep)) - 1));
+        d[2 * u] = static_cast<uint32_t>(w);
+        d[2 * u + 1] = static_cast<uint32_t>(w >> 32);
+    }
+    uint64_t lo = 0, hi = 0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        uint32_t sum = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) sum = __builtin_amdgcn_udot4(d[i], W[8 * t + i], sum, false);
+        if (t <= 4)
+            lo += static_cast<uint64_t>(sum) << (8 * t);
+        else
+            hi += ((static_cast<uint64_t>(sum) << (8 * t)) & kP) + (static_cast<uint64_t>(sum) >> (61 - 8 * t));
+    }
+    return mp_fold(lo + hi);
+}
+
+__device__ __forceinline__ uint64_t block32_masked_hash(const SView& S, const HashQ& q, int32_t j, int32_t e) {
+    if (S.bpc == 2) {
+        const uint64_t w = S.w[j] & ((1ull << (2 * e)) - 1);
+        uint64_t s = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += q.lut32[k][(w >> (8 * k)) & 0xFFu];
+        return mp_fold(s);
+    }
+    return block32_masked_hash8(S.w, q.w8, j, e);
+}
+
 __device__ __forceinline__ uint64_t get_hash(const SView& S, gword* T, const HashQ& q,
                                              int32_t p) {
     const int32_t j = p >> q.log2b;
     const int32_t e = p & ((1 << q.log2b) - 1);
     uint64_t h = T[j];
-    if (e) h = mp_add(mp_mul(h, q.pow0[e]), partial_hash(S, q, j << q.log2b, e));
-    return h;
+    if (!e) return h;
+    if (q.log2b == 5 && S.bpc == 2)
+        return mp_mul(mp_add(mp_mul(h, q.r32), block32_masked_hash(S, q, j, e)), q.rinv[32 - e]);
+    return mp_add(mp_mul(h, q.pow0[e]), partial_hash(S, q, j << q.log2b, e));
 }
 
 // Wave-parallel LCP by hashing (uniform x, y, lim; the first l0 characters
@@ -333,19 +378,11 @@ __device__ __forceinline__ int32_t lcp_wave_hash(const SView& A, const SView& B,
     return lcp_wave_direct(A, B, x, y, lim, 0);
 }
 
-// LDS table: hash of the 4 characters held by a packed byte,
-// c0 r^3 + c1 r^2 + c2 r + c3 with c_j = bits [2j, 2j+2) of the byte.
-__device__ __forceinline__ void build_lut4(uint64_t* lut4, uint64_t r, int tid, int nthreads) {
-    const uint64_t r2 = mp_mul(r, r);
-    const uint64_t r3 = mp_mul(r2, r);
-    for (int v = tid; v < 256; v += nthreads) {
-        const uint64_t c0 = v & 3, c1 = (v >> 2) & 3, c2 = (v >> 4) & 3, c3 = (v >> 6) & 3;
-        uint64_t h = mp_mul(c0, r3);
-        h = mp_add(h, mp_mul(c1, r2));
-        h = mp_add(h, mp_mul(c2, r));
-        h = mp_add(h, c3);
-        lut4[v] = h;
-    }
+// LDS copy of the host-built tables of packed bytes: lut32[k][v] is the hash
+// of the 4 characters of byte v as byte k of a 32-character word, weights
+// r^(31-4k-j) (row 7 is the hash of the 4 characters alone).
+__device__ __forceinline__ void load_lut32(uint64_t (*lut32)[256], const uint64_t* rtab, int tid, int nthreads) {
+    for (int i = tid; i < 8 * 256; i += nthreads) lut32[i >> 8][i & 255] = rtab[kRtabLut32 + i];
 }
 
 // ---------------------------------------------------------------------------

@@ -59,7 +59,7 @@ struct RoundShared {
 
 struct LdsState {
     int32_t row[2][kLdsRowLen];
-    uint64_t lut4[256];
+    uint64_t lut32[8][256];
     RoundShared rs;
     CountersDev cnt;
 };
@@ -424,7 +424,7 @@ __device__ __forceinline__ gword* uni(gword* p) { return (gword*)uni(reinterpret
 // runs rounds, so the other engine's code and fields drop out of it.
 template <int KIND>
 __device__ __forceinline__ Engine make_engine(const PairDev& p, const HashDev& h, int lane_words,
-                                              const uint64_t* lut4) {
+                                              const uint64_t (*lut32)[256]) {
     Engine en;
     const uint32_t alpha = *p.alpha;
     pair_views(p, alpha, en.A, en.B);
@@ -443,15 +443,20 @@ __device__ __forceinline__ Engine make_engine(const PairDev& p, const HashDev& h
         en.q.pow0 = uni((gword*)h.pow0);
         en.q.pow1 = uni((gword*)h.pow1);
         en.q.r4 = mp_mul(mp_mul(en.q.h.r, en.q.h.r), mp_mul(en.q.h.r, en.q.h.r));
-        en.q.lut4 = lut4;
+        en.q.r32 = uni(h.pow0[32]);
+        en.q.rinv = uni((gword*)(h.rtab + kRtabRinv32));
+        en.q.w8 = reinterpret_cast<const uint32_t*>(uni(reinterpret_cast<uint64_t>(h.rtab + kRtabDot8)));
+        en.q.lut32 = lut32;
         en.q.log2b = uni(p.log2b);
     } else {
         en.TA = en.TB = nullptr;
         en.q.h.r = 0;
         en.q.h.pow0 = en.q.h.pow1 = nullptr;
         en.q.pow0 = en.q.pow1 = nullptr;
-        en.q.r4 = 0;
-        en.q.lut4 = nullptr;
+        en.q.r4 = en.q.r32 = 0;
+        en.q.rinv = nullptr;
+        en.q.w8 = nullptr;
+        en.q.lut32 = nullptr;
         en.q.log2b = 0;
     }
     en.kind = KIND;
@@ -542,7 +547,7 @@ template <int KIND>
 __device__ void solo_task(const TaskParams& P, int32_t pi, LdsState& L, JobCursor& jc, Cnt& cnt) {
     TaskPair* S = P.pairs + pi;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const Engine en = make_engine<KIND>(S->p, P.h, P.lane_words, L.lut4);
+    const Engine en = make_engine<KIND>(S->p, P.h, P.lane_words, L.lut32);
     const int32_t n = en.A.len, m = en.B.len;
     const int32_t maxnm = imax(n, m);
     const int32_t off = kLdsRoundsMax + 2;  // diagonal i at row[i + off]
@@ -598,7 +603,7 @@ __device__ void chunk_task(const TaskParams& P, int32_t pi, int32_t c, LdsState&
                            Cnt& cnt) {
     TaskPair* S = P.pairs + pi;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const Engine en = make_engine<KIND>(S->p, P.h, P.lane_words, L.lut4);
+    const Engine en = make_engine<KIND>(S->p, P.h, P.lane_words, L.lut32);
     RoundShared& RS = L.rs;
     const int32_t t = uni(S->t), H = uni(S->H), T = uni(S->T), C = uni(S->chunk), K = uni(S->K),
                   cur = uni(S->cur);
@@ -680,9 +685,9 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
     cnt_init_shared(&L.cnt);
     JobCursor jc;
     rs_init(L.rs, jc);
-    if (KIND == 1) build_lut4(L.lut4, P.h.r, tid, nthr);
+    if (KIND == 1) load_lut32(L.lut32, P.h.rtab, tid, nthr);
     __syncthreads();
-    const Engine en = make_engine<KIND>(P.p, P.h, P.lane_words, L.lut4);
+    const Engine en = make_engine<KIND>(P.p, P.h, P.lane_words, L.lut32);
     int32_t* const dump = DUMP ? P.dump : nullptr;
     RoundShared& RS = L.rs;
     const int32_t n = en.A.len, m = en.B.len;
@@ -839,7 +844,7 @@ __global__ __launch_bounds__(kFrontierThreads) void task_kernel(TaskParams P) {
     cnt_init_shared(&L.cnt);
     JobCursor jc;
     rs_init(L.rs, jc);
-    if (KIND == 1) build_lut4(L.lut4, P.h.r, tid, blockDim.x);
+    if (KIND == 1) load_lut32(L.lut32, P.h.rtab, tid, blockDim.x);
     for (;;) {
         __syncthreads();
         if (tid == 0) L.rs.task = q_pop(P);
@@ -857,15 +862,15 @@ __global__ __launch_bounds__(kFrontierThreads) void task_kernel(TaskParams P) {
 }
 
 __global__ __launch_bounds__(256) void lcp_query_kernel(LcpQueryParams Q) {
-    __shared__ uint64_t lut4[256];
+    __shared__ uint64_t lut32[8][256];
     __shared__ CountersDev sh;
     Cnt cnt;
     cnt_bind(cnt, &sh);
     cnt_init_shared(&sh);
-    if (Q.engine == 1) build_lut4(lut4, Q.h.r, threadIdx.x, blockDim.x);
+    if (Q.engine == 1) load_lut32(lut32, Q.h.rtab, threadIdx.x, blockDim.x);
     __syncthreads();
-    const Engine en = Q.engine == 1 ? make_engine<1>(Q.p, Q.h, Q.lane_words, lut4)
-                                    : make_engine<0>(Q.p, Q.h, Q.lane_words, lut4);
+    const Engine en = Q.engine == 1 ? make_engine<1>(Q.p, Q.h, Q.lane_words, lut32)
+                                    : make_engine<0>(Q.p, Q.h, Q.lane_words, lut32);
     const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
     for (int64_t qi = wave; qi < Q.count; qi += nwaves) {

@@ -52,6 +52,7 @@ struct HashDev {
     uint64_t r;             // base
     const uint64_t* pow0;   // r^a, a < 65536
     const uint64_t* pow1;   // r^(65536 a), a < 65536
+    const uint64_t* rtab;   // lookup tables and powers (kRtab* layout)
 };
 
 // Per-run counters (device), summed with atomics at kernel exit.
@@ -179,12 +180,14 @@ struct PrepParams {
     const uint64_t* rtab;  // the kRtab* layout below
 };
 
-// Power and lookup tables of the table passes, built on the host with the
-// other power tables (R = r^kTileChars):
+// Power and lookup tables of the table passes and of the hash queries, built
+// on the host with the other power tables (R = r^kTileChars):
 //   r^p, p = 0..64 | r^(64k), k = 0..256 | R^d, d = 0..64 |
 //   lut32[k][v] = sum_j c_j r^(31-4k-j), c_j = 2-bit code j of byte v (k = 0..7) |
 //   lut8[k][v] = v r^(7-k) (k = 0..7) | r^(-256 d), d = 0..64 |
-//   R^(8 * 2^j), j = 0..9 | R^(8 (l + 1)), l = 0..63
+//   R^(8 * 2^j), j = 0..9 | R^(8 (l + 1)), l = 0..63 |
+//   byte t of the weights r^(31-4i-j), j = 0..3, packed in dword 8t + i (t, i = 0..7; two per entry) |
+//   r^(-d), d = 0..32
 constexpr int kRtabRseg = 65;
 constexpr int kRtabR = kRtabRseg + 257;
 constexpr int kRtabLut32 = kRtabR + 65;
@@ -192,7 +195,9 @@ constexpr int kRtabLut8 = kRtabLut32 + 8 * 256;
 constexpr int kRtabRinv256 = kRtabLut8 + 8 * 256;
 constexpr int kRtabR8pow2 = kRtabRinv256 + 65;
 constexpr int kRtabR8lane = kRtabR8pow2 + 10;
-constexpr int kRtabEntries = kRtabR8lane + 64;
+constexpr int kRtabDot8 = kRtabR8lane + 64;
+constexpr int kRtabRinv32 = kRtabDot8 + 32;
+constexpr int kRtabEntries = kRtabRinv32 + 33;
 
 struct LcpQueryParams {
     PairDev p;
