@@ -371,11 +371,25 @@ def serve_leg(ed, ctx, count, seed=0, warmup=0):
         lat2.append(time.perf_counter() - (start + arrive[i]))
     span2 = time.perf_counter() - start
     q50, q99 = pct(lat2)
+    # served latency by n decade and by alphabet
+    lat_by_tag = {r["tag"]: (r["t_done_ns"] - r["t_arrive_ns"]) / 1e9 for r in res}
+    buckets = {}
+    for i, r in enumerate(trace):
+        for key in ("n=1e%d" % int(math.log10(max(1, r["n"]))), "sigma=%d" % r["sigma"]):
+            buckets.setdefault(key, []).append((lat_by_tag[i], lat2[i]))
+    by = {}
+    for key in sorted(buckets):
+        v = buckets[key]
+        s50, s99 = pct([a for a, _ in v])
+        p50_, p99_ = pct([b for _, b in v])
+        by[key] = {"requests": len(v), "served_p50_s": s50, "served_p99_s": s99,
+                   "per_pair_p50_s": p50_, "per_pair_p99_s": p99_}
     return {"workload": "%d requests, Poisson arrivals, n log-uniform [1e2, 1e7], alphabet 4 or 20, "
                         "k uniform [0, 0.05 n], seed %d" % (count, seed),
             "arrival_rate_per_s": rate, "batched_pairs_per_s": count / tb,
             "served": {"pairs_per_s": count / span, "p50_s": p50, "p99_s": p99},
             "per_pair": {"pairs_per_s": count / span2, "p50_s": q50, "p99_s": q99},
+            "latency_by_bucket": by,
             "equal_to_stored_oracle": exact}
 
 
@@ -615,6 +629,21 @@ def main():
                "kind": "oracle",
                "sample": "oracle lv_omp (OpenMP Landau-Vishkin, 8-byte word LCP) on the same %d "
                          "pairs, once, %.1f s" % (len(ks), tc)}
+        # the literal sequential Landau-Vishkin (character-by-character LCP), one thread:
+        # the 10,000-character pair with 100 planted edits, and the n = 1e8 pairs with k <= 1e3
+        naive = {}
+        A1, B1, _ = synth.small_pair(0)
+        t1 = time.perf_counter()
+        k1 = oracle.lv_naive(A1, B1)
+        naive["n1e4_k100"] = {"ed": k1, "s": round(time.perf_counter() - t1, 4)}
+        for i, k in enumerate(ks):
+            if k <= 1000:
+                t1 = time.perf_counter()
+                kc = oracle.lv_naive(host[i][0], host[i][1])
+                if kc != last[i][0]:
+                    raise SystemExit("GPU %d != lv_naive %d at k=%d" % (last[i][0], kc, k))
+                naive["n1e8_k%d" % k] = {"ed": kc, "s": round(time.perf_counter() - t1, 3)}
+        cpu["lv_naive_single_thread"] = naive
 
     for c in ctxs.values():
         ed.ed_shutdown(c)

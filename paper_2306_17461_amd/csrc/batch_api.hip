@@ -54,14 +54,14 @@ long long task_chunk(int32_t pi, int32_t c) {
 int32_t block_rounds_of(const ed_ctx* c) {
     const uint32_t v = c->opt.task_block_rounds ? c->opt.task_block_rounds
                        : c->opt.block_rounds    ? c->opt.block_rounds
-                                                : kDefaultBlockRounds;
+                                                : kTaskDefaultBlockRounds;
     return static_cast<int32_t>(v);
 }
 
 uint32_t task_solo_rounds(const ed_ctx* c) {
     return c->opt.task_lds_rounds ? c->opt.task_lds_rounds
            : c->opt.lds_rounds    ? c->opt.lds_rounds
-                                  : kDefaultLdsRounds;
+                                  : kTaskDefaultLdsRounds;
 }
 
 int32_t chunk_diags_of(const ed_ctx* c) {

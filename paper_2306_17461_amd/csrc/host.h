@@ -31,8 +31,12 @@ constexpr size_t kPowEntries = 2 * 65536 + kRtabEntries;
 // layout of a pair's small device block
 constexpr size_t kMiscAlpha = 64;
 
-constexpr uint32_t kDefaultLdsRounds = 1024;
-constexpr uint32_t kDefaultBlockRounds = 32;
+// single-pair kernel (measured best at n = 1e8 for k = 1e2 .. 1e5)
+constexpr uint32_t kDefaultLdsRounds = 512;
+constexpr uint32_t kDefaultBlockRounds = 64;
+// many-pair kernel, when neither its own knob nor the single-pair one is set
+constexpr uint32_t kTaskDefaultLdsRounds = 1024;
+constexpr uint32_t kTaskDefaultBlockRounds = 32;
 constexpr int32_t kChunkDiags = 2048;  // diagonals per chunk task
 
 }  // namespace ed
