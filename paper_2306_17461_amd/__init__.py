@@ -35,6 +35,7 @@ FLAG_NO_PHASE_A = 2
 FLAG_SHUFFLE = 4
 FLAG_TIMING = 8
 FLAG_CERTIFY = 16
+FLAG_WEAK_HASH = 32
 OP_MATCH, OP_SUB, OP_DEL, OP_INS = 0, 1, 2, 3
 BUF_PACKED2 = 0
 BUF_BYTES = 1

@@ -161,8 +161,11 @@ static int check_options(const ed_options* o) {
     return ED_OK;
 }
 
-int ed::ctx_set_hash(ed_ctx* c, uint64_t seed) {
-    const uint64_t r = ed_hash_base(seed);
+uint64_t ed::opt_base(const ed_options& o) {
+    return (o.flags & ED_FLAG_WEAK_HASH) ? 1 : ed_hash_base(o.hash_seed);
+}
+
+int ed::ctx_set_hash(ed_ctx* c, uint64_t r) {
     if (c->d_pow && r == c->r) return ED_OK;
     std::vector<uint64_t> h(kPowEntries);
     // pow0 | pow1 | rtab
@@ -274,7 +277,7 @@ int ed_init(ed_ctx** out, int device, const ed_options* opt) {
         ed_shutdown(c);
         return ED_EDEVICE;
     }
-    int rc = ctx_set_hash(c, o.hash_seed);
+    int rc = ctx_set_hash(c, opt_base(o));
     if (rc != ED_OK) {
         ed_shutdown(c);
         return rc;
@@ -291,7 +294,7 @@ int ed_set_options(ed_ctx* c, const ed_options* opt) {
         return ED_EINVAL;
     }
     HIP_TRY(hipSetDevice(c->device));
-    int rc = ctx_set_hash(c, opt->hash_seed);
+    int rc = ctx_set_hash(c, opt_base(*opt));
     if (rc != ED_OK) return rc;
     c->opt = *opt;
     return ED_OK;
@@ -386,7 +389,16 @@ int ed::prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B
     const uint32_t b = c->opt.block ? c->opt.block : 32;
     p->log2b = log2u(b);
     p->force8 = c->opt.pack_bits == 8 ? 1 : 0;
-    p->seed = c->opt.hash_seed;
+    if (c->opt.engine == ED_ENGINE_HASH) {
+        // tables with the base of the current options (a query on an older
+        // pair may have left the context on that pair's base)
+        const int rc = ctx_set_hash(c, opt_base(c->opt));
+        if (rc != ED_OK) {
+            delete p;
+            return rc;
+        }
+    }
+    p->r = c->r;
     const bool table = p->engine == ED_ENGINE_HASH;
     const uint8_t* src[2] = {A, B};
     int32_t tiles[2];
@@ -541,8 +553,8 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
         set_error("ed_distance: pair has no prefix tables");
         return ED_EINVAL;
     }
-    if (p->engine == ED_ENGINE_HASH && p->seed != c->opt.hash_seed) {
-        int rc = ctx_set_hash(c, p->seed);
+    if (p->engine == ED_ENGINE_HASH && p->r != c->r) {
+        int rc = ctx_set_hash(c, p->r);
         if (rc != ED_OK) return rc;
     }
     const int64_t n = static_cast<int64_t>(p->len[0]), m = static_cast<int64_t>(p->len[1]);
@@ -852,8 +864,8 @@ int ed_debug_lcp(ed_ctx* c, ed_pair* p, int engine, const int64_t* x, const int6
         }
     }
     if (count == 0) return ED_OK;
-    if (eng == 1 && p->seed != c->opt.hash_seed) {
-        int rc = ctx_set_hash(c, p->seed);
+    if (eng == 1 && p->r != c->r) {
+        int rc = ctx_set_hash(c, p->r);
         if (rc != ED_OK) return rc;
     }
     hipStream_t s = static_cast<hipStream_t>(hip_stream);

@@ -168,14 +168,14 @@ int batch_locked(ed_ctx* c, ed_pair* const* pairs, uint64_t count, int64_t k_max
             set_error("ed_batch: pair %llu is NULL or from another context", (unsigned long long)i);
             return ED_EINVAL;
         }
-        if (pairs[i]->engine != engine) {
-            set_error("ed_batch: all pairs must use the same engine");
+        if (pairs[i]->engine != engine || (engine == ED_ENGINE_HASH && pairs[i]->r != pairs[0]->r)) {
+            set_error("ed_batch: all pairs must use the same engine (and hash base)");
             return ED_EINVAL;
         }
     }
     if (count > static_cast<uint64_t>(INT32_MAX)) return ED_EINVAL;
-    if (engine == ED_ENGINE_HASH && pairs[0]->seed != c->opt.hash_seed) {
-        int rc = ctx_set_hash(c, pairs[0]->seed);
+    if (engine == ED_ENGINE_HASH && pairs[0]->r != c->r) {
+        int rc = ctx_set_hash(c, pairs[0]->r);
         if (rc != ED_OK) return rc;
     }
     const uint32_t solo = task_solo_rounds(c);

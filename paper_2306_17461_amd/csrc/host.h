@@ -65,7 +65,7 @@ struct ed_pair {
     uint32_t engine = 0;
     int32_t log2b = 5;
     int32_t force8 = 0;
-    uint64_t seed = 0;
+    uint64_t r = 0;  // hash base its tables were built with
     void* w2[2] = {nullptr, nullptr};
     void* w8[2] = {nullptr, nullptr};
     void* tab[2] = {nullptr, nullptr};
@@ -97,7 +97,10 @@ struct ed_pair {
 
 namespace ed {
 void set_error(const char* fmt, ...);
-int ctx_set_hash(ed_ctx* c, uint64_t seed);
+// hash base of a set of options (the seed's base, or 1 with ED_FLAG_WEAK_HASH)
+uint64_t opt_base(const ed_options& o);
+// power and lookup tables of base r on the context (no work when already there)
+int ctx_set_hash(ed_ctx* c, uint64_t r);
 void pair_free(ed_pair* p);
 PairDev pair_dev(const ed_pair* p);
 HashDev ctx_hash(const ed_ctx* c);

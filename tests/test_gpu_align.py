@@ -192,3 +192,56 @@ def test_small_buffer_then_retry_returns_the_kept_script(ed, make_ctx, orc):
     k3, script3 = ed.ed_align(ctx, p)
     assert k3 == k.value and script3 == script
     ed.ed_release(p)
+
+
+def test_weak_hash_collisions_are_caught(ed, make_ctx, orc):
+    # fault injection: with the hash base r = 1 a string hashes like any of its
+    # permutations.  B is A with one pair of neighbouring characters swapped
+    # (ED = 2); the weak hash sees equal prefixes past the swap, so the plain
+    # hash distance comes out too small (one-sided, never too large).  The check
+    # of ed_align must reject it, and ED_FLAG_CERTIFY must answer the exact 2.
+    # (the swap lies past the first 16384 characters, which the lane and
+    # wavefront tiers compare directly before the hash search takes over)
+    d4 = synth.CharDist("uniform", 4)
+    A = synth.random_string(100000, d4, 61)
+    pos = next(i for i in range(50000, 100000) if A[i] != A[i + 1])
+    B = A.copy()
+    B[pos], B[pos + 1] = A[pos + 1], A[pos]
+    assert orc.lv_omp(A, B, -1, 1) == 2
+    weak = make_ctx(engine=ed.ENGINE_HASH, flags=ed.FLAG_WEAK_HASH)
+    p = ed.ed_prepare(weak, A, B)
+    k_weak = ed.ed_distance(weak, p)
+    assert k_weak < 2  # the collision made an LCP too long
+    with pytest.raises(ed.EdError) as ei:
+        ed.ed_align(weak, p)
+    assert ei.value.status == ed.ED_ECOLLISION
+    ed.ed_release(p)
+    cert = make_ctx(engine=ed.ENGINE_HASH, flags=ed.FLAG_WEAK_HASH | ed.FLAG_CERTIFY)
+    p = ed.ed_prepare(cert, A, B)
+    assert ed.ed_distance(cert, p) == 2
+    assert ed.ed_pair_stats(p)["certify_retries"] == 1
+    ed.ed_release(p)
+    # the engines of a strong context agree with the oracle on the same pair
+    strong = make_ctx(engine=ed.ENGINE_HASH)
+    p = ed.ed_prepare(strong, A, B)
+    assert ed.ed_distance(strong, p) == 2
+    ed.ed_release(p)
+
+
+def test_pairs_keep_their_hash_base_across_option_changes(ed, make_ctx, orc):
+    # a pair's tables are built with the base of the options at prepare time;
+    # queries on pairs of different bases (in any order) each use their own
+    ctx = make_ctx(engine=ed.ENGINE_HASH, hash_seed=1)
+    pairs = []
+    for s in range(4):
+        A, B, _ = synth.single_pair(20000, 150, 70 + s)
+        if s:
+            o = ed.ed_get_options(ctx)
+            o["hash_seed"] = 1 + s
+            ed.ed_set_options(ctx, **o)
+        pairs.append((ed.ed_prepare(ctx, A, B), orc.lv_omp(A, B, -1, 1)))
+    for p, want in pairs + pairs[::-1]:
+        assert ed.ed_distance(ctx, p) == want
+        assert ed.ed_pair_stats(p)["collisions"] == 0
+    for p, _ in pairs:
+        ed.ed_release(p)
