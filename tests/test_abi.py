@@ -56,3 +56,17 @@ def test_null_arguments_rejected():
     assert ed.lib.ed_release(None) == ed.ED_EINVAL
     assert ed.lib.ed_distance(None, None, -1, None, None) == ed.ED_EINVAL
     assert ed.lib.ed_prepare(None, None, 0, None, 0, 1, None, None) == ed.ED_EINVAL
+
+
+def test_binding_constants_match_the_header():
+    import re
+    import paper_2306_17461_amd as ed
+    src = open(os.path.join(ROOT, "include", "ed.h")).read()
+    consts = {m.group(1): m.group(2) for m in re.finditer(r"#define (ED_\w+) \(?\(?(?:uint64_t\))?(-?\d+)u?\)?", src)}
+    assert int(consts["ED_MAX_LEN"]) == ed.ED_MAX_LEN
+    for name, py in [("ED_FLAG_DEBUG_DUMP", "FLAG_DEBUG_DUMP"), ("ED_FLAG_NO_PHASE_A", "FLAG_NO_PHASE_A"),
+                     ("ED_FLAG_SHUFFLE", "FLAG_SHUFFLE"), ("ED_FLAG_TIMING", "FLAG_TIMING"),
+                     ("ED_FLAG_CERTIFY", "FLAG_CERTIFY"), ("ED_FLAG_WEAK_HASH", "FLAG_WEAK_HASH"),
+                     ("ED_OP_MATCH", "OP_MATCH"), ("ED_OP_SUB", "OP_SUB"), ("ED_OP_DEL", "OP_DEL"),
+                     ("ED_OP_INS", "OP_INS"), ("ED_ECOLLISION", "ED_ECOLLISION"), ("ED_EINVAL", "ED_EINVAL")]:
+        assert int(consts[name]) == getattr(ed, py), name

@@ -518,3 +518,44 @@ def test_serve_tiny_budget_and_growth(ed, make_ctx, orc):
     A, B = reqs[0]
     assert ed.ed_serve_submit(srv, A, B, 0) == ed.ED_ENOMEM
     ed.ed_serve_close(srv)
+
+
+def test_invalid_argument_matrix(ed, make_ctx):
+    # every entry point refuses bad arguments with ED_EINVAL before touching memory
+    import ctypes
+    say("invalid arguments")
+    ctx = make_ctx()
+    other = make_ctx()
+    A = synth.random_string(100, synth.CharDist("uniform", 4), 1)
+    keep = (ctypes.c_uint8 * 100).from_buffer_copy(A.tobytes())
+    out = ctypes.c_void_p()
+    # NULL string with a positive length, and lengths at or past the limit
+    assert ed.lib.ed_prepare(ctx, None, 5, keep, 100, 0, None, ctypes.byref(out)) == ed.ED_EINVAL
+    assert ed.lib.ed_prepare(ctx, keep, 100, None, 1, 0, None, ctypes.byref(out)) == ed.ED_EINVAL
+    assert ed.lib.ed_prepare(ctx, keep, ed.ED_MAX_LEN, keep, 100, 0, None, ctypes.byref(out)) == ed.ED_EINVAL
+    assert ed.lib.ed_prepare(ctx, keep, 100, keep, 1 << 40, 0, None, ctypes.byref(out)) == ed.ED_EINVAL
+    p = ed.ed_prepare(ctx, A, A)
+    k = ctypes.c_uint64()
+    cnt = ctypes.c_uint64()
+    # a pair used with another context
+    assert ed.lib.ed_distance(other, p, -1, ctypes.byref(k), None) == ed.ED_EINVAL
+    assert ed.lib.ed_align(other, p, ctypes.byref(k), None, 0, ctypes.byref(cnt), None) == ed.ED_EINVAL
+    # ed_align: missing outputs, a capacity without a buffer
+    assert ed.lib.ed_align(ctx, p, None, None, 0, ctypes.byref(cnt), None) == ed.ED_EINVAL
+    assert ed.lib.ed_align(ctx, p, ctypes.byref(k), None, 4, ctypes.byref(cnt), None) == ed.ED_EINVAL
+    # runs outside the strings
+    with pytest.raises(ed.EdError) as ei:
+        ed.ed_debug_check_runs(ctx, p, [(90, 0, 20)])
+    assert ei.value.status == ed.ED_EINVAL
+    with pytest.raises(ed.EdError) as ei:
+        ed.ed_debug_check_runs(ctx, p, [(-1, 0, 5)])
+    assert ei.value.status == ed.ED_EINVAL
+    # a batch mixing engines
+    hctx = make_ctx(engine=ed.ENGINE_HASH)
+    q = ed.ed_prepare(hctx, A, A)
+    arr = (ctypes.c_void_p * 2)(p.value, q.value)
+    kout = (ctypes.c_uint64 * 2)()
+    st = (ctypes.c_int32 * 2)()
+    assert ed.lib.ed_batch(ctx, arr, 2, -1, kout, st, None) == ed.ED_EINVAL
+    ed.ed_release(q)
+    ed.ed_release(p)
