@@ -8,7 +8,7 @@ device memory (torch uint8 tensors) when the timed region starts.
 
     value = 4e8 characters / (seconds per step)
 
-Prints one JSON line.  With --gpus N > 1 it exits: this build measures one GPU.
+Prints one JSON line.  With --gpus N > 1 it exits: the benchmark measures one GPU.
 """
 import argparse
 import json
