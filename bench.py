@@ -66,6 +66,20 @@ def paper_context(ks, n):
             "note": "the paper's numbers on its machine and alphabet; not this workload"}
 
 
+def host_cpu():
+    """Model name and logical CPU count of the host (for the CPU baselines)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
+
+
 def stored_oracle():
     """Oracle distances of the workloads (tests/golden/fullsize.json), if present."""
     try:
@@ -75,7 +89,7 @@ def stored_oracle():
         return None
 
 
-def batch_leg(ed, ctx, count=4096, seed=0):
+def batch_leg(ed, ctx, count=4096, seed=0, cpu_sample=0):
     """Batched workload: `count` pairs, n = floor(10^U) with U ~ U[3, 6], alphabet
     {0,1,2,3}, k ~ U{0..floor(0.01 n)} planted edits.  One ed_batch launch against
     a loop of one ed_distance launch per pair, on the same prepared pairs."""
@@ -111,8 +125,25 @@ def batch_leg(ed, ctx, count=4096, seed=0):
             raise SystemExit("batch distances differ from the stored oracle values")
     for p in pairs:
         ed.ed_release(p)
+    cpu = None
+    if cpu_sample:
+        # the oracle on the first `cpu_sample` pairs (by default all), one pair per host thread
+        import oracle
+        from concurrent.futures import ThreadPoolExecutor
+        log("batch leg: oracle on %d pairs" % cpu_sample)
+        sample = [synth.single_pair(nn, kk, ps)[:2] for nn, kk, ps in specs[:cpu_sample]]
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(os.cpu_count() or 1) as ex:
+            kc = list(ex.map(lambda ab: oracle.lv_omp(ab[0], ab[1], -1, 1), sample))
+        tcpu = time.perf_counter() - t0
+        if kc != list(kb[:cpu_sample]):
+            raise SystemExit("batch: oracle and GPU distances differ")
+        cpu = {"pairs_per_s": cpu_sample / tcpu, "cores": os.cpu_count(), "kind": "oracle",
+               "sample": "oracle lv_omp, one thread per pair, on the first %d pairs of the batch, %.1f s"
+                         % (cpu_sample, tcpu)}
     return {"workload": "%d pairs, n log-uniform [1e3, 1e6], alphabet {0,1,2,3}, k uniform "
                         "[0, 0.01 n], seed %d" % (count, seed),
+            "cpu_baseline": cpu,
             "pairs": count, "chars_A": chars, "sum_k": int(sum(kb)),
             "batched_pairs_per_s": count / tb, "batched_s": tb,
             "untuned_batched_pairs_per_s": count / tb0,
@@ -603,7 +634,7 @@ def main():
 
     batch = None
     if not args.no_batch:
-        batch = batch_leg(ed, ctxs["direct"])
+        batch = batch_leg(ed, ctxs["direct"], cpu_sample=0 if args.no_cpu else 4096)
     lcp = None
     if not args.no_lcp:
         log("lcp leg: one LCP of 1e9 characters on the grid tier")
@@ -619,16 +650,20 @@ def main():
     if not args.no_cpu:
         import oracle
         log("cpu baseline (oracle lv_omp) on the same %d pairs" % len(ks))
-        t1 = time.perf_counter()
-        for i, (A, B, _) in enumerate(host):
-            kc = oracle.lv_omp(A, B)
-            if kc != last[i][0]:
-                raise SystemExit("GPU %d != oracle %d at k=%d" % (last[i][0], kc, ks[i]))
-        tc = time.perf_counter() - t1
+        runs = []
+        for rep in range(3):
+            t1 = time.perf_counter()
+            for i, (A, B, _) in enumerate(host):
+                kc = oracle.lv_omp(A, B)
+                if kc != last[i][0]:
+                    raise SystemExit("GPU %d != oracle %d at k=%d" % (last[i][0], kc, ks[i]))
+            runs.append(time.perf_counter() - t1)
+        tc = sorted(runs)[1]
         cpu = {"value": n * len(ks) / tc, "unit": "chars/s", "cores": oracle.omp_max_threads(),
                "kind": "oracle",
                "sample": "oracle lv_omp (OpenMP Landau-Vishkin, 8-byte word LCP) on the same %d "
-                         "pairs, once, %.1f s" % (len(ks), tc)}
+                         "pairs, median of 3 runs, %.1f s each" % (len(ks), tc),
+               "host": host_cpu()}
         # the literal sequential Landau-Vishkin (character-by-character LCP), one thread:
         # the 10,000-character pair with 100 planted edits, and the n = 1e8 pairs with k <= 1e3
         naive = {}
