@@ -298,8 +298,18 @@ __device__ __forceinline__ uint64_t get_hash(const SView& S, gword* T, const Has
     const int32_t e = p & ((1 << q.log2b) - 1);
     uint64_t h = T[j];
     if (!e) return h;
-    if (q.log2b == 5 && S.bpc == 2)
-        return mp_mul(mp_add(mp_mul(h, q.r32), block32_masked_hash(S, q, j, e)), q.rinv[32 - e]);
+    if (q.log2b == 5) {
+        if (S.bpc == 2)
+            return mp_mul(mp_add(mp_mul(h, q.r32), block32_masked_hash(S, q, j, e)), q.rinv[32 - e]);
+        // 8-bit: past the middle of the block (and when the next entry exists),
+        // the shorter suffix: H = (T[j+1] - h(S[p .. 32(j+1)))) r^(e-32)
+        if (e > 16 && 32 * (j + 1) <= S.len) {
+            uint64_t hs = 0;
+            for (int32_t pos = p; pos < 32 * (j + 1); ++pos)
+                hs = mp_add(mp_mul(hs, q.h.r), (S.w[pos >> 3] >> ((pos & 7) * 8)) & 0xFFu);
+            return mp_mul(mp_sub(T[j + 1], hs), q.rinv[32 - e]);
+        }
+    }
     return mp_add(mp_mul(h, q.pow0[e]), partial_hash(S, q, j << q.log2b, e));
 }
 
