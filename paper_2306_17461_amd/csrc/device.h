@@ -301,12 +301,22 @@ __device__ __forceinline__ uint64_t get_hash(const SView& S, gword* T, const Has
     if (q.log2b == 5) {
         if (S.bpc == 2)
             return mp_mul(mp_add(mp_mul(h, q.r32), block32_masked_hash(S, q, j, e)), q.rinv[32 - e]);
-        // 8-bit: past the middle of the block (and when the next entry exists),
-        // the shorter suffix: H = (T[j+1] - h(S[p .. 32(j+1)))) r^(e-32)
-        if (e > 16 && 32 * (j + 1) <= S.len) {
+        // 8-bit: the block's two words of the shorter side are loaded together
+        // and at most 16 characters are folded from registers: the prefix when
+        // e <= 16, else (when the next entry exists) the suffix, with
+        // H = (T[j+1] - h(S[p .. 32(j+1)))) r^(e-32)
+        if (e <= 16) {
+            const uint64_t w0 = S.w[4 * j], w1 = S.w[4 * j + 1];
+            uint64_t hp = 0;
+            for (int c = 0; c < e; ++c)
+                hp = mp_add(mp_mul(hp, q.h.r), ((c < 8 ? w0 >> (8 * c) : w1 >> (8 * (c - 8))) & 0xFFu));
+            return mp_add(mp_mul(h, q.pow0[e]), hp);
+        }
+        if (32 * (j + 1) <= S.len) {
+            const uint64_t w2 = S.w[4 * j + 2], w3 = S.w[4 * j + 3];
             uint64_t hs = 0;
-            for (int32_t pos = p; pos < 32 * (j + 1); ++pos)
-                hs = mp_add(mp_mul(hs, q.h.r), (S.w[pos >> 3] >> ((pos & 7) * 8)) & 0xFFu);
+            for (int c = e; c < 32; ++c)
+                hs = mp_add(mp_mul(hs, q.h.r), ((c < 24 ? w2 >> (8 * (c - 16)) : w3 >> (8 * (c - 24))) & 0xFFu));
             return mp_mul(mp_sub(T[j + 1], hs), q.rinv[32 - e]);
         }
     }

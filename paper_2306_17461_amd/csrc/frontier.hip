@@ -52,6 +52,7 @@ struct RoundShared {
     int32_t jl[2 * kJobHalf];
     int32_t jcount[2];  // monotonic job counters, one per round parity
     int32_t wmin;       // workgroup-tier reduction slot
+    int32_t hres;       // hash engine: result of wavefront 0's search for the workgroup
     int32_t flag;
     int32_t pair;
     long long task;
@@ -138,6 +139,40 @@ __device__ __forceinline__ int32_t lcp_wg_direct(const SView& A, const SView& B,
     return lim;
 }
 
+// Hash engine, workgroup tier: direct steps of the workgroup first (4 words
+// per thread, then W), then, for an LCP that runs past them, the
+// wavefront-parallel hash search by wavefront 0.  A direct step costs about 5
+// us here; the search, several rounds of dependent probes, about 9 us on 2-bit
+// strings (the masked block hash) and 30 us on 8-bit ones.  Hence one step at
+// 2 bits (131072 characters) and kWgHashSteps8 at 8 bits (32768 + 3 x 65536).
+constexpr int kWgHashSteps8 = 4;
+template <int W>
+__device__ __forceinline__ int32_t lcp_wg_hash(const Engine& en, int32_t x, int32_t y, int32_t lim, int32_t l,
+                                               RoundShared& RS, Cnt& cnt) {
+    constexpr int32_t nthr = kFrontierThreads;
+    if (l < lim) {
+        const int32_t m = wg_step<4>(en.A, en.B, x, y, lim, l, RS.wmin);
+        if (m != INT_MAX) return m < lim ? m : lim;
+        l += (4 * nthr) << en.A.lcpw;
+    }
+    // (the many-pair kernel, at its register limit, takes the first step only)
+    const int steps = (W == kWgWords && en.A.bpc == 8) ? kWgHashSteps8 : 1;
+    for (int st = 1; st < steps && l < lim; ++st) {
+        const int32_t m = wg_step<W>(en.A, en.B, x, y, lim, l, RS.wmin);
+        if (m != INT_MAX) return m < lim ? m : lim;
+        l += (W * nthr) << en.A.lcpw;
+    }
+    if (l >= lim) return lim;
+    if ((threadIdx.x >> 6) == 0) {
+        const int32_t r = lcp_wave_hash(en.A, en.B, en.TA, en.TB, en.q, x, y, lim, l, cnt);
+        if (threadIdx.x == 0) RS.hres = r;
+    }
+    __syncthreads();
+    const int32_t r = RS.hres;
+    __syncthreads();  // hres is written again by the next job
+    return r;
+}
+
 // Tiers (2)/(3) for one slot of diagonals of a wavefront: every lane with a
 // pending LCP is extended in turn by the whole wavefront.  Arguments are the
 // calling lane's own values; `l` and `queued` are updated in that lane.
@@ -155,26 +190,23 @@ __device__ __forceinline__ void wave_extend(const Engine& en, bool pend, int32_t
         int32_t r = lcp_wave_steps(en.A, en.B, jx, jy, jlim, jl, kWaveSteps, done);
         if (lane == 0) atomicAdd(&cnt.sh->wave_lcps, 1ull);
         if (!done) {
-            if (en.kind == 1) {
-                r = lcp_wave_hash(en.A, en.B, en.TA, en.TB, en.q, jx, jy, jlim, r, cnt);
-            } else {
-                int32_t s = 0;
-                if (lane == 0) s = atomicAdd(&RS.jcount[par], 1) - jstart;
-                s = shfl_i32(s, 0);
-                if (s < kJobHalf) {
-                    if (lane == src) {
-                        RS.ji[half + s] = i;
-                        RS.jx[half + s] = jx;
-                        RS.jy[half + s] = jy;
-                        RS.jlim[half + s] = jlim;
-                        RS.jl[half + s] = r;
-                        queued = true;
-                    }
-                    continue;
+            // the workgroup tier takes it after the round's barrier
+            int32_t s = 0;
+            if (lane == 0) s = atomicAdd(&RS.jcount[par], 1) - jstart;
+            s = shfl_i32(s, 0);
+            if (s < kJobHalf) {
+                if (lane == src) {
+                    RS.ji[half + s] = i;
+                    RS.jx[half + s] = jx;
+                    RS.jy[half + s] = jy;
+                    RS.jlim[half + s] = jlim;
+                    RS.jl[half + s] = r;
+                    queued = true;
                 }
-                // queue full: the wavefront finishes it
-                r = lcp_wave_direct(en.A, en.B, jx, jy, jlim, r);
+                continue;
             }
+            // queue full: the wavefront finishes it
+            r = lcp_wave_direct(en.A, en.B, jx, jy, jlim, r);
         }
         if (lane == src) l = r;
     }
@@ -354,15 +386,16 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
     }
     if (found) RS.flag = 1;
     __syncthreads();
-    // workgroup tier for the queued LCPs of this round (direct engine)
+    // workgroup tier for the queued LCPs of this round
     const int32_t jend = RS.jcount[par];
     const int32_t nj = imin(jend - jstart, kJobHalf);
     jc.start[par] = jend;
-    if (en.kind == 0 && nj > 0) {  // only the direct engine queues LCPs
+    if (nj > 0) {
         for (int j = 0; j < nj; ++j) {
             const int32_t jx = RS.jx[half + j];
             const int32_t jy = RS.jy[half + j], jlim = RS.jlim[half + j], jl = RS.jl[half + j];
-            const int32_t r = lcp_wg_direct<WGW>(en.A, en.B, jx, jy, jlim, jl, RS.wmin);
+            const int32_t r = en.kind == 0 ? lcp_wg_direct<WGW>(en.A, en.B, jx, jy, jlim, jl, RS.wmin)
+                                           : lcp_wg_hash<WGW>(en, jx, jy, jlim, jl, RS, cnt);
             if (tid == 0) {
                 const int32_t i = RS.ji[half + j];
                 const int32_t f = jx + r;

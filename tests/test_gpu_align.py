@@ -200,11 +200,12 @@ def test_weak_hash_collisions_are_caught(ed, make_ctx, orc):
     # (ED = 2); the weak hash sees equal prefixes past the swap, so the plain
     # hash distance comes out too small (one-sided, never too large).  The check
     # of ed_align must reject it, and ED_FLAG_CERTIFY must answer the exact 2.
-    # (the swap lies past the first 16384 characters, which the lane and
-    # wavefront tiers compare directly before the hash search takes over)
+    # (the swap lies past the first 16384 + 131072 + 3 x 262144 characters,
+    # which the lane, wavefront and workgroup tiers compare directly before the
+    # hash search)
     d4 = synth.CharDist("uniform", 4)
-    A = synth.random_string(100000, d4, 61)
-    pos = next(i for i in range(50000, 100000) if A[i] != A[i + 1])
+    A = synth.random_string(3000000, d4, 61)
+    pos = next(i for i in range(1500000, 3000000) if A[i] != A[i + 1])
     B = A.copy()
     B[pos], B[pos + 1] = A[pos + 1], A[pos]
     assert orc.lv_omp(A, B, -1, 1) == 2
