@@ -205,14 +205,6 @@ int ed::ctx_set_hash(ed_ctx* c, uint64_t r) {
         a = hmul(a, a);
     }
     for (int l = 0; l < 64; ++l) rt[kRtabR8lane + l] = hpow(R, 8ull * (l + 1));
-    // byte t of r^(31 - 4i - j) at byte j of dword 8t + i
-    uint32_t* W = reinterpret_cast<uint32_t*>(rt + kRtabDot8);
-    for (int t = 0; t < 8; ++t)
-        for (int i = 0; i < 8; ++i) {
-            uint32_t w = 0;
-            for (int j = 0; j < 4; ++j) w |= static_cast<uint32_t>((p0[31 - 4 * i - j] >> (8 * t)) & 0xFFu) << (8 * j);
-            W[8 * t + i] = w;
-        }
     const uint64_t rinv = hpow(r, kP - 2);
     a = 1;
     for (int d = 0; d < 33; ++d) {

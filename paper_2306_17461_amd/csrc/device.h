@@ -210,7 +210,6 @@ struct HashQ {
     gword* pow0;           // r^a, a < 65536
     gword* pow1;           // r^(65536 a), a < 65536
     gword* rinv;           // r^(-d), d = 0..32
-    const uint32_t* w8;    // byte limbs of the weights of a 32-character block (8-bit strings)
     uint64_t r4;           // r^4
     uint64_t r32;          // r^32
     const uint64_t (*lut32)[256];  // LDS: packed byte k of a 2-bit word, weights r^(31-4k-j)
@@ -252,44 +251,16 @@ __device__ __forceinline__ uint64_t partial_hash(const SView& S, const HashQ& q,
     return h;
 }
 
-// b = 32: the block's characters past e are masked to zero and the whole
-// block is hashed with the weights r^(31-k) (table lookups at 2 bits per
-// character, byte dot products against the weights' byte limbs at 8 bits),
+// b = 32 on 2-bit strings: the block's characters past e are masked to zero
+// and the whole block is hashed with the weights r^(31-k) (8 table lookups),
 // giving M = h(S[32j .. 32j+e)) r^(32-e); then
 // H = T[j] r^e + h(S[32j .. 32j+e)) = (T[j] r^32 + M) r^(e-32).
-__device__ __forceinline__ uint64_t block32_masked_hash8(gword* w8s, const uint32_t* W, int32_t j, int32_t e) {
-    uint32_t d[8];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int32_t keep = e - 8 * u;  // characters of word u inside the prefix
-        uint64_t w = w8s[4 * j + u];
-        w = keep >= 8 ? w : (keep <= 0 ? 0 : w & ((1ull << (8 * keep)) - 1));
-        d[2 * u] = static_cast<uint32_t>(w);
-        d[2 * u + 1] = static_cast<uint32_t>(w >> 32);
-    }
-    uint64_t lo = 0, hi = 0;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        uint32_t sum = 0;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) sum = __builtin_amdgcn_udot4(d[i], W[8 * t + i], sum, false);
-        if (t <= 4)
-            lo += static_cast<uint64_t>(sum) << (8 * t);
-        else
-            hi += ((static_cast<uint64_t>(sum) << (8 * t)) & kP) + (static_cast<uint64_t>(sum) >> (61 - 8 * t));
-    }
-    return mp_fold(lo + hi);
-}
-
 __device__ __forceinline__ uint64_t block32_masked_hash(const SView& S, const HashQ& q, int32_t j, int32_t e) {
-    if (S.bpc == 2) {
-        const uint64_t w = S.w[j] & ((1ull << (2 * e)) - 1);
-        uint64_t s = 0;
+    const uint64_t w = S.w[j] & ((1ull << (2 * e)) - 1);
+    uint64_t s = 0;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) s += q.lut32[k][(w >> (8 * k)) & 0xFFu];
-        return mp_fold(s);
-    }
-    return block32_masked_hash8(S.w, q.w8, j, e);
+    for (int k = 0; k < 8; ++k) s += q.lut32[k][(w >> (8 * k)) & 0xFFu];
+    return mp_fold(s);
 }
 
 __device__ __forceinline__ uint64_t get_hash(const SView& S, gword* T, const HashQ& q,

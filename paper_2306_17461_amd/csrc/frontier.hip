@@ -478,7 +478,6 @@ __device__ __forceinline__ Engine make_engine(const PairDev& p, const HashDev& h
         en.q.r4 = mp_mul(mp_mul(en.q.h.r, en.q.h.r), mp_mul(en.q.h.r, en.q.h.r));
         en.q.r32 = uni(h.pow0[32]);
         en.q.rinv = uni((gword*)(h.rtab + kRtabRinv32));
-        en.q.w8 = reinterpret_cast<const uint32_t*>(uni(reinterpret_cast<uint64_t>(h.rtab + kRtabDot8)));
         en.q.lut32 = lut32;
         en.q.log2b = uni(p.log2b);
     } else {
@@ -488,7 +487,6 @@ __device__ __forceinline__ Engine make_engine(const PairDev& p, const HashDev& h
         en.q.pow0 = en.q.pow1 = nullptr;
         en.q.r4 = en.q.r32 = 0;
         en.q.rinv = nullptr;
-        en.q.w8 = nullptr;
         en.q.lut32 = nullptr;
         en.q.log2b = 0;
     }

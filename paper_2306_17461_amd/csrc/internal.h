@@ -185,9 +185,7 @@ struct PrepParams {
 //   r^p, p = 0..64 | r^(64k), k = 0..256 | R^d, d = 0..64 |
 //   lut32[k][v] = sum_j c_j r^(31-4k-j), c_j = 2-bit code j of byte v (k = 0..7) |
 //   lut8[k][v] = v r^(7-k) (k = 0..7) | r^(-256 d), d = 0..64 |
-//   R^(8 * 2^j), j = 0..9 | R^(8 (l + 1)), l = 0..63 |
-//   byte t of the weights r^(31-4i-j), j = 0..3, packed in dword 8t + i (t, i = 0..7; two per entry) |
-//   r^(-d), d = 0..32
+//   R^(8 * 2^j), j = 0..9 | R^(8 (l + 1)), l = 0..63 | r^(-d), d = 0..32
 constexpr int kRtabRseg = 65;
 constexpr int kRtabR = kRtabRseg + 257;
 constexpr int kRtabLut32 = kRtabR + 65;
@@ -195,8 +193,7 @@ constexpr int kRtabLut8 = kRtabLut32 + 8 * 256;
 constexpr int kRtabRinv256 = kRtabLut8 + 8 * 256;
 constexpr int kRtabR8pow2 = kRtabRinv256 + 65;
 constexpr int kRtabR8lane = kRtabR8pow2 + 10;
-constexpr int kRtabDot8 = kRtabR8lane + 64;
-constexpr int kRtabRinv32 = kRtabDot8 + 32;
+constexpr int kRtabRinv32 = kRtabR8lane + 64;
 constexpr int kRtabEntries = kRtabRinv32 + 33;
 
 struct LcpQueryParams {
@@ -255,6 +252,5 @@ hipError_t launch_lcp_queries(const LcpQueryParams& qp, hipStream_t s);
 hipError_t launch_lcp_grid(const LcpQueryParams& qp, int grid, hipStream_t s);
 hipError_t launch_lcp_grid_finish(const LcpQueryParams& qp, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
-hipError_t launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t s);
 
 }  // namespace ed

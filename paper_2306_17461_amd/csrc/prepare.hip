@@ -485,12 +485,6 @@ __global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
         p[i] = v;
 }
 
-__global__ void fill_u32_kernel(unsigned int* p, int64_t n, unsigned int v) {
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-        p[i] = v;
-}
-
 hipError_t launch_prep_clear(const PrepParams& pp, hipStream_t s) {
     const int blocks = (pp.total_tiles + 255) / 256 + 1;
     hipLaunchKernelGGL(prep_clear_kernel, dim3(blocks), dim3(256), 0, s, pp);
@@ -530,14 +524,6 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
     int64_t blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(fill_i32_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, p, n, v);
-    return hipGetLastError();
-}
-
-hipError_t launch_fill_u32(unsigned int* p, int64_t n, unsigned int v, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    int64_t blocks = (n + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(fill_u32_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 
