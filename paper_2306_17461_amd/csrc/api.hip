@@ -57,6 +57,7 @@ static uint64_t hadd(uint64_t a, uint64_t b) {
     return s >= kP ? s - kP : s;
 }
 
+static uint64_t hsub(uint64_t a, uint64_t b) { return a >= b ? a - b : a + kP - b; }
 static uint64_t hpow(uint64_t r, uint64_t e) {
     uint64_t acc = 1, b = r;
     while (e) {
@@ -205,12 +206,39 @@ int ed::ctx_set_hash(ed_ctx* c, uint64_t r) {
         a = hmul(a, a);
     }
     for (int l = 0; l < 64; ++l) rt[kRtabR8lane + l] = hpow(R, 8ull * (l + 1));
+    for (int d = 0; d < 64; ++d) rt[kRtabRChunk + d] = hpow(R, 2048ull * d);
     const uint64_t rinv = hpow(r, kP - 2);
     a = 1;
     for (int d = 0; d < 33; ++d) {
         rt[kRtabRinv32 + d] = a;
         a = hmul(a, rinv);
     }
+    // Block hashes of 8-bit strings as int8 matrix products (prepare.hip):
+    // each weight r^(31 - j) written exactly as 8 signed base-256 digits in
+    // [-128, 127]; lane l = 16 g + i holds in byte e of its A operand digit
+    // t = i mod 8 of the weight of character 16 (g mod 2) + e of a block when
+    // g / 2 = i / 8 (the half of the 64 characters that row i sums), else
+    // zero.  The characters enter as c - 128 and each product row with 2^19
+    // added; the constant undoes both: 128 sum_j r^(31 - j) minus
+    // 2^19 sum_t 256^t.
+    auto digits = [](uint64_t w, int t) {
+        int64_t v = static_cast<int64_t>(w);
+        for (int u = 0;; ++u) {
+            int64_t dg = v & 0xFF;
+            if (dg >= 128) dg -= 256;
+            if (u == t) return static_cast<int8_t>(dg);
+            v = (v - dg) >> 8;
+        }
+    };
+    int8_t* mA = reinterpret_cast<int8_t*>(rt + kRtabMmaA);
+    for (int l = 0; l < 64; ++l) {
+        const int i = l % 16, g = l / 16;
+        for (int e = 0; e < 16; ++e) mA[16 * l + e] = (g / 2 == i / 8) ? digits(p0[31 - 16 * (g % 2) - e], i % 8) : 0;
+    }
+    uint64_t wblk = 0, geo = 0;
+    for (int j = 0; j < 32; ++j) wblk = hadd(wblk, p0[j]);
+    for (int t = 0; t < 8; ++t) geo = hadd(geo, 1ull << (8 * t));
+    rt[kRtabMmaK] = hsub(hmul(128, wblk), hmul(1ull << 19, geo));
     if (!c->d_pow) {
         HIP_TRY(hipMalloc(&c->d_pow, kPowEntries * sizeof(uint64_t)));
     }
@@ -408,12 +436,13 @@ int ed::prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B
         }
     }
     const int32_t total = tiles[0] + tiles[1];
-    // alphabet word | tile hashes | chunk flags | tile prefixes | [lane prefixes]
+    // alphabet word | tile hashes | chunk flags | tile prefixes | [lane prefixes | scan chunk hashes]
     const size_t agg_off = kMiscAlpha + 64;
     const size_t big_off = agg_off + static_cast<size_t>(total) * 8;
     const size_t pre_off = big_off + ((static_cast<size_t>(total) * kTileChunks + 7) & ~size_t(7));
     const size_t lane_off = pre_off + static_cast<size_t>(total) * 8;
-    p->misc = c->pool.get(lane_off + (table ? static_cast<size_t>(total) * 64 * 8 : 0));
+    const size_t tot_off = lane_off + (table ? static_cast<size_t>(total) * 64 * 8 : 0);
+    p->misc = c->pool.get(tot_off + (table ? 2 * 64 * 8 : 0));
     if (!p->misc) {
         pair_free(p);
         delete p;
@@ -461,10 +490,12 @@ int ed::prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B
     pp.log2b = p->log2b;
     pp.force8 = p->force8;
     pp.build_table = table ? 1 : 0;
+    pp.fuse_table = table && p->log2b == 5 ? 1 : 0;
     pp.r = c->r;
     pp.tile_agg = reinterpret_cast<uint64_t*>(misc + agg_off);
     pp.tile_prefix = reinterpret_cast<uint64_t*>(misc + pre_off);
     pp.lane_excl = table ? reinterpret_cast<uint64_t*>(misc + lane_off) : nullptr;
+    pp.chunk_tot = table ? reinterpret_cast<uint64_t*>(misc + tot_off) : nullptr;
     pp.alpha = reinterpret_cast<uint32_t*>(misc + kMiscAlpha);
     pp.packed_any = reinterpret_cast<uint32_t*>(misc + kMiscAlpha + 4);
     pp.chunk_big = reinterpret_cast<uint8_t*>(misc + big_off);

@@ -170,10 +170,13 @@ struct PrepParams {
     int32_t log2b;
     int32_t force8;        // write 8-bit copies of every tile
     int32_t build_table;
+    int32_t fuse_table;    // block size 32: pack_kernel takes the block hashes (the first table pass)
     uint64_t r;            // hash base
     uint64_t* tile_agg;    // total_tiles entries: hash of each tile
     uint64_t* tile_prefix; // total_tiles entries: hash of its string before each tile
+    uint64_t* chunk_tot;   // per chunk of 2048 tiles of each string: its hash (prefix scan)
     uint64_t* lane_excl;   // 64 per tile: hash of the tile's characters before each lane's 256
+                           // (8-bit strings at b = 32: before each run of 512, 32 per tile)
     uint32_t* alpha;       // OR of all characters (atomicOr), zeroed before launch
     uint32_t* packed_any;  // nonzero when some chunk had no character > 3 (zeroed before launch)
     uint8_t* chunk_big;    // per chunk (kTileChunks per tile): 1 if it has a character > 3
@@ -185,7 +188,10 @@ struct PrepParams {
 //   r^p, p = 0..64 | r^(64k), k = 0..256 | R^d, d = 0..64 |
 //   lut32[k][v] = sum_j c_j r^(31-4k-j), c_j = 2-bit code j of byte v (k = 0..7) |
 //   lut8[k][v] = v r^(7-k) (k = 0..7) | r^(-256 d), d = 0..64 |
-//   R^(8 * 2^j), j = 0..9 | R^(8 (l + 1)), l = 0..63 | r^(-d), d = 0..32
+//   R^(8 * 2^j), j = 0..9 | R^(8 (l + 1)), l = 0..63 | r^(-d), d = 0..32 |
+//   per lane l = 0..63 the 16 int8 of its A operand of the block-hash matrix
+//   product (two entries) | the constant term of that product |
+//   R^(2048 d), d = 0..63
 constexpr int kRtabRseg = 65;
 constexpr int kRtabR = kRtabRseg + 257;
 constexpr int kRtabLut32 = kRtabR + 65;
@@ -194,7 +200,10 @@ constexpr int kRtabRinv256 = kRtabLut8 + 8 * 256;
 constexpr int kRtabR8pow2 = kRtabRinv256 + 65;
 constexpr int kRtabR8lane = kRtabR8pow2 + 10;
 constexpr int kRtabRinv32 = kRtabR8lane + 64;
-constexpr int kRtabEntries = kRtabRinv32 + 33;
+constexpr int kRtabMmaA = kRtabRinv32 + 34;  // 16-byte aligned
+constexpr int kRtabMmaK = kRtabMmaA + 128;
+constexpr int kRtabRChunk = kRtabMmaK + 1;
+constexpr int kRtabEntries = kRtabRChunk + 64;
 
 struct LcpQueryParams {
     PairDev p;

@@ -18,6 +18,7 @@ namespace ed {
 namespace {
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 // LDS of the table passes (one of the two lookup tables, by the pair's packing)
 struct TableShared {
@@ -87,29 +88,103 @@ __global__ void prep_clear_kernel(PrepParams P) {
     }
 }
 
-// Streaming pass: wavefront w takes chunks w, w + W, ... (W wavefronts in the
-// grid).  Every load and store instruction covers a contiguous range: lane l
-// holds the 16-character pieces at chunk offsets 1024 k + 16 l (k = 0..3),
-// packs each into 32 bits (the low or high half of a packed word) and writes
-// them at 32-bit index 64 k + l of the chunk.  Chunk slots past the end of a
-// string are written as zeros (padding the last tile).
+// Block hashes of 32 characters on the matrix cores.  h of a block is linear
+// in its characters, h = sum_j c_j r^(31 - j), and with each weight written
+// as 8 signed base-256 digits d[j][t] it is sum_t 256^t X_t with
+// X_t = sum_j c_j d[j][t]: an int8 matrix product of the characters with a
+// digit matrix.  One v_mfma_i32_16x16x64_i8 takes 16 columns of 64
+// characters (two blocks, one per half) against 16 rows (two halves x 8
+// digits; each row's weights are zero outside its half).  Characters enter
+// as c - 128 (signed bytes) and the host constant restores the offsets.
+// Lane l (i = l mod 16, g = l / 16) holds rows 4g .. 4g + 3 of column i:
+// digits 4 (g mod 2) .. + 3 of the block in half g / 2.  The hash does not
+// depend on the packing (a 2-bit code is the character's value), so it is
+// taken from the input bytes.
+//
+// Product p of a tile takes its characters 1024 p .. + 1023 (one load
+// instruction reads them all): column i, half h is block 32 p + 16 h + i,
+// lane l's operand is its characters 16 (g mod 2) .. + 15 (kMmaOff).  The
+// A operand holds at the same byte positions the digits of those
+// characters' weights, so each character meets its own weights whichever
+// way the instruction orders its 64 products.  Products come in pairs: the
+// even-g lanes keep the first product's block, the odd-g lanes the
+// second's, and one exchange between lanes l and l ^ 16 completes every
+// lane's digits.
+__device__ __forceinline__ int32_t mma_off(int lane) {
+    return 32 * (lane & 15) + 512 * (lane >> 5) + 16 * ((lane >> 4) & 1);
+}
+
+// This lane's digits of one product (4 (g mod 2) .. + 3) as a value mod P
+// times 256^(4 (g mod 2)); the offset makes the digit sums non-negative.
+__device__ __forceinline__ uint64_t mma_part(i32x4 x, int32_t rot) {
+    uint64_t z = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) z += static_cast<uint64_t>(static_cast<uint32_t>(x[i] + (1 << 19))) << (8 * i);
+    return ((z << rot) & kP) + (z >> (61 - rot));  // z 2^rot mod P, z < 2^61
+}
+
+// The even-g lane keeps product 0's value, the odd-g lane product 1's; each
+// takes the other half of its digits from lane l ^ 16.
+__device__ __forceinline__ uint64_t mma_pair(uint64_t z0, uint64_t z1, bool even, uint64_t kfix) {
+    const uint64_t own = even ? z0 : z1;
+    const uint64_t send = even ? z1 : z0;
+    return mp_fold(own + __shfl_xor(static_cast<unsigned long long>(send), 16) + kfix);
+}
+
+__device__ __forceinline__ i32x4 as_i32x4(u32x4 v, uint32_t x) {
+    return i32x4{static_cast<int>(v.x ^ x), static_cast<int>(v.y ^ x), static_cast<int>(v.z ^ x),
+                 static_cast<int>(v.w ^ x)};
+}
+
+// Streaming pass: wavefront w takes tiles w, w + W, ... (W wavefronts in the
+// grid), each as 4 chunks of 4096 characters and each chunk as 4 loads of
+// 1024 characters; lane l holds the 16 characters at mma_off(l) of each
+// (every load and store instruction covers a contiguous range).  It packs
+// each piece into 32 bits (a quarter of a packed word) or copies it to the
+// 8-bit words, both stored at the piece's own position.  Chunk slots past
+// the end of a string are written as zeros (padding the last tile).
+//
+// With prefix tables of block size 32 (fuse_table) the pass also takes the
+// block hashes of its tile from the same registers (see above), stores each
+// at T[j + 1] (block j), the slot whose prefix value the emission pass
+// writes over it, and, as the first table pass does for other block sizes,
+// folds the 8 blocks of each lane's 256 characters and stores the in-tile
+// prefix of each lane (lane_excl) and the tile's hash (tile_agg).
 __global__ __launch_bounds__(kPrepThreads) void pack_kernel(PrepParams P) {
+    __shared__ uint64_t stage[kPrepThreads / 64][64 * 9];
     const int lane = threadIdx.x & 63;
     const int32_t wave = __builtin_amdgcn_readfirstlane(static_cast<int32_t>((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
     const int32_t nwaves = static_cast<int32_t>((gridDim.x * blockDim.x) >> 6);
-    const int32_t total = P.total_tiles * kTileChunks;
-    const int32_t split = P.s[1].tile0 * kTileChunks;
+    const int32_t total = P.total_tiles;
+    const int32_t off = mma_off(lane);
+    const int g4 = lane >> 4;
+    const bool even = (g4 & 1) == 0;
+    const bool fuse = P.fuse_table != 0;
+    uint64_t* st = &stage[threadIdx.x >> 6][0];
+    i32x4 ablk{0, 0, 0, 0};
+    uint64_t kblk = 0, r32 = 0, rseg = 0, rinv = 0;
+    if (fuse) {
+        const u32x4 av = reinterpret_cast<const u32x4*>(P.rtab + kRtabMmaA)[lane];
+        ablk = as_i32x4(av, 0u);
+        kblk = P.rtab[kRtabMmaK];
+        r32 = P.rtab[32];
+        rseg = P.rtab[kRtabRseg + 4 * (63 - lane)];  // r^(256 (63 - lane))
+        rinv = P.rtab[kRtabRinv256 + 64 - lane];     // r^(-256 (64 - lane))
+    }
+    const int32_t rot = even ? 0 : 32;
+    // the block this lane ends up with in pair q: 64 q + lam
+    const int32_t lam = (lane & 15) + 16 * (g4 >> 1) + 32 * (g4 & 1);
     uint32_t orr = 0;
     uint32_t packed_any = 0;  // this wavefront packed a chunk (no character > 3)
-    for (int32_t g = wave; g < total; g += nwaves) {
-        const StrSel str(P, g >= split);
-        const int32_t c = g - str.tile0 * kTileChunks;
-        const int32_t cbase = c * kChunkChars;
+    // chunk cc of tile g in v; the next chunk's loads are issued before
+    // this chunk's work
+    auto load = [&](int32_t g, int cc, u32x4 (&v)[4]) {
+        const StrSel str(P, g >= P.s[1].tile0);
+        const int32_t cbase = ((g - str.tile0) * kTileChunks + cc) * kChunkChars;
         const int32_t len = str.len;
-        u32x4 v[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int32_t pos = cbase + k * 1024 + lane * 16;
+            const int32_t pos = cbase + k * 1024 + off;
             if (pos + 16 <= len) {
                 v[k] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(str.raw + pos));
             } else {
@@ -122,25 +197,86 @@ __global__ __launch_bounds__(kPrepThreads) void pack_kernel(PrepParams P) {
                 v[k].w = d[3];
             }
         }
-        uint32_t o = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) o |= v[k].x | v[k].y | v[k].z | v[k].w;
-        orr |= o;
-        const bool big = ballot((o & 0xFCFCFCFCu) != 0u) != 0;
-        if (!big) {
-            uint32_t* dst = reinterpret_cast<uint32_t*>(str.w2 + static_cast<int64_t>(c) * kChunkWords2);
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                dst[k * 64 + lane] = pack_dword(v[k].x) | (pack_dword(v[k].y) << 8) | (pack_dword(v[k].z) << 16) |
-                                     (pack_dword(v[k].w) << 24);
+    };
+    u32x4 v[4], nv[4];
+    int32_t g = wave;
+    int cc = 0;
+    if (g < total) load(g, 0, v);
+    while (g < total) {
+        int32_t ng = g;
+        int ncc = cc + 1;
+        if (ncc == kTileChunks) {
+            ncc = 0;
+            ng += nwaves;
         }
-        if (big || P.force8) {
-            u32x4* dst = reinterpret_cast<u32x4*>(str.w8 + static_cast<int64_t>(c) * kChunkWords8);
+        if (ng < total) load(ng, ncc, nv);
+        const StrSel str(P, g >= P.s[1].tile0);
+        const int32_t t = g - str.tile0;
+        const int32_t len = str.len;
+        {
+            const int32_t c = t * kTileChunks + cc;
+            uint32_t o = 0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) dst[k * 64 + lane] = v[k];
+            for (int k = 0; k < 4; ++k) o |= v[k].x | v[k].y | v[k].z | v[k].w;
+            orr |= o;
+            const bool big = ballot((o & 0xFCFCFCFCu) != 0u) != 0;
+            if (!big) {
+                uint32_t* dst = reinterpret_cast<uint32_t*>(str.w2 + static_cast<int64_t>(c) * kChunkWords2);
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    dst[k * 64 + (off >> 4)] = pack_dword(v[k].x) | (pack_dword(v[k].y) << 8) |
+                                               (pack_dword(v[k].z) << 16) | (pack_dword(v[k].w) << 24);
+            }
+            if (big || P.force8) {
+                u32x4* dst = reinterpret_cast<u32x4*>(str.w8 + static_cast<int64_t>(c) * kChunkWords8);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) dst[k * 64 + (off >> 4)] = v[k];
+            }
+            if (lane == 0) P.chunk_big[str.tile0 * kTileChunks + c] = big ? 1 : 0;
+            packed_any |= big ? 0u : 1u;
+            if (fuse) {
+#pragma unroll
+                for (int k = 0; k < 4; k += 2) {
+                    const i32x4 x0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(ablk, as_i32x4(v[k], 0x80808080u),
+                                                                           i32x4{0, 0, 0, 0}, 0, 0, 0);
+                    const i32x4 x1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(ablk, as_i32x4(v[k + 1], 0x80808080u),
+                                                                           i32x4{0, 0, 0, 0}, 0, 0, 0);
+                    const int32_t blk = 64 * (2 * cc + k / 2) + lam;
+                    st[(blk >> 3) * 9 + (blk & 7)] = mma_pair(mma_part(x0, rot), mma_part(x1, rot), even, kblk);
+                }
+            }
         }
-        if (lane == 0) P.chunk_big[g] = big ? 1 : 0;
-        packed_any |= big ? 0u : 1u;
+        if (fuse && cc == kTileChunks - 1) {
+            const int32_t base = t * (kTileChars / 32) + 1;  // T index of the tile's first block end
+            const int32_t last = len >> 5;
+            __builtin_amdgcn_wave_barrier();
+            // block hashes to T (64 consecutive entries per store); this
+            // lane's 8 blocks folded by Horner's rule
+            uint64_t h = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int32_t i = k * 64 + lane;
+                if (base + i <= last) str.tab[base + i] = st[(i >> 3) * 9 + (i & 7)];
+                h = mp_add(mp_mul(h, r32), st[lane * 9 + k]);
+            }
+            __builtin_amdgcn_wave_barrier();
+            // I(l) = sum over lanes l' <= l of h(l') r^(256 (63 - l')): the
+            // tile's hash is I(63), the hash of its characters before lane l
+            // is I(l - 1) r^(-256 (64 - l))
+            uint64_t x = mp_mul(h, rseg);
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint64_t y = __shfl_up(static_cast<unsigned long long>(x), d);
+                if (lane >= d) x = mp_add(x, y);
+            }
+            const uint64_t ip = __shfl_up(static_cast<unsigned long long>(x), 1);
+            P.lane_excl[static_cast<int64_t>(g) * 64 + lane] = lane == 0 ? 0 : mp_mul(ip, rinv);
+            if (lane == 63) P.tile_agg[g] = x;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = nv[k];
+        g = ng;
+        cc = ncc;
     }
     // one atomic per workgroup at most, and none when the bits are already
     // there: atomics on one address from every wavefront serialise
@@ -170,8 +306,8 @@ __global__ __launch_bounds__(kPrepThreads) void pack_kernel(PrepParams P) {
 //                              lanes under h(S1 S2) = h(S1) r^|S2| + h(S2);
 //                              stores each lane's exclusive prefix within the
 //                              tile (lane_excl) and the tile's hash (tile_agg)
-//   table_scan_kernel          per string: prefix hash before every tile
-//                              (tile_prefix), Horner over tiles with R = r^16384
+//   table_total_kernel,        per string: prefix hash before every tile
+//   table_scan_kernel          (tile_prefix), Horner over tiles with R = r^16384
 //   table_tiles_kernel<true>   per lane: the prefix hash at its first
 //                              character from the two, then Horner over its
 //                              units with T[j] written at every block end
@@ -351,6 +487,72 @@ __device__ __forceinline__ void table_tiles(const PrepParams& P, TableShared& S,
     }
 }
 
+// Block size 32: the emission pass from the block hashes pack_kernel stored
+// in T (the characters are not read again).  Per tile the 512 entries come
+// through the wavefront's staging slots, each lane turns the 8 of its 256
+// characters into prefix values, starting from the prefix hash at its first
+// character, and they go back to T, 64 consecutive entries per store.  The
+// next tile's entries are requested before this tile's arithmetic.  A kernel
+// of its own: few registers and little LDS, so that many wavefronts keep
+// loads in flight.
+__global__ __launch_bounds__(kPrepThreads) void table_emit_kernel(PrepParams P, const uint64_t* rtab) {
+    __shared__ uint64_t stage[kPrepThreads / 64][64 * 9];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int32_t gw = __builtin_amdgcn_readfirstlane(static_cast<int32_t>(blockIdx.x * (kPrepThreads / 64) + (tid >> 6)));
+    const int32_t W = static_cast<int32_t>(gridDim.x * (kPrepThreads / 64));
+    const int32_t total = P.total_tiles;
+    uint64_t* st = &stage[tid >> 6][0];
+    const uint64_t r32 = rtab[32];
+    const uint64_t rlane = rtab[kRtabRseg + 4 * lane];  // r^(256 lane)
+    uint64_t cur[8], nxt[8];
+    uint64_t pre = 0, ex = 0, npre = 0, nex = 0;
+    auto fetch = [&](int32_t g, uint64_t (&e)[8], uint64_t& tp, uint64_t& le) {
+        const StrSel str(P, g >= P.s[1].tile0);
+        const int32_t base = (g - str.tile0) * (kTileChars / 32) + 1;
+        const int32_t last = str.len >> 5;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int32_t i = k * 64 + lane;
+            e[k] = base + i <= last ? str.tab[base + i] : 0;
+        }
+        tp = P.tile_prefix[g];
+        le = P.lane_excl[static_cast<int64_t>(g) * 64 + lane];
+    };
+    if (gw < total) fetch(gw, cur, pre, ex);
+    for (int32_t g = gw; g < total; g += W) {
+        if (g + W < total) fetch(g + W, nxt, npre, nex);
+        const StrSel str(P, g >= P.s[1].tile0);
+        const int32_t t = g - str.tile0;
+        const int32_t base = t * (kTileChars / 32) + 1;
+        const int32_t last = str.len >> 5;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int32_t i = k * 64 + lane;
+            st[(i >> 3) * 9 + (i & 7)] = cur[k];
+        }
+        if (t == 0 && lane == 0) str.tab[0] = 0;
+        __builtin_amdgcn_wave_barrier();
+        uint64_t h = mp_add(mp_mul(pre, rlane), ex);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            h = mp_add(mp_mul(h, r32), st[lane * 9 + q]);
+            st[lane * 9 + q] = h;
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int32_t i = k * 64 + lane;
+            if (base + i <= last) str.tab[base + i] = st[(i >> 3) * 9 + (i & 7)];
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int k = 0; k < 8; ++k) cur[k] = nxt[k];
+        pre = npre;
+        ex = nex;
+    }
+}
+
 template <bool EMIT, bool SMALLB>
 __global__ __launch_bounds__(kPrepThreads) void table_tiles_kernel(PrepParams P, const uint64_t* rtab) {
     __shared__ TableShared S;
@@ -376,75 +578,121 @@ __global__ __launch_bounds__(kPrepThreads) void table_tiles_kernel(PrepParams P,
         table_tiles<EMIT, false, SMALLB>(P, S, gw, W, lane, tid >> 6);
 }
 
-// Pass 2: one workgroup per string.  prefix[u] = h(S[0 .. 16384 u)) from the
-// tile hashes by Horner's rule with R = r^16384, over chunks of 8192 tiles
-// staged in LDS: each thread folds 8 consecutive tiles, the threads' values
-// are combined by inclusive scans under x(l) = x(l - d) R^(8 d) + x(l) within
-// each wavefront and then over the wavefronts (the string's prefix before the
-// chunk enters ahead of the first), and each thread writes the prefixes of
-// its 8 tiles.  The chunk is zero-padded; the padding only follows the last
-// real tile.  The powers of R come from the host.
-__global__ __launch_bounds__(1024) void table_scan_kernel(PrepParams P, const uint64_t* rtab) {
-    constexpr int kPer = 8, kChunk = 1024 * kPer;
-    __shared__ uint64_t buf[kChunk];
-    __shared__ uint64_t wpre[16];  // prefix before each wavefront's tiles
-    __shared__ uint64_t wtot[16];
-    __shared__ uint64_t carry_s;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const StrSel str(P, blockIdx.x == 1);
-    const int32_t tiles = (blockIdx.x == 1 ? P.total_tiles : P.s[1].tile0) - str.tile0;
+// Pass 2: prefix[u] = h(S[0 .. 16384 u)) from the tile hashes, with
+// R = r^16384, in chunks of kScanChunk tiles, one workgroup per chunk of each
+// string (the chunks of string 0 first), in two launches: table_total_kernel
+// folds each chunk to its hash (Horner's rule), table_scan_kernel takes the
+// hash of the string before its chunk from those of the earlier chunks (one
+// term per lane, times R^(kScanChunk d), summed over the wavefront) and scans
+// its chunk with it.  Within a chunk each thread folds 8 consecutive tiles,
+// the threads' values are combined by inclusive scans under
+// x(l) = x(l - d) R^(8 d) + x(l) within each wavefront and then over the
+// wavefronts.  The last chunk is zero-padded: its hash is never used and
+// the padding only follows the last real tile.  Powers of R come from the
+// host.
+constexpr int kScanThreads = 256, kScanPer = 8, kScanChunk = kScanThreads * kScanPer;  // 2048 tiles
+constexpr int kScanWaves = kScanThreads / 64;
+
+struct ScanChunk {
+    int32_t tile0;  // first tile of the string
+    int32_t c;      // chunk within the string
+    int32_t cn;     // real tiles in the chunk
+    int32_t first;  // workgroup of the string's chunk 0
+};
+
+__device__ __forceinline__ ScanChunk scan_chunk(const PrepParams& P) {
+    const int32_t t1 = P.s[1].tile0;
+    const int32_t c0 = (t1 + kScanChunk - 1) / kScanChunk;
+    const bool second = static_cast<int32_t>(blockIdx.x) >= c0;
+    ScanChunk k;
+    k.tile0 = second ? t1 : 0;
+    k.first = second ? c0 : 0;
+    k.c = static_cast<int32_t>(blockIdx.x) - k.first;
+    const int32_t tiles = second ? P.total_tiles - t1 : t1;
+    k.cn = imin32(kScanChunk, tiles - k.c * kScanChunk);
+    return k;
+}
+
+// Horner over the thread's tiles and the inclusive scan over the wavefront.
+__device__ __forceinline__ uint64_t scan_fold(const uint64_t* agg, int32_t cn, const uint64_t* rtab, int tid,
+                                              uint64_t (&a)[kScanPer]) {
     const uint64_t R = rtab[kRtabR + 1];
-    const uint64_t* R8p = rtab + kRtabR8pow2;        // R^(8 * 2^j)
-    const uint64_t Rlane = rtab[kRtabR8lane + lane];  // R^(8 (lane + 1))
-    const uint64_t* agg = P.tile_agg + str.tile0;
-    uint64_t* pre = P.tile_prefix + str.tile0;
-    uint64_t carry = 0;
-    for (int32_t c0 = 0; c0 < tiles; c0 += kChunk) {
-        const int32_t cn = imin32(kChunk, tiles - c0);
-        for (int i = tid; i < kChunk; i += 1024) buf[i] = i < cn ? agg[c0 + i] : 0;
-        __syncthreads();
-        uint64_t a[kPer];
-        uint64_t h = 0;
+    const uint64_t* R8p = rtab + kRtabR8pow2;  // R^(8 * 2^j)
+    const int lane = tid & 63;
+    uint64_t h = 0;
 #pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            a[j] = buf[kPer * tid + j];
-            h = mp_add(mp_mul(h, R), a[j]);
-        }
-#pragma unroll
-        for (int d = 1, j = 0; d < 64; d <<= 1, ++j) {
-            const uint64_t y = __shfl_up(static_cast<unsigned long long>(h), d);
-            if (lane >= d) h = mp_add(mp_mul(y, R8p[j]), h);
-        }
-        if (lane == 63) wtot[wave] = h;
-        __syncthreads();
-        if (wave == 0) {
-            // over the 16 wavefronts (512 tiles each), the carry ahead of the first
-            uint64_t x = lane < 16 ? wtot[lane] : 0;
-            if (lane == 0) x = mp_add(mp_mul(carry, R8p[6]), x);
-#pragma unroll
-            for (int d = 1, j = 6; d < 16; d <<= 1, ++j) {
-                const uint64_t y = __shfl_up(static_cast<unsigned long long>(x), d);
-                if (lane >= d) x = mp_add(mp_mul(y, R8p[j]), x);
-            }
-            const uint64_t xp = __shfl_up(static_cast<unsigned long long>(x), 1);
-            if (lane < 16) wpre[lane] = lane == 0 ? carry : xp;
-        }
-        __syncthreads();
-        const uint64_t pw = wpre[wave];
-        const uint64_t incl = mp_add(mp_mul(pw, Rlane), h);
-        const uint64_t ex = __shfl_up(static_cast<unsigned long long>(incl), 1);
-        uint64_t p = lane == 0 ? pw : ex;
-#pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            buf[kPer * tid + j] = p;
-            p = mp_add(mp_mul(p, R), a[j]);
-        }
-        if (tid == 1023) carry_s = incl;
-        __syncthreads();
-        for (int i = tid; i < cn; i += 1024) pre[c0 + i] = buf[i];
-        carry = carry_s;
-        __syncthreads();
+    for (int j = 0; j < kScanPer; ++j) {
+        const int32_t i = kScanPer * tid + j;
+        a[j] = i < cn ? agg[i] : 0;
+        h = mp_add(mp_mul(h, R), a[j]);
     }
+#pragma unroll
+    for (int d = 1, j = 0; d < 64; d <<= 1, ++j) {
+        const uint64_t y = __shfl_up(static_cast<unsigned long long>(h), d);
+        if (lane >= d) h = mp_add(mp_mul(y, R8p[j]), h);
+    }
+    return h;
+}
+
+__global__ __launch_bounds__(kScanThreads) void table_total_kernel(PrepParams P, const uint64_t* rtab) {
+    __shared__ uint64_t wtot[kScanWaves];
+    const int tid = threadIdx.x;
+    const ScanChunk k = scan_chunk(P);
+    uint64_t a[kScanPer];
+    const uint64_t h = scan_fold(P.tile_agg + k.tile0 + k.c * kScanChunk, k.cn, rtab, tid, a);
+    if ((tid & 63) == 63) wtot[tid >> 6] = h;
+    __syncthreads();
+    if (tid == 0) {
+        const uint64_t Rw = rtab[kRtabR8pow2 + 6];  // R^512: tiles per wavefront
+        uint64_t x = 0;
+        for (int w = 0; w < kScanWaves; ++w) x = mp_add(mp_mul(x, Rw), wtot[w]);
+        P.chunk_tot[blockIdx.x] = x;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void table_scan_kernel(PrepParams P, const uint64_t* rtab) {
+    __shared__ uint64_t buf[kScanChunk];
+    __shared__ uint64_t wtot[kScanWaves];
+    __shared__ uint64_t wpre[kScanWaves];  // prefix before each wavefront's tiles
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const ScanChunk k = scan_chunk(P);
+    const uint64_t R = rtab[kRtabR + 1];
+    const uint64_t* R8p = rtab + kRtabR8pow2;
+    const uint64_t Rlane = rtab[kRtabR8lane + lane];  // R^(8 (lane + 1))
+    uint64_t a[kScanPer];
+    const uint64_t h = scan_fold(P.tile_agg + k.tile0 + k.c * kScanChunk, k.cn, rtab, tid, a);
+    if (lane == 63) wtot[wave] = h;
+    __syncthreads();
+    if (wave == 0) {
+        // the string before the chunk: sum over earlier chunks i of
+        // tot(i) R^(kScanChunk (c - 1 - i)) (at most 64 chunks per string)
+        uint64_t cy = lane < k.c ? mp_mul(P.chunk_tot[k.first + lane], rtab[kRtabRChunk + (k.c - 1 - lane)]) : 0;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) cy = mp_add(cy, __shfl_xor(static_cast<unsigned long long>(cy), d));
+        // over the wavefronts (512 tiles each), the carry ahead of the first
+        uint64_t x = lane < kScanWaves ? wtot[lane] : 0;
+        if (lane == 0) x = mp_add(mp_mul(cy, R8p[6]), x);
+#pragma unroll
+        for (int d = 1, j = 6; d < kScanWaves; d <<= 1, ++j) {
+            const uint64_t y = __shfl_up(static_cast<unsigned long long>(x), d);
+            if (lane >= d) x = mp_add(mp_mul(y, R8p[j]), x);
+        }
+        const uint64_t xp = __shfl_up(static_cast<unsigned long long>(x), 1);
+        if (lane < kScanWaves) wpre[lane] = lane == 0 ? cy : xp;
+    }
+    __syncthreads();
+    const uint64_t pw = wpre[wave];
+    const uint64_t incl = mp_add(mp_mul(pw, Rlane), h);
+    const uint64_t ex = __shfl_up(static_cast<unsigned long long>(incl), 1);
+    uint64_t p = lane == 0 ? pw : ex;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        buf[kScanPer * tid + j] = p;
+        p = mp_add(mp_mul(p, R), a[j]);
+    }
+    __syncthreads();
+    uint64_t* pre = P.tile_prefix + k.tile0 + k.c * kScanChunk;
+    for (int i = tid; i < k.cn; i += kScanThreads) pre[i] = buf[i];
 }
 
 // Second pass for pairs that cannot be packed: 8-bit copy of the chunks the
@@ -501,13 +749,23 @@ hipError_t launch_table(const PrepParams& pp, int grid, hipStream_t s) {
     const int need = (pp.total_tiles + kPrepThreads / 64 - 1) / (kPrepThreads / 64);
     if (grid > need) grid = need;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL((table_tiles_kernel<false, false>), dim3(grid), dim3(kPrepThreads), 0, s, pp, pp.rtab);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(table_scan_kernel, dim3(2), dim3(1024), 0, s, pp, pp.rtab);
+    hipError_t e;
+    if (!pp.fuse_table) {  // else pack_kernel did the first pass
+        hipLaunchKernelGGL((table_tiles_kernel<false, false>), dim3(grid), dim3(kPrepThreads), 0, s, pp, pp.rtab);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int32_t t1 = pp.s[1].tile0;
+    const int chunks = (t1 + kScanChunk - 1) / kScanChunk + (pp.total_tiles - t1 + kScanChunk - 1) / kScanChunk;
+    hipLaunchKernelGGL(table_total_kernel, dim3(chunks), dim3(kScanThreads), 0, s, pp, pp.rtab);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (pp.log2b <= 2)
+    hipLaunchKernelGGL(table_scan_kernel, dim3(chunks), dim3(kScanThreads), 0, s, pp, pp.rtab);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (pp.fuse_table)
+        hipLaunchKernelGGL(table_emit_kernel, dim3(2 * grid), dim3(kPrepThreads), 0, s, pp, pp.rtab);
+    else if (pp.log2b <= 2)
         hipLaunchKernelGGL((table_tiles_kernel<true, true>), dim3(grid), dim3(kPrepThreads), 0, s, pp, pp.rtab);
     else
         hipLaunchKernelGGL((table_tiles_kernel<true, false>), dim3(grid), dim3(kPrepThreads), 0, s, pp, pp.rtab);

@@ -143,7 +143,7 @@ def test_table_bit_exact(ed, make_ctx, orc, b, alpha):
         ed.ed_release(p)
 
 
-@pytest.mark.parametrize("b,sigma", [(32, 4), (4096, 4), (64, 256)])
+@pytest.mark.parametrize("b,sigma", [(32, 4), (4096, 4), (32, 256), (64, 256)])
 def test_table_bit_exact_multi_chunk_scan(ed, make_ctx, orc, b, sigma):
     # more than 8192 tiles of 16384 characters: the scan of the tile hashes
     # runs over several chunks and carries the prefix from one to the next
