@@ -53,6 +53,7 @@ struct RoundShared {
     int32_t jcount[2];  // monotonic job counters, one per round parity
     int32_t wmin;       // workgroup-tier reduction slot
     int32_t hres;       // hash engine: result of wavefront 0's search for the workgroup
+    int32_t hskip;      // hash engine: the last searched LCP outran the direct steps
     int32_t flag;
     int32_t pair;
     long long task;
@@ -78,6 +79,7 @@ __device__ __forceinline__ void rs_init(RoundShared& RS, JobCursor& jc) {
         RS.jcount[0] = 0;
         RS.jcount[1] = 0;
         RS.flag = 0;
+        RS.hskip = 0;
     }
     jc.start[0] = 0;
     jc.start[1] = 0;
@@ -144,32 +146,40 @@ __device__ __forceinline__ int32_t lcp_wg_direct(const SView& A, const SView& B,
 // wavefront-parallel hash search by wavefront 0.  A direct step costs about 5
 // us here; the search, several rounds of dependent probes, about 9 us on 2-bit
 // strings (the masked block hash) and 30 us on 8-bit ones.  Hence one step at
-// 2 bits (131072 characters) and kWgHashSteps8 at 8 bits (32768 + 3 x 65536).
+// 2 bits (131072 characters) and kWgHashSteps8 at 8 bits (32768 + 3 x 65536),
+// and none while the workgroup's last searched LCP ran on past their reach
+// (the LCPs of a pair tend to be alike: about n/k characters on the path).
 constexpr int kWgHashSteps8 = 4;
 template <int W>
 __device__ __forceinline__ int32_t lcp_wg_hash(const Engine& en, int32_t x, int32_t y, int32_t lim, int32_t l,
                                                RoundShared& RS, Cnt& cnt) {
     constexpr int32_t nthr = kFrontierThreads;
-    if (l < lim) {
-        const int32_t m = wg_step<4>(en.A, en.B, x, y, lim, l, RS.wmin);
-        if (m != INT_MAX) return m < lim ? m : lim;
-        l += (4 * nthr) << en.A.lcpw;
-    }
     // (the many-pair kernel, at its register limit, takes the first step only)
     const int steps = (W == kWgWords && en.A.bpc == 8) ? kWgHashSteps8 : 1;
-    for (int st = 1; st < steps && l < lim; ++st) {
-        const int32_t m = wg_step<W>(en.A, en.B, x, y, lim, l, RS.wmin);
-        if (m != INT_MAX) return m < lim ? m : lim;
-        l += (W * nthr) << en.A.lcpw;
+    const int32_t reach = (4 * nthr + (steps - 1) * W * nthr) << en.A.lcpw;
+    const int32_t l0 = l;
+    if (!RS.hskip) {
+        if (l < lim) {
+            const int32_t m = wg_step<4>(en.A, en.B, x, y, lim, l, RS.wmin);
+            if (m != INT_MAX) return m < lim ? m : lim;
+            l += (4 * nthr) << en.A.lcpw;
+        }
+        for (int st = 1; st < steps && l < lim; ++st) {
+            const int32_t m = wg_step<W>(en.A, en.B, x, y, lim, l, RS.wmin);
+            if (m != INT_MAX) return m < lim ? m : lim;
+            l += (W * nthr) << en.A.lcpw;
+        }
+        if (l >= lim) return lim;
     }
-    if (l >= lim) return lim;
     if ((threadIdx.x >> 6) == 0) {
         const int32_t r = lcp_wave_hash(en.A, en.B, en.TA, en.TB, en.q, x, y, lim, l, cnt);
         if (threadIdx.x == 0) RS.hres = r;
     }
     __syncthreads();
     const int32_t r = RS.hres;
-    __syncthreads();  // hres is written again by the next job
+    // every thread read hskip before the barrier above
+    if (threadIdx.x == 0) RS.hskip = r - l0 > reach ? 1 : 0;
+    __syncthreads();  // hres and hskip are written again by the next job
     return r;
 }
 

@@ -136,10 +136,12 @@ __device__ __forceinline__ i32x4 as_i32x4(u32x4 v, uint32_t x) {
                  static_cast<int>(v.w ^ x)};
 }
 
-// Streaming pass: wavefront w takes tiles w, w + W, ... (W wavefronts in the
-// grid), each as 4 chunks of 4096 characters and each chunk as 4 loads of
-// 1024 characters; lane l holds the 16 characters at mma_off(l) of each
-// (every load and store instruction covers a contiguous range).  It packs
+// Streaming pass: wavefront w takes chunks of 4096 characters w, w + W, ...
+// (W wavefronts in the grid), or, when it takes the block hashes too, tiles
+// w, w + W, ... chunk by chunk; a chunk is 4 loads of 1024 characters, lane
+// l holding the 16 characters at 16 l of each, or at mma_off(l) when the
+// block hashes are taken (every load and store instruction covers a
+// contiguous range).  It packs
 // each piece into 32 bits (a quarter of a packed word) or copies it to the
 // 8-bit words, both stored at the piece's own position.  Chunk slots past
 // the end of a string are written as zeros (padding the last tile).
@@ -156,10 +158,11 @@ __global__ __launch_bounds__(kPrepThreads) void pack_kernel(PrepParams P) {
     const int32_t wave = __builtin_amdgcn_readfirstlane(static_cast<int32_t>((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
     const int32_t nwaves = static_cast<int32_t>((gridDim.x * blockDim.x) >> 6);
     const int32_t total = P.total_tiles;
-    const int32_t off = mma_off(lane);
+    const bool fuse = P.fuse_table != 0;
+    // the operands' order only when the block hashes are taken
+    const int32_t off = fuse ? mma_off(lane) : 16 * lane;
     const int g4 = lane >> 4;
     const bool even = (g4 & 1) == 0;
-    const bool fuse = P.fuse_table != 0;
     uint64_t* st = &stage[threadIdx.x >> 6][0];
     i32x4 ablk{0, 0, 0, 0};
     uint64_t kblk = 0, r32 = 0, rseg = 0, rinv = 0;
@@ -176,11 +179,9 @@ __global__ __launch_bounds__(kPrepThreads) void pack_kernel(PrepParams P) {
     const int32_t lam = (lane & 15) + 16 * (g4 >> 1) + 32 * (g4 & 1);
     uint32_t orr = 0;
     uint32_t packed_any = 0;  // this wavefront packed a chunk (no character > 3)
-    // chunk cc of tile g in v; the next chunk's loads are issued before
-    // this chunk's work
-    auto load = [&](int32_t g, int cc, u32x4 (&v)[4]) {
-        const StrSel str(P, g >= P.s[1].tile0);
-        const int32_t cbase = ((g - str.tile0) * kTileChunks + cc) * kChunkChars;
+    // chunk c (of its string) in v
+    auto load = [&](const StrSel& str, int32_t c, u32x4 (&v)[4]) {
+        const int32_t cbase = c * kChunkChars;
         const int32_t len = str.len;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -198,85 +199,103 @@ __global__ __launch_bounds__(kPrepThreads) void pack_kernel(PrepParams P) {
             }
         }
     };
-    u32x4 v[4], nv[4];
-    int32_t g = wave;
-    int cc = 0;
-    if (g < total) load(g, 0, v);
-    while (g < total) {
-        int32_t ng = g;
-        int ncc = cc + 1;
-        if (ncc == kTileChunks) {
-            ncc = 0;
-            ng += nwaves;
+    // alphabet OR, 2-bit words or 8-bit copy, chunk flag
+    auto pack = [&](const StrSel& str, int32_t c, const u32x4 (&v)[4]) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o |= v[k].x | v[k].y | v[k].z | v[k].w;
+        orr |= o;
+        const bool big = ballot((o & 0xFCFCFCFCu) != 0u) != 0;
+        if (!big) {
+            uint32_t* dst = reinterpret_cast<uint32_t*>(str.w2 + static_cast<int64_t>(c) * kChunkWords2);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                dst[k * 64 + (off >> 4)] = pack_dword(v[k].x) | (pack_dword(v[k].y) << 8) | (pack_dword(v[k].z) << 16) |
+                                           (pack_dword(v[k].w) << 24);
         }
-        if (ng < total) load(ng, ncc, nv);
-        const StrSel str(P, g >= P.s[1].tile0);
-        const int32_t t = g - str.tile0;
-        const int32_t len = str.len;
-        {
-            const int32_t c = t * kTileChunks + cc;
-            uint32_t o = 0;
+        if (big || P.force8) {
+            u32x4* dst = reinterpret_cast<u32x4*>(str.w8 + static_cast<int64_t>(c) * kChunkWords8);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) o |= v[k].x | v[k].y | v[k].z | v[k].w;
-            orr |= o;
-            const bool big = ballot((o & 0xFCFCFCFCu) != 0u) != 0;
-            if (!big) {
-                uint32_t* dst = reinterpret_cast<uint32_t*>(str.w2 + static_cast<int64_t>(c) * kChunkWords2);
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    dst[k * 64 + (off >> 4)] = pack_dword(v[k].x) | (pack_dword(v[k].y) << 8) |
-                                               (pack_dword(v[k].z) << 16) | (pack_dword(v[k].w) << 24);
+            for (int k = 0; k < 4; ++k) dst[k * 64 + (off >> 4)] = v[k];
+        }
+        if (lane == 0) P.chunk_big[str.tile0 * kTileChunks + c] = big ? 1 : 0;
+        packed_any |= big ? 0u : 1u;
+    };
+    u32x4 v[4];
+    if (!fuse) {
+        // chunks w, w + W, ... (no state across chunks)
+        const int32_t chunks = total * kTileChunks;
+        for (int32_t gc = wave; gc < chunks; gc += nwaves) {
+            const StrSel str(P, gc >= P.s[1].tile0 * kTileChunks);
+            const int32_t c = gc - str.tile0 * kTileChunks;
+            load(str, c, v);
+            pack(str, c, v);
+        }
+    } else {
+        // tiles w, w + W, ..., chunk by chunk; the next chunk's loads are
+        // issued before this chunk's work
+        u32x4 nv[4];
+        int32_t g = wave;
+        int cc = 0;
+        if (g < total) {
+            const StrSel str(P, g >= P.s[1].tile0);
+            load(str, (g - str.tile0) * kTileChunks, v);
+        }
+        while (g < total) {
+            int32_t ng = g;
+            int ncc = cc + 1;
+            if (ncc == kTileChunks) {
+                ncc = 0;
+                ng += nwaves;
             }
-            if (big || P.force8) {
-                u32x4* dst = reinterpret_cast<u32x4*>(str.w8 + static_cast<int64_t>(c) * kChunkWords8);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) dst[k * 64 + (off >> 4)] = v[k];
+            if (ng < total) {
+                const StrSel nstr(P, ng >= P.s[1].tile0);
+                load(nstr, (ng - nstr.tile0) * kTileChunks + ncc, nv);
             }
-            if (lane == 0) P.chunk_big[str.tile0 * kTileChunks + c] = big ? 1 : 0;
-            packed_any |= big ? 0u : 1u;
-            if (fuse) {
+            const StrSel str(P, g >= P.s[1].tile0);
+            const int32_t t = g - str.tile0;
+            pack(str, t * kTileChunks + cc, v);
 #pragma unroll
-                for (int k = 0; k < 4; k += 2) {
-                    const i32x4 x0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(ablk, as_i32x4(v[k], 0x80808080u),
-                                                                           i32x4{0, 0, 0, 0}, 0, 0, 0);
-                    const i32x4 x1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(ablk, as_i32x4(v[k + 1], 0x80808080u),
-                                                                           i32x4{0, 0, 0, 0}, 0, 0, 0);
-                    const int32_t blk = 64 * (2 * cc + k / 2) + lam;
-                    st[(blk >> 3) * 9 + (blk & 7)] = mma_pair(mma_part(x0, rot), mma_part(x1, rot), even, kblk);
+            for (int k = 0; k < 4; k += 2) {
+                const i32x4 x0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(ablk, as_i32x4(v[k], 0x80808080u),
+                                                                       i32x4{0, 0, 0, 0}, 0, 0, 0);
+                const i32x4 x1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(ablk, as_i32x4(v[k + 1], 0x80808080u),
+                                                                       i32x4{0, 0, 0, 0}, 0, 0, 0);
+                const int32_t blk = 64 * (2 * cc + k / 2) + lam;
+                st[(blk >> 3) * 9 + (blk & 7)] = mma_pair(mma_part(x0, rot), mma_part(x1, rot), even, kblk);
+            }
+            if (cc == kTileChunks - 1) {
+                const int32_t base = t * (kTileChars / 32) + 1;  // T index of the tile's first block end
+                const int32_t last = str.len >> 5;
+                __builtin_amdgcn_wave_barrier();
+                // block hashes to T (64 consecutive entries per store); this
+                // lane's 8 blocks folded by Horner's rule
+                uint64_t h = 0;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int32_t i = k * 64 + lane;
+                    if (base + i <= last) str.tab[base + i] = st[(i >> 3) * 9 + (i & 7)];
+                    h = mp_add(mp_mul(h, r32), st[lane * 9 + k]);
                 }
+                __builtin_amdgcn_wave_barrier();
+                // I(l) = sum over lanes l' <= l of h(l') r^(256 (63 - l')): the
+                // tile's hash is I(63), the hash of its characters before lane
+                // l is I(l - 1) r^(-256 (64 - l))
+                uint64_t x = mp_mul(h, rseg);
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const uint64_t y = __shfl_up(static_cast<unsigned long long>(x), d);
+                    if (lane >= d) x = mp_add(x, y);
+                }
+                const uint64_t ip = __shfl_up(static_cast<unsigned long long>(x), 1);
+                P.lane_excl[static_cast<int64_t>(g) * 64 + lane] = lane == 0 ? 0 : mp_mul(ip, rinv);
+                if (lane == 63) P.tile_agg[g] = x;
             }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = nv[k];
+            g = ng;
+            cc = ncc;
         }
-        if (fuse && cc == kTileChunks - 1) {
-            const int32_t base = t * (kTileChars / 32) + 1;  // T index of the tile's first block end
-            const int32_t last = len >> 5;
-            __builtin_amdgcn_wave_barrier();
-            // block hashes to T (64 consecutive entries per store); this
-            // lane's 8 blocks folded by Horner's rule
-            uint64_t h = 0;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int32_t i = k * 64 + lane;
-                if (base + i <= last) str.tab[base + i] = st[(i >> 3) * 9 + (i & 7)];
-                h = mp_add(mp_mul(h, r32), st[lane * 9 + k]);
-            }
-            __builtin_amdgcn_wave_barrier();
-            // I(l) = sum over lanes l' <= l of h(l') r^(256 (63 - l')): the
-            // tile's hash is I(63), the hash of its characters before lane l
-            // is I(l - 1) r^(-256 (64 - l))
-            uint64_t x = mp_mul(h, rseg);
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const uint64_t y = __shfl_up(static_cast<unsigned long long>(x), d);
-                if (lane >= d) x = mp_add(x, y);
-            }
-            const uint64_t ip = __shfl_up(static_cast<unsigned long long>(x), 1);
-            P.lane_excl[static_cast<int64_t>(g) * 64 + lane] = lane == 0 ? 0 : mp_mul(ip, rinv);
-            if (lane == 63) P.tile_agg[g] = x;
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = nv[k];
-        g = ng;
-        cc = ncc;
     }
     // one atomic per workgroup at most, and none when the bits are already
     // there: atomics on one address from every wavefront serialise
