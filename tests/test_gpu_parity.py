@@ -159,6 +159,30 @@ def test_table_bit_exact_multi_chunk_scan(ed, make_ctx, orc, b, sigma):
     np.testing.assert_array_equal(TA, orc.horner_table(A, b, orc.hash_base(seed)))
 
 
+@pytest.mark.parametrize("b", [32, 64])
+def test_table_and_distance_with_forced_8bit_copy(ed, make_ctx, orc, b):
+    # alphabet {0,1,2,3} kept at 8 bits per character (pack_bits=8): the
+    # block hashes come from the input bytes whatever the packing, and the
+    # tables must equal Horner's rule over the characters either way
+    say("table force8", b)
+    seed = 31 + b
+    ctx = make_ctx(engine=ed.ENGINE_HASH, block=b, hash_seed=seed, pack_bits=8)
+    d4 = synth.CharDist("uniform", 4)
+    for n in [1, 31, 32, 33, 16384 * 3 + 17]:
+        A = synth.random_string(n, d4, n + 7)
+        B, _ = synth.plant_edits(A, max(1, n // 500), d4, n + 8)
+        p = ed.ed_prepare(ctx, A, B)
+        try:
+            assert ed.ed_pair_stats(p)["bits_per_char"] == 8
+            np.testing.assert_array_equal(ed.ed_pair_buffer(ctx, p, 0, ed.BUF_TABLE),
+                                          orc.horner_table(A, b, orc.hash_base(seed)), err_msg="A n=%d" % n)
+            np.testing.assert_array_equal(ed.ed_pair_buffer(ctx, p, 1, ed.BUF_TABLE),
+                                          orc.horner_table(B, b, orc.hash_base(seed)), err_msg="B n=%d" % n)
+            assert ed.ed_distance(ctx, p) == orc.lv_omp(A, B)
+        finally:
+            ed.ed_release(p)
+
+
 # ---------------------------------------------------------------------------
 # LCP engines against the character loop (section 2)
 # ---------------------------------------------------------------------------
