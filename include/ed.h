@@ -214,7 +214,9 @@ typedef struct ed_stats {
     double gpu_ns_lcp_kernel;
     uint64_t wg_lcps;         /* LCPs extended by a whole workgroup (workgroup tier) */
     /* with ED_FLAG_TIMING, hash engine: HIP-event time of the prefix-table
-     * kernels alone (part of gpu_ns_prepare_kernel; 0 for the direct engine) */
+     * kernels that follow the pack kernel (part of gpu_ns_prepare_kernel; at
+     * b = 32 the pack kernel itself takes the block hashes, so this is the
+     * scan and the emission of T; 0 for the direct engine) */
     double gpu_ns_table_kernel;
     /* ED_FLAG_CERTIFY: hash-engine distances whose check failed (then answered
      * by the direct engine) */

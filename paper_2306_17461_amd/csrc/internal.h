@@ -176,7 +176,6 @@ struct PrepParams {
     uint64_t* tile_prefix; // total_tiles entries: hash of its string before each tile
     uint64_t* chunk_tot;   // per chunk of 2048 tiles of each string: its hash (prefix scan)
     uint64_t* lane_excl;   // 64 per tile: hash of the tile's characters before each lane's 256
-                           // (8-bit strings at b = 32: before each run of 512, 32 per tile)
     uint32_t* alpha;       // OR of all characters (atomicOr), zeroed before launch
     uint32_t* packed_any;  // nonzero when some chunk had no character > 3 (zeroed before launch)
     uint8_t* chunk_big;    // per chunk (kTileChunks per tile): 1 if it has a character > 3

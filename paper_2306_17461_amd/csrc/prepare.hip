@@ -1,16 +1,20 @@
 // Prepare a pair: the input bytes of both strings are read once.
-//   pack_kernel   streaming, one wavefront per 4096-character chunk, no LDS:
+//   pack_kernel   streaming, one wavefront per 4096-character chunk:
 //                 alphabet detection (bitwise OR of every character; 2-bit
 //                 packing is possible when the OR is <= 3), 2-bit packing of
 //                 every chunk without a character > 3, and an 8-bit copy of
 //                 every chunk with one (the rest of the copy, when the pair
-//                 cannot be packed, is written by copy8_rest_kernel);
+//                 cannot be packed, is written by copy8_rest_kernel); with
+//                 prefix tables of block size 32 it also takes the block
+//                 hashes of the input bytes on the matrix cores and the first
+//                 table pass;
 //   table_*       (hash engine) prefix table T[j] = h(S[0..jb)) mod 2^61-1
-//                 (sections 3.2 and 3.3, Algorithm 2 "Build") from the packed
-//                 words (or the 8-bit copy): block hashes from LDS lookup
-//                 tables (h is linear in the characters), combined under the
-//                 concatenation h(S1 S2) = h(S1) r^|S2| + h(S2) within each
-//                 tile, across tiles by a separate scan of the tile hashes.
+//                 (sections 3.2 and 3.3, Algorithm 2 "Build"): block hashes
+//                 (matrix products at b = 32, else LDS lookup tables over the
+//                 packed words or the 8-bit copy; h is linear in the
+//                 characters), combined under the concatenation
+//                 h(S1 S2) = h(S1) r^|S2| + h(S2) within each tile, across
+//                 tiles by a separate scan of the tile hashes.
 #include "device.h"
 
 namespace ed {
