@@ -577,6 +577,21 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 6),
                 "traffic": measured_traffic(dom, main_engine, ks, n),
                 "algorithmic_bytes_per_launch": byts, "avg_launch_ms": round(avg_ns / 1e6, 4)}
+    if dom == "frontier_kernel":
+        # the latency floor of a round: its LCP loads take their addresses
+        # from the previous round's row, one dependent access at least
+        lctx = ed.ed_init(0)
+        try:
+            cold = ed.ed_debug_mem_latency(lctx, 1 << 32, 4000)
+            warm = ed.ed_debug_mem_latency(lctx, 1 << 20, 2000, warm=True)
+        finally:
+            ed.ed_shutdown(lctx)
+        big = max(range(len(ks)), key=lambda i: ks[i])
+        us_round = per_k[str(ks[big])]["us_per_round"]
+        roofline["latency_floor"] = {
+            "dependent_access_ns_4GiB_cold": round(cold, 1), "dependent_access_ns_1MiB_warm": round(warm, 1),
+            "k": ks[big], "us_per_round": us_round,
+            "frac_one_cold_access_per_round": round(cold / 1e3 / us_round, 3)}
 
     def prep_roofline(engine, prep_ms, table_ms=None):
         """Prepare kernels (pack, [table]) against the HBM peak: algorithmic

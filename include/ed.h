@@ -275,6 +275,18 @@ int ed_debug_lcp(ed_ctx *ctx, ed_pair *pair, int engine, const int64_t *x, const
 int ed_debug_check_runs(ed_ctx *ctx, ed_pair *pair, const int32_t *x, const int32_t *y, const int32_t *len,
                         uint64_t count, uint32_t *bad, void *hip_stream);
 
+/* Dependent-access latency on this device, for measurement: a cycle of links
+ * one per 128-byte line over a fresh region of region_bytes (a power of two,
+ * 8 KiB .. 256 GiB; allocated and freed by the call), followed by one
+ * wavefront whose every access reads the address of the next (64 chains),
+ * `steps` links each (1 .. 2^24); with warm != 0 the same walk runs once
+ * before the timed one, so a region that fits a cache is read from it.
+ * *ns_per_access = HIP-event time / steps.  A frontier round (Algorithm 1)
+ * needs at least one such access: its LCP loads take their addresses from
+ * the previous round's row.  ED_EINVAL on bad sizes, ED_ENOMEM when the
+ * region cannot be allocated, ED_EDEVICE on a HIP error. */
+int ed_debug_mem_latency(ed_ctx *ctx, uint64_t region_bytes, uint32_t steps, int warm, double *ns_per_access);
+
 /* ---- serving ---------------------------------------------------------------- */
 typedef struct ed_server ed_server;
 typedef struct ed_result {

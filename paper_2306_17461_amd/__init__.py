@@ -98,7 +98,7 @@ EXPORTS = [
     "ed_default_options", "ed_hash_base", "ed_init", "ed_set_options", "ed_get_options",
     "ed_shutdown", "ed_prepare", "ed_release", "ed_distance", "ed_distance_dump", "ed_align", "ed_batch",
     "ed_autotune_batch", "ed_pair_stats", "ed_pair_buffer", "ed_debug_lcp", "ed_debug_check_runs",
-    "ed_serve_open",
+    "ed_debug_mem_latency", "ed_serve_open",
     "ed_serve_submit",
     "ed_serve_poll", "ed_serve_drain", "ed_serve_close", "ed_strerror", "ed_last_error",
 ]
@@ -132,6 +132,7 @@ def _load():
         "ed_pair_buffer": (i32, [vp, vp, i32, i32, vp, u64, P(u64)]),
         "ed_debug_lcp": (i32, [vp, vp, i32, vp, vp, u64, vp, vp]),
         "ed_debug_check_runs": (i32, [vp, vp, vp, vp, vp, u64, P(ctypes.c_uint32), vp]),
+        "ed_debug_mem_latency": (i32, [vp, u64, ctypes.c_uint32, i32, P(ctypes.c_double)]),
         "ed_serve_open": (i32, [vp, u64, ctypes.c_uint32, P(vp)]),
         "ed_serve_submit": (i32, [vp, vp, u64, vp, u64, u64]),
         "ed_serve_poll": (i32, [vp, P(ed_result), ctypes.c_uint32, P(ctypes.c_uint32)]),
@@ -287,6 +288,14 @@ def ed_debug_check_runs(ctx, pair, runs, stream=None):
     _check(lib.ed_debug_check_runs(ctx, pair, x.ctypes.data, y.ctypes.data, ln.ctypes.data, len(r),
                                    ctypes.byref(bad), _stream_handle(stream)), "ed_debug_check_runs")
     return int(bad.value)
+
+
+def ed_debug_mem_latency(ctx, region_bytes, steps, warm=False):
+    """Nanoseconds per dependent global access over a region of region_bytes."""
+    ns = ctypes.c_double()
+    _check(lib.ed_debug_mem_latency(ctx, region_bytes, steps, 1 if warm else 0, ctypes.byref(ns)),
+           "ed_debug_mem_latency")
+    return ns.value
 
 
 def ed_batch(ctx, pairs, k_max=-1, stream=None, check=True):

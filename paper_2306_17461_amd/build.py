@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libed.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["prepare.hip", "frontier.hip", "api.hip", "batch_api.hip", "serve.hip", "align.hip", "align_api.hip"]
+SOURCES = ["prepare.hip", "frontier.hip", "api.hip", "batch_api.hip", "serve.hip", "align.hip", "align_api.hip",
+           "probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -583,3 +583,19 @@ def test_invalid_argument_matrix(ed, make_ctx):
     assert ed.lib.ed_batch(ctx, arr, 2, -1, kout, st, None) == ed.ED_EINVAL
     ed.ed_release(q)
     ed.ed_release(p)
+
+
+# ---------------------------------------------------------------------------
+# dependent-access latency probe (the floor of a frontier round)
+# ---------------------------------------------------------------------------
+def test_dependent_access_latency_probe(ed, make_ctx):
+    say("latency probe")
+    ctx = make_ctx()
+    cached = ed.ed_debug_mem_latency(ctx, 1 << 20, 2000, warm=True)
+    cold = ed.ed_debug_mem_latency(ctx, 1 << 32, 4000, warm=False)
+    print("dependent access: 1 MiB warm %.0f ns, 4 GiB cold %.0f ns" % (cached, cold))
+    assert 20 < cached < cold < 50000
+    for bad in [(3 << 20, 10), (1 << 12, 10), (1 << 20, 0)]:
+        with pytest.raises(ed.EdError) as ei:
+            ed.ed_debug_mem_latency(ctx, *bad)
+        assert ei.value.status == ed.ED_EINVAL
