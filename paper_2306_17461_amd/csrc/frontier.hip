@@ -358,20 +358,13 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
             const uint64_t b1 = (wb[u][1] >> sb) | ((wb[u][2] << 1) << (63 - sb));
             d0[u] = a0 ^ b0;
             d1[u] = a1 ^ b1;
-            if (go) {
-                if (d0[u]) {
-                    l[u] = imin((ctz64(d0[u]) >> en.A.lbpc), lim[u]);
-                } else if (lim[u] <= cpw) {
-                    l[u] = lim[u];
-                } else if (d1[u]) {
-                    l[u] = imin(cpw + (ctz64(d1[u]) >> en.A.lbpc), lim[u]);
-                } else if (lim[u] <= 2 * cpw) {
-                    l[u] = lim[u];
-                } else {
-                    l[u] = 2 * cpw;
-                    pend[u] = true;
-                }
-            }
+            // the first mismatch in each word (cpw when none), without
+            // branches: every lane takes the same instructions
+            const int32_t m0 = d0[u] ? (ctz64(d0[u]) >> en.A.lbpc) : cpw;
+            const int32_t m1 = d1[u] ? (ctz64(d1[u]) >> en.A.lbpc) : cpw;
+            const int32_t ll = m0 < cpw ? m0 : cpw + m1;  // <= 2 cpw
+            l[u] = go ? imin(ll, lim[u]) : 0;
+            pend[u] = go && ll == 2 * cpw && lim[u] > 2 * cpw;
         }
         // (2)/(3) the wavefront extends its lanes' long LCPs
 #pragma unroll
