@@ -309,6 +309,12 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
             slot[u] = base + u * nthr + wbase < i_end;
             const int32_t i = base + u * nthr + tid;
             iv[u] = i;
+            if (!slot[u]) {  // no diagonal of this wavefront (a uniform branch)
+                act[u] = val[u] = false;
+                c[u] = -1;
+                lim[u] = 0;
+                continue;
+            }
             act[u] = i < i_end;
             const bool inr = act[u] && i >= lo && i <= hi;
             int32_t cc = -1;
@@ -374,7 +380,7 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-            if (queued[u]) continue;
+            if (!slot[u] || queued[u]) continue;
             const int32_t f = val[u] ? c[u] + l[u] : kNone;
             if (act[u]) {
                 cur[iv[u] + ofs] = f;
