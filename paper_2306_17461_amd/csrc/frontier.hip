@@ -27,9 +27,9 @@
 //
 // Inside a round every thread takes up to kU diagonals and issues the first
 // word loads of all of them before comparing (one memory latency per pass).
-// LCPs that run past the lane tier go to a job list in LDS: the direct engine
-// extends each job with the whole workgroup (4 words per thread per step),
-// the hash engine gives each job to one wavefront.
+// LCPs that run past the lane and wavefront tiers go to a job list in LDS
+// and the whole workgroup extends each job (4 words per thread per step);
+// the hash engine follows its direct steps with a wavefront's hash search.
 #include <climits>
 
 #include "device.h"
@@ -272,8 +272,9 @@ __device__ __forceinline__ void grid_segments(const SView& A, const SView& B, in
 // [dlo, dhi] are also copied to dump_row[i + t].  Returns true in the thread
 // that found the target.
 //
-// Tiers of the slide: (1) each lane compares the first two words of each of
-// its diagonals, all loads in flight together; (2) a lane whose LCP runs on
+// Tiers of the slide: (1) each lane compares the first cpw characters of each
+// of its diagonals (one 64-bit window from two words), all loads in flight
+// together; (2) a lane whose LCP runs on
 // is extended by its own wavefront, kWaveSteps steps of 4 words per lane;
 // (3) the hash engine then finishes with its wavefront-parallel search, the
 // direct engine queues the LCP and the whole workgroup extends it after the
@@ -302,8 +303,7 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
     for (int32_t base = i_begin; base < i_end; base += nthr * kU) {
         int32_t iv[kU], c[kU], l[kU], lim[kU];
         bool val[kU], act[kU], pend[kU], queued[kU], slot[kU];
-        uint64_t d0[kU], d1[kU];
-        uint64_t wa[kU][3], wb[kU][3];
+        uint64_t wa[kU][2], wb[kU][2];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             slot[u] = base + u * nthr + wbase < i_end;
@@ -331,9 +331,9 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
             val[u] = inr && cc >= 0;
             lim[u] = val[u] ? imin(n - cc, m - (cc - i)) : 0;
         }
-        // (1) three words of A and of B per diagonal (the first 2 cpw
-        // characters from any offset), issued for every slot before any use:
-        // one memory latency per pass.  Idle lanes read word 0 (always there).
+        // (1) two words of A and of B per diagonal (the first cpw characters
+        // from any offset), issued for every slot before any use: one memory
+        // latency per pass.  Idle lanes read word 0 (always there).
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             if (!slot[u]) continue;
@@ -342,35 +342,27 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
             const int32_t qb = go ? (c[u] - iv[u]) >> en.A.lcpw : 0;
             wa[u][0] = en.A.w[qa];
             wa[u][1] = en.A.w[qa + 1];
-            wa[u][2] = en.A.w[qa + 2];
             wb[u][0] = en.B.w[qb];
             wb[u][1] = en.B.w[qb + 1];
-            wb[u][2] = en.B.w[qb + 2];
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             l[u] = 0;
             pend[u] = false;
             queued[u] = false;
-            d0[u] = d1[u] = 0;
             if (!slot[u]) continue;
             const bool go = lim[u] > 0;
             const uint32_t sa = go ? static_cast<uint32_t>(c[u] & qmask) << en.A.lbpc : 0;
             const uint32_t sb = go ? static_cast<uint32_t>((c[u] - iv[u]) & qmask) << en.A.lbpc : 0;
             // (hi << 1) << (63 - sh) equals hi << (64 - sh) and is 0 for sh = 0
             const uint64_t a0 = (wa[u][0] >> sa) | ((wa[u][1] << 1) << (63 - sa));
-            const uint64_t a1 = (wa[u][1] >> sa) | ((wa[u][2] << 1) << (63 - sa));
             const uint64_t b0 = (wb[u][0] >> sb) | ((wb[u][1] << 1) << (63 - sb));
-            const uint64_t b1 = (wb[u][1] >> sb) | ((wb[u][2] << 1) << (63 - sb));
-            d0[u] = a0 ^ b0;
-            d1[u] = a1 ^ b1;
-            // the first mismatch in each word (cpw when none), without
-            // branches: every lane takes the same instructions
-            const int32_t m0 = d0[u] ? (ctz64(d0[u]) >> en.A.lbpc) : cpw;
-            const int32_t m1 = d1[u] ? (ctz64(d1[u]) >> en.A.lbpc) : cpw;
-            const int32_t ll = m0 < cpw ? m0 : cpw + m1;  // <= 2 cpw
-            l[u] = go ? imin(ll, lim[u]) : 0;
-            pend[u] = go && ll == 2 * cpw && lim[u] > 2 * cpw;
+            const uint64_t d = a0 ^ b0;
+            // the first mismatch (cpw when none), without branches: every
+            // lane takes the same instructions
+            const int32_t m0 = d ? (ctz64(d) >> en.A.lbpc) : cpw;
+            l[u] = go ? imin(m0, lim[u]) : 0;
+            pend[u] = go && m0 == cpw && lim[u] > cpw;
         }
         // (2)/(3) the wavefront extends its lanes' long LCPs
 #pragma unroll
