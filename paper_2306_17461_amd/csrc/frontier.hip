@@ -372,17 +372,18 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
-            if (!slot[u] || queued[u]) continue;
+            if (!slot[u]) continue;
+            // (a queued diagonal is written by the workgroup tier)
             const int32_t f = val[u] ? c[u] + l[u] : kNone;
-            if (act[u]) {
+            if (act[u] && !queued[u]) {
                 cur[iv[u] + ofs] = f;
                 if (dump_row && iv[u] >= dlo && iv[u] <= dhi) dump_row[iv[u] + t] = f;
             }
-            if (val[u]) {
-                cnt.updates++;
-                cnt.lcp_chars += static_cast<unsigned long long>(l[u]);
-                if (iv[u] == target && f == n) found = true;
-            }
+            // counters and the target test as selects (no branch)
+            const bool done = val[u] && !queued[u];
+            cnt.updates += done ? 1ull : 0ull;
+            cnt.lcp_chars += done ? static_cast<unsigned long long>(l[u]) : 0ull;
+            found = found || (done && iv[u] == target && f == n);
         }
     }
     if (found) RS.flag = 1;
