@@ -199,7 +199,10 @@ typedef struct ed_stats {
     uint64_t hash_queries;    /* LCPs answered by the hash engine */
     uint64_t hash_probes;     /* hash equality tests */
     uint64_t collisions;      /* detected collisions (fell back to the direct engine) */
-    double collision_bound;   /* union bound on an undetected collision for the last run */
+    double collision_bound;   /* hash engine: bound on the probability (over the base drawn from
+                               * the seed) that the last run met an undetected collision: the sum
+                               * of (L - 1) / (2^61 - 1 - 2^21) over the verdicts on strings of
+                               * length L that decided a step of a hash search (Schwartz-Zippel) */
     uint64_t launches;        /* kernel launches of the last ed_distance */
     double ns_prepare, ns_distance; /* host wall time of the last calls */
     /* with ED_FLAG_TIMING: HIP-event time of the prepare kernel and of the

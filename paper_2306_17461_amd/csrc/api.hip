@@ -603,10 +603,13 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
         *b = c->pool.get(static_cast<size_t>(2 * Kn + 5) * 4);
         return *a && *b;
     };
+    auto free_rows = [&](void* a, void* b) {
+        c->pool.put(a);
+        c->pool.put(b);
+    };
     void *f0 = nullptr, *f1 = nullptr;
     if (!alloc_rows(K, &f0, &f1)) {
-        c->pool.put(f0);
-        c->pool.put(f1);
+        free_rows(f0, f1);
         c->pool.put(dump_buf);
         return ED_ENOMEM;
     }
@@ -666,7 +669,7 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
         total.wg_lcps += cd.wg_lcps;
         total.hash_queries += cd.hash_queries;
         total.hash_probes += cd.hash_probes;
-        total.hash_eq_len += cd.hash_eq_len;
+        total.hash_ne_len += cd.hash_ne_len;
         total.collisions += cd.collisions;
         const FrontierCtl& st = *c->h_ctl;
         if (launches == 1) {
@@ -689,8 +692,7 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
             }
             void *g0 = nullptr, *g1 = nullptr;
             if (!alloc_rows(K2, &g0, &g1)) {
-                c->pool.put(g0);
-                c->pool.put(g1);
+                free_rows(g0, g1);
                 rc = ED_ENOMEM;
                 break;
             }
@@ -700,8 +702,7 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
                                static_cast<int32_t*>(srcrow) + (K + 2) - (t + 2),
                                static_cast<size_t>(2 * t + 5) * 4, hipMemcpyDeviceToDevice, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
-            c->pool.put(f0);
-            c->pool.put(f1);
+            free_rows(f0, f1);
             f0 = g0;
             f1 = g1;
             if (e != hipSuccess) {
@@ -717,8 +718,7 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
         rc = ED_EINTERNAL;
         break;
     }
-    c->pool.put(f0);
-    c->pool.put(f1);
+    free_rows(f0, f1);
     if (rc == ED_OK) {
         *k_out = result;
         p->rounds = result;
@@ -810,9 +810,14 @@ int ed_pair_stats(const ed_pair* p, ed_stats* o) {
     o->hash_queries = p->counters.hash_queries;
     o->hash_probes = p->counters.hash_probes;
     o->collisions = p->counters.collisions;
-    // Schwartz-Zippel: a false "equal" for strings of length L has
-    // probability <= (L-1)/P over a uniform base
-    o->collision_bound = static_cast<double>(p->counters.hash_eq_len) / static_cast<double>(kP);
+    // Schwartz-Zippel: for distinct strings of length L, h(A) - h(B) is a
+    // nonzero polynomial of degree <= L - 1 in the base, so a base drawn
+    // uniformly from the kP - 2^21 admissible values makes them hash alike
+    // with probability <= (L - 1) / (kP - 2^21).  A run can go wrong only
+    // where a verdict that decides a search step is a false "equal"; in the
+    // run without collisions those verdicts on distinct strings are the first
+    // "unequal" probe of each step, whose L - 1 the kernels add up.
+    o->collision_bound = static_cast<double>(p->counters.hash_ne_len) / static_cast<double>(kP - (1ull << 21));
     o->launches = static_cast<uint64_t>(p->launches_distance);
     o->certify_retries = p->certify_retries;
     o->ns_prepare = p->ns_prepare;

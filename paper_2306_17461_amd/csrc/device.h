@@ -181,14 +181,14 @@ __device__ __forceinline__ int32_t lcp_wave_steps(const SView& A, const SView& B
 struct Cnt {
     unsigned long long updates;    // this lane's diagonal updates
     unsigned long long lcp_chars;  // characters matched by this lane's slides
-    unsigned long long eq_len;     // sum of L over this lane's hash "equal" verdicts
+    unsigned long long ne_len;     // sum of L - 1 over the deciding "unequal" verdicts of hash searches
     CountersDev* sh;               // workgroup counters (LDS)
 };
 
 __device__ __forceinline__ void cnt_bind(Cnt& c, CountersDev* sh) {
     c.updates = 0;
     c.lcp_chars = 0;
-    c.eq_len = 0;
+    c.ne_len = 0;
     c.sh = sh;
 }
 
@@ -327,12 +327,13 @@ __device__ __forceinline__ int32_t lcp_wave_hash(const SView& A, const SView& B,
         const bool e = active ? eq(L) : true;
         const uint64_t pa = ballot(active);
         if (lane == 0) atomicAdd(&cnt.sh->hash_probes, static_cast<unsigned long long>(__builtin_popcountll(pa)));
-        if (active && e) cnt.eq_len += static_cast<unsigned long long>(L);
         const uint64_t ne = ballot(active && !e);
         if (ne == 0) return lim;  // every probe up to lim matched
         const int k = ctz64(ne);
         hi = shfl_i32(L, k);
         if (k > 0) lo = shfl_i32(L, k - 1);
+        // the one verdict on distinct strings that decides this step
+        if (lane == 0) cnt.ne_len += static_cast<unsigned long long>(hi - 1);
     }
     while (hi - lo > span) {
         const int32_t step = (hi - lo + 63) / 64;
@@ -341,13 +342,13 @@ __device__ __forceinline__ int32_t lcp_wave_hash(const SView& A, const SView& B,
         const bool e = active ? eq(M) : true;
         const uint64_t act = ballot(active);
         if (lane == 0) atomicAdd(&cnt.sh->hash_probes, static_cast<unsigned long long>(__builtin_popcountll(act)));
-        if (active && e) cnt.eq_len += static_cast<unsigned long long>(M);
         const uint64_t ne = ballot(active && !e);
         if (ne) {
             const int k = ctz64(ne);
             const int32_t nhi = shfl_i32(M, k);
             if (k > 0) lo = shfl_i32(M, k - 1);
             hi = nhi;
+            if (lane == 0) cnt.ne_len += static_cast<unsigned long long>(hi - 1);
         } else {
             lo = shfl_i32(M, 63 - __builtin_clzll(act));
         }
@@ -427,11 +428,11 @@ __device__ __forceinline__ void flush_counters(Cnt& c, CountersDev* g) {
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
         return v;
     };
-    const unsigned long long u = red(c.updates), lc = red(c.lcp_chars), he = red(c.eq_len);
+    const unsigned long long u = red(c.updates), lc = red(c.lcp_chars), he = red(c.ne_len);
     if (lane_id() == 0) {
         if (u) atomicAdd(&c.sh->updates, u);
         if (lc) atomicAdd(&c.sh->lcp_chars, lc);
-        if (he) atomicAdd(&c.sh->hash_eq_len, he);
+        if (he) atomicAdd(&c.sh->hash_ne_len, he);
     }
     __syncthreads();
     if (threadIdx.x == 0 && g) {
@@ -444,7 +445,7 @@ __device__ __forceinline__ void flush_counters(Cnt& c, CountersDev* g) {
         if (s.wg_lcps) atomicAdd(&g->wg_lcps, s.wg_lcps);
         if (s.hash_queries) atomicAdd(&g->hash_queries, s.hash_queries);
         if (s.hash_probes) atomicAdd(&g->hash_probes, s.hash_probes);
-        if (s.hash_eq_len) atomicAdd(&g->hash_eq_len, s.hash_eq_len);
+        if (s.hash_ne_len) atomicAdd(&g->hash_ne_len, s.hash_ne_len);
         if (s.collisions) atomicAdd(&g->collisions, s.collisions);
     }
 }

@@ -64,7 +64,7 @@ struct CountersDev {
     unsigned long long wg_lcps;      // LCPs extended by a whole workgroup
     unsigned long long hash_queries;
     unsigned long long hash_probes;
-    unsigned long long hash_eq_len;  // sum of L over hash "equal" verdicts
+    unsigned long long hash_ne_len;  // sum of L - 1 over the deciding "unequal" hash verdicts
     unsigned long long collisions;
 };
 
