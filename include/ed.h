@@ -134,6 +134,23 @@ int ed_release(ed_pair *pair);
 int ed_distance(ed_ctx *ctx, ed_pair *pair, int64_t k_max, uint64_t *k_out, void *hip_stream);
 
 /*
+ * For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): ed_distance with every round's frontier
+ * rows in a fixed device array of the library instead of memory from the
+ * context's pool.  It calls no hipMalloc, hipFree or other allocating routine.
+ * k_max is required and bounded: 0 <= k_max <= ED_NOALLOC_MAX_K, else
+ * ED_EINVAL (the array holds the two rows of 2 k_max + 5 int32 entries, 8 MB);
+ * as with ed_distance, *k_out = k_max + 1 when the distance is larger.  The
+ * pair must have been prepared with the context's current hash base (else
+ * ED_EINVAL).  The array is one per device, shared by every context and call
+ * on that device: calls that overlap on one device race, and it keeps the
+ * last call's contents (every entry a call reads it writes first).
+ * Synchronous on hip_stream.  Errors: ED_EINVAL, ED_EDEVICE, ED_EINTERNAL.
+ */
+#define ED_NOALLOC_MAX_K ((uint64_t)500000u)
+int ed_distance_noalloc(ed_ctx *ctx, ed_pair *pair, int64_t k_max, uint64_t *k_out, void *hip_stream);
+
+/*
  * As ed_distance, and also copies the frontier of every round to `rows`
  * (host int32 array): row t (t = 0..k) starts at index t*t and holds the 2t+1
  * entries f_t[-t..t]; a diagonal without a cell holds ED_NONE.  Needs

@@ -42,6 +42,7 @@ BUF_PACKED2 = 0
 BUF_BYTES = 1
 BUF_TABLE = 2
 NONE = -(1 << 30)
+NOALLOC_MAX_K = 500000
 MAX_LEN = 2146435072
 
 
@@ -96,7 +97,7 @@ class ed_result(ctypes.Structure):
 # every symbol declared in include/ed.h
 EXPORTS = [
     "ed_default_options", "ed_hash_base", "ed_init", "ed_set_options", "ed_get_options",
-    "ed_shutdown", "ed_prepare", "ed_release", "ed_distance", "ed_distance_dump", "ed_align", "ed_batch",
+    "ed_shutdown", "ed_prepare", "ed_release", "ed_distance", "ed_distance_noalloc", "ed_distance_dump", "ed_align", "ed_batch",
     "ed_autotune_batch", "ed_pair_stats", "ed_pair_buffer", "ed_debug_lcp", "ed_debug_check_runs",
     "ed_debug_mem_latency", "ed_serve_open",
     "ed_serve_submit",
@@ -124,6 +125,7 @@ def _load():
         "ed_prepare": (i32, [vp, vp, u64, vp, u64, i32, vp, P(vp)]),
         "ed_release": (i32, [vp]),
         "ed_distance": (i32, [vp, vp, i64, P(u64), vp]),
+        "ed_distance_noalloc": (i32, [vp, vp, i64, P(u64), vp]),
         "ed_distance_dump": (i32, [vp, vp, i64, P(u64), vp, u64, vp]),
         "ed_align": (i32, [vp, vp, P(u64), P(ed_op_run), u64, P(u64), vp]),
         "ed_batch": (i32, [vp, P(vp), u64, i64, P(u64), P(ctypes.c_int32), vp]),
@@ -251,6 +253,15 @@ def ed_release(pair):
 def ed_distance(ctx, pair, k_max=-1, stream=None):
     k = ctypes.c_uint64()
     _check(lib.ed_distance(ctx, pair, k_max, ctypes.byref(k), _stream_handle(stream)), "ed_distance")
+    return int(k.value)
+
+
+def ed_distance_noalloc(ctx, pair, k_max, stream=None):
+    """ed_distance without device allocation: rows in the library's fixed
+    array, 0 <= k_max <= NOALLOC_MAX_K."""
+    k = ctypes.c_uint64()
+    _check(lib.ed_distance_noalloc(ctx, pair, k_max, ctypes.byref(k), _stream_handle(stream)),
+           "ed_distance_noalloc")
     return int(k.value)
 
 

@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libed.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["prepare.hip", "frontier.hip", "api.hip", "batch_api.hip", "serve.hip", "align.hip", "align_api.hip",
-           "probe.hip"]
+           "probe.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -298,6 +298,7 @@ int ed_init(ed_ctx** out, int device, const ed_options* opt) {
         return ED_EDEVICE;
     }
     int rc = ctx_set_hash(c, opt_base(o));
+    if (rc == ED_OK) rc = scratch_setup(c);
     if (rc != ED_OK) {
         ed_shutdown(c);
         return rc;
@@ -571,7 +572,12 @@ static int frontier_grid(const ed_ctx* c) {
 }
 
 int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, int32_t* rows,
-                        uint64_t rows_cap, hipStream_t s, int32_t* dev_dump, uint64_t dev_cap) {
+                        uint64_t rows_cap, hipStream_t s, int32_t* dev_dump, uint64_t dev_cap,
+                        int32_t* fixed_rows, int64_t fixed_K) {
+    if (fixed_rows && (k_max < 0 || k_max > fixed_K || rows || dev_dump)) {
+        set_error("distance_locked: fixed rows need 0 <= k_max <= %lld", (long long)fixed_K);
+        return ED_EINVAL;
+    }
     if (p->engine == ED_ENGINE_HASH && (!p->tab[0] || !p->tab[1])) {
         set_error("ed_distance: pair has no prefix tables");
         return ED_EINVAL;
@@ -585,6 +591,8 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
     int64_t K = std::min<int64_t>(maxnm, c->opt.init_rows ? int64_t(c->opt.init_rows) : int64_t(1) << 17);
     if (k_max >= 0) K = std::min<int64_t>(K, std::max<int64_t>(k_max, 1));
     K = std::max<int64_t>(K, 1);
+    // caller-owned rows: sized for every round up to k_max, never grown
+    if (fixed_rows) K = std::max<int64_t>(k_max, 1);
     const uint32_t lds_rounds = c->opt.lds_rounds ? c->opt.lds_rounds : kDefaultLdsRounds;
     const uint32_t lane_words = c->opt.lane_words ? c->opt.lane_words
                                                   : (p->engine == ED_ENGINE_HASH ? 1u : 2u);
@@ -599,11 +607,17 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
         rows_cap = dev_cap;
     }
     auto alloc_rows = [&](int64_t Kn, void** a, void** b) -> bool {
+        if (fixed_rows) {
+            *a = fixed_rows;
+            *b = fixed_rows + (2 * Kn + 5);
+            return Kn <= fixed_K;
+        }
         *a = c->pool.get(static_cast<size_t>(2 * Kn + 5) * 4);
         *b = c->pool.get(static_cast<size_t>(2 * Kn + 5) * 4);
         return *a && *b;
     };
     auto free_rows = [&](void* a, void* b) {
+        if (fixed_rows) return;
         c->pool.put(a);
         c->pool.put(b);
     };
@@ -685,7 +699,7 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
             // grow the rows and resume from the saved frontier f_t
             const int64_t t = st.result_t;
             const int64_t K2 = std::min<int64_t>(maxnm, std::max<int64_t>(2 * K, t + 1));
-            if (K2 <= K) {
+            if (K2 <= K || fixed_rows) {
                 set_error("ed_distance: capacity exhausted at t=%lld (K=%lld)", (long long)t, (long long)K);
                 rc = ED_EINTERNAL;
                 break;

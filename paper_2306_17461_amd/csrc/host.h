@@ -56,6 +56,7 @@ struct ed_ctx {
     ed::CountersDev* h_cnt = nullptr;  // pinned
     hipEvent_t ev[2] = {nullptr, nullptr};  // frontier timing
     unsigned int* d_bar = nullptr;          // device-wide barrier flags
+    int32_t* d_scratch = nullptr;           // this device's scratch array (ed_distance_noalloc)
     ed::DevPool pool;
 };
 
@@ -108,8 +109,14 @@ int prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B, ui
                    int on_device, hipStream_t s, ed_pair** out);
 // rows: host copy of every round's frontier row (ed_distance_dump); dev_dump:
 // the same rows kept in device memory (dev_cap entries), for the traceback
+// fixed_rows: two rows of 2 fixed_K + 5 entries that the caller owns (no
+// allocation and no growth; needs 0 <= k_max <= fixed_K)
 int distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, int32_t* rows,
-                    uint64_t rows_cap, hipStream_t s, int32_t* dev_dump = nullptr, uint64_t dev_cap = 0);
+                    uint64_t rows_cap, hipStream_t s, int32_t* dev_dump = nullptr, uint64_t dev_cap = 0,
+                    int32_t* fixed_rows = nullptr, int64_t fixed_K = 0);
+// device address of this device's scratch array (noalloc.hip), taken once at
+// ed_init with the device current
+int scratch_setup(ed_ctx* c);
 // k, an optimal path (k + 1 steps) and the direct check of its runs of matches
 int align_locked(ed_ctx* c, ed_pair* p, uint64_t* k_out, std::vector<PathStep>& path, hipStream_t s);
 int tasks_run(ed_ctx* c, std::vector<TaskPair>& st, const std::vector<long long>& first, int64_t k_max,
