@@ -6,18 +6,30 @@ touches the HIP library.  The full-size GPU tests regenerate the same inputs
 from the same seeds and compare the library's distances with these values.
 
 Workloads:
-  * single pairs, n = 10^8, alphabet {0,1,2,3} uniform, k in {10^2 .. 10^5}, seed 0;
+  * single pairs, n = 10^8, alphabet {0,1,2,3} uniform, k in {10^2 .. 10^5},
+    seeds 0, 1, 2;
   * single pairs, n = 10^9, Zipf(1.0) over 256 symbols and its period-64
-    variant, k in {10^3, 10^5}, seed 0;
+    variant, k in {10^3, 10^5}, seeds 0, 1, 2;
   * the paper's own synthetic shape: n = 10^8 uniform over 256 symbols,
     k in {10^2 .. 10^5}, seed 0 (the workload of its full-run table);
   * the 4096-pair batch (n log-uniform in [10^3, 10^6], k uniform in
-    [0, 0.01 n], alphabet 4), seed 0;
-  * the first 40 requests of the serving trace (n log-uniform in [10^2, 10^7],
-    alphabet 4 or 20, k uniform in [0, 0.05 n]), seed 0.
+    [0, 0.01 n], alphabet 4), seeds 0, 1, 2;
+  * the first 40 requests of the mixed-alphabet serving trace (n log-uniform
+    in [10^2, 10^7], alphabet 4 or 20, k uniform in [0, 0.05 n]), seed 0;
+  * the serving traces at their measured size: 2200 requests (200 warm-up +
+    2000), one alphabet per trace (4 or 20), seeds 0, 1, 2.  The oracle takes
+    about 2 hours of 8 cores per trace in full (the sum of k^2 is about
+    8e12 diagonal updates), so a sample is stored: every request with
+    k_planted <= SERVE_SMALL_K, plus SERVE_LARGE_PICK larger requests chosen
+    by a seeded draw (stratified: the largest ones are represented).  The
+    GPU test checks every sampled request against these values and the rest
+    against properties that hold at any size.
 
-Usage: python tests/golden/make_golden.py [--only single|big|paper|batch|serve]
-(several minutes on 8 cores; the single pairs at n = 10^9 need ~10 GB of RAM).
+Entries already in the file with the same specification are kept (the
+script only computes what is missing); --force recomputes everything.
+
+Usage: python tests/golden/make_golden.py [--only single|big|paper|batch|serve|trace] [--force]
+(the single pairs at n = 10^9 need ~10 GB of RAM).
 """
 import argparse
 import json
@@ -25,6 +37,8 @@ import os
 import sys
 import time
 from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
@@ -34,15 +48,28 @@ import oracle  # noqa: E402
 import synth  # noqa: E402
 
 OUT = os.path.join(HERE, "fullsize.json")
+SEEDS = (0, 1, 2)
 
-SINGLE = [dict(name="n1e8_sigma4_k%d" % k, n=10 ** 8, k=k, seed=0, kind="uniform", sigma=4,
-               periodic=False) for k in (100, 1000, 10000, 100000)]
-BIG = [dict(name="n1e9_zipf%s_k%d" % ("_periodic" if p else "", k), n=10 ** 9, k=k, seed=0,
-            kind="zipf", sigma=256, periodic=p) for p in (False, True) for k in (1000, 100000)]
+
+def _sfx(seed):
+    return "" if seed == 0 else "_seed%d" % seed
+
+
+SINGLE = [dict(name="n1e8_sigma4_k%d%s" % (k, _sfx(s)), n=10 ** 8, k=k, seed=s, kind="uniform", sigma=4,
+               periodic=False) for s in SEEDS for k in (100, 1000, 10000, 100000)]
+BIG = [dict(name="n1e9_zipf%s_k%d%s" % ("_periodic" if p else "", k, _sfx(s)), n=10 ** 9, k=k, seed=s,
+            kind="zipf", sigma=256, periodic=p) for s in SEEDS for p in (False, True) for k in (1000, 100000)]
 PAPER = [dict(name="n1e8_sigma256_k%d" % k, n=10 ** 8, k=k, seed=0, kind="uniform", sigma=256,
               periodic=False) for k in (100, 1000, 10000, 100000)]
-BATCH = dict(name="batch4096_seed0", count=4096, seed=0)
+BATCH = [dict(name="batch4096_seed%d" % s, count=4096, seed=s) for s in SEEDS]
 SERVE = dict(name="serve40_seed0", count=40, seed=0)
+TRACE_COUNT = 2200
+TRACE_WARMUP = 200
+SERVE_SMALL_K = 30000
+SERVE_LARGE_PICK = 8
+TRACES = [dict(name="serve%d_sigma%d_seed%d" % (TRACE_COUNT, sg, s), count=TRACE_COUNT, warmup=TRACE_WARMUP,
+               seed=s, sigma=sg, small_k=SERVE_SMALL_K, large_pick=SERVE_LARGE_PICK)
+          for sg in (4, 20) for s in SEEDS]
 
 
 def log(*a):
@@ -58,8 +85,9 @@ def single(spec):
     A, B, info = synth.single_pair(spec["n"], spec["k"], spec["seed"], sigma=spec["sigma"],
                                    kind=spec["kind"], periodic=spec["periodic"])
     ed = oracle.lv_omp(A, B, -1, threads())
-    out = dict(spec, m=len(B), ed=ed, k_planted=info["k_planted"])
-    log("%-28s m=%d ed=%d (%.1f s)" % (spec["name"], len(B), ed, time.time() - t0))
+    dt = time.time() - t0
+    out = dict(spec, m=len(B), ed=ed, k_planted=info["k_planted"], oracle_s=round(dt, 1))
+    log("%-34s m=%d ed=%d (%.1f s)" % (spec["name"], len(B), ed, dt))
     return out
 
 
@@ -74,8 +102,8 @@ def many(pairs_of, count, name):
 
     with ThreadPoolExecutor(threads()) as ex:
         eds = list(ex.map(one, range(count)))
-    log("%-28s %d pairs (%.1f s)" % (name, count, time.time() - t0))
-    return eds
+    log("%-34s %d pairs (%.1f s)" % (name, count, time.time() - t0))
+    return eds, time.time() - t0
 
 
 def batch(spec):
@@ -86,38 +114,107 @@ def batch(spec):
         A, B, _ = synth.single_pair(n, k, ps)
         return A, B
 
-    return dict(spec, eds=many(pairs_of, spec["count"], spec["name"]))
+    eds, dt = many(pairs_of, spec["count"], spec["name"])
+    return dict(spec, eds=eds, oracle_s=round(dt, 1))
 
 
 def serve(spec):
     trace = synth.arrival_trace(spec["count"], spec["seed"], rate_per_s=1.0)
-    return dict(spec, eds=many(lambda i: synth.request_pair(trace[i]), spec["count"],
-                               spec["name"]))
+    eds, dt = many(lambda i: synth.request_pair(trace[i]), spec["count"], spec["name"])
+    return dict(spec, eds=eds, oracle_s=round(dt, 1))
+
+
+def trace_sample(spec):
+    """Indices of a serving trace whose oracle values are stored: every request
+    with k_planted <= small_k, and large_pick of the others, drawn with the
+    trace's seed (half from the upper half of the larger k, half from the lower
+    half, so that the heaviest requests are represented)."""
+    trace = synth.arrival_trace(spec["count"], spec["seed"], rate_per_s=1.0, sigmas=(spec["sigma"],))
+    small = [i for i, r in enumerate(trace) if r["k"] <= spec["small_k"]]
+    large = sorted((i for i, r in enumerate(trace) if r["k"] > spec["small_k"]), key=lambda i: trace[i]["k"])
+    half = len(large) // 2
+    draws = synth.draws(spec["seed"] + 1000 * spec["sigma"], synth.S_REQ_SEED, spec["large_pick"])
+    pick = []
+    for j in range(spec["large_pick"]):
+        lo, hi = (half, len(large)) if j % 2 == 0 else (0, half)
+        pool = [i for i in large[lo:hi] if i not in pick]
+        if pool:
+            pick.append(pool[int(draws[j] % np.uint64(len(pool)))])
+    return trace, sorted(small + pick)
+
+
+def serve_trace(spec):
+    trace, idx = trace_sample(spec)
+    t0 = time.time()
+    small = [i for i in idx if trace[i]["k"] <= spec["small_k"]]
+    large = [i for i in idx if trace[i]["k"] > spec["small_k"]]
+    got = {}
+    with ThreadPoolExecutor(threads()) as ex:
+        for i, e in zip(small, ex.map(lambda i: oracle.lv_omp(*synth.request_pair(trace[i]), -1, 1), small)):
+            got[i] = e
+    for i in large:
+        t1 = time.time()
+        got[i] = oracle.lv_omp(*synth.request_pair(trace[i]), -1, threads())
+        log("  %s request %d: n=%d k=%d ed=%d (%.1f s)" % (spec["name"], i, trace[i]["n"], trace[i]["k"],
+                                                          got[i], time.time() - t1))
+    dt = time.time() - t0
+    log("%-34s %d of %d requests (%.1f s)" % (spec["name"], len(idx), spec["count"], dt))
+    return dict(spec, index=idx, eds=[got[i] for i in idx], oracle_s=round(dt, 1), threads=threads())
+
+
+def _merge(old, specs, fn, force):
+    """Entries of `specs`, reusing an old entry with the same specification."""
+    have = {g["name"]: g for g in (old or [])}
+    out = []
+    for s in specs:
+        g = have.get(s["name"])
+        if g is not None and not force and all(g.get(k) == v for k, v in s.items()):
+            out.append(g)
+        else:
+            out.append(fn(s))
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--only", choices=["single", "big", "paper", "batch", "serve"])
+    ap.add_argument("--only", choices=["single", "big", "paper", "batch", "serve", "trace"])
+    ap.add_argument("--force", action="store_true")
     args = ap.parse_args()
     oracle.build(force=False)
     data = {}
     if os.path.exists(OUT):
         with open(OUT) as f:
             data = json.load(f)
+    if isinstance(data.get("batch"), dict):  # older single-seed layout
+        data["batch"] = [data["batch"]]
     data["source"] = ("oracle.lv_omp on synth inputs; written by tests/golden/make_golden.py")
+
+    def save():
+        with open(OUT + ".tmp", "w") as f:
+            json.dump(data, f, indent=1)
+        os.replace(OUT + ".tmp", OUT)
+
     if args.only in (None, "single"):
-        data["single"] = [single(s) for s in SINGLE]
+        data["single"] = _merge(data.get("single"), SINGLE, single, args.force)
+        save()
     if args.only in (None, "big"):
-        data["big"] = [single(s) for s in BIG]
+        data["big"] = _merge(data.get("big"), BIG, single, args.force)
+        save()
     if args.only in (None, "paper"):
-        data["paper"] = [single(s) for s in PAPER]
+        data["paper"] = _merge(data.get("paper"), PAPER, single, args.force)
+        save()
     if args.only in (None, "batch"):
-        data["batch"] = batch(BATCH)
+        data["batch"] = _merge(data.get("batch"), BATCH, batch, args.force)
+        save()
     if args.only in (None, "serve"):
-        data["serve"] = serve(SERVE)
-    with open(OUT + ".tmp", "w") as f:
-        json.dump(data, f, indent=1)
-    os.replace(OUT + ".tmp", OUT)
+        data["serve"] = _merge([data["serve"]] if "serve" in data else [], [SERVE], serve, args.force)[0]
+        save()
+    if args.only in (None, "trace"):
+        out = []
+        for s in TRACES:
+            out = _merge(data.get("serve_trace"), [s], serve_trace, args.force)
+            data["serve_trace"] = [g for g in data.get("serve_trace", []) if g["name"] != s["name"]] + out
+            save()
     log("wrote", OUT)
 
 

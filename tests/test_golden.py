@@ -23,18 +23,63 @@ def gold():
 
 
 def test_golden_file_complete(gold):
-    assert [g["k"] for g in gold["single"]] == [100, 1000, 10000, 100000]
+    seeds = (0, 1, 2)
+    assert sorted((g["seed"], g["k"]) for g in gold["single"]) == [
+        (s, k) for s in seeds for k in (100, 1000, 10000, 100000)]
     assert all(g["n"] == 10 ** 8 and g["sigma"] == 4 for g in gold["single"])
-    assert {(g["periodic"], g["k"]) for g in gold["big"]} == {
-        (False, 1000), (False, 100000), (True, 1000), (True, 100000)}
+    assert sorted((g["seed"], g["periodic"], g["k"]) for g in gold["big"]) == [
+        (s, p, k) for s in seeds for p in (False, True) for k in (1000, 100000)]
     assert all(g["n"] == 10 ** 9 and g["kind"] == "zipf" for g in gold["big"])
     assert [g["k"] for g in gold["paper"]] == [100, 1000, 10000, 100000]
     assert all(g["n"] == 10 ** 8 and g["sigma"] == 256 and g["kind"] == "uniform" for g in gold["paper"])
-    assert len(gold["batch"]["eds"]) == gold["batch"]["count"] == 4096
+    assert [b["seed"] for b in gold["batch"]] == list(seeds)
+    assert all(len(b["eds"]) == b["count"] == 4096 for b in gold["batch"])
     assert len(gold["serve"]["eds"]) == gold["serve"]["count"] == 40
+    assert sorted((t["sigma"], t["seed"]) for t in gold["serve_trace"]) == [
+        (sg, s) for sg in (4, 20) for s in seeds]
+    for t in gold["serve_trace"]:
+        assert t["count"] >= 2200 and t["warmup"] == 200 and len(t["index"]) == len(t["eds"])
     # distance bounds of planted edits: |n - m| <= ED <= k
     for g in gold["single"] + gold["big"] + gold["paper"]:
         assert abs(g["n"] - g["m"]) <= g["ed"] <= g["k_planted"]
+
+
+def _trace_entry(gold, sigma, seed):
+    return next(t for t in gold["serve_trace"] if t["sigma"] == sigma and t["seed"] == seed)
+
+
+@pytest.mark.parametrize("sigma", [4, 20])
+def test_serve_trace_sample_rule(gold, sigma):
+    """The stored sample is the rule of make_golden.py: every request with
+    k_planted <= small_k, plus large_pick larger ones, half of them from the
+    upper half of the larger k."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "make_golden", os.path.join(os.path.dirname(GOLD_PATH), "make_golden.py"))
+    mg = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mg)
+    t = _trace_entry(gold, sigma, 0)
+    trace, idx = mg.trace_sample(t)
+    assert idx == t["index"]
+    ks = sorted(r["k"] for r in trace if r["k"] > t["small_k"])
+    picked = [trace[i]["k"] for i in idx if trace[i]["k"] > t["small_k"]]
+    assert len(picked) == t["large_pick"]
+    assert sum(k >= ks[len(ks) // 2] for k in picked) >= t["large_pick"] // 2
+    for i, e in zip(t["index"], t["eds"]):
+        r = trace[i]
+        assert e <= r["k"]
+
+
+@pytest.mark.parametrize("sigma", [4, 20])
+def test_serve_trace_small_requests_recomputed(gold, orc, sigma):
+    t = _trace_entry(gold, sigma, 1)
+    trace = synth.arrival_trace(t["count"], t["seed"], rate_per_s=1.0, sigmas=(sigma,))
+    got = dict(zip(t["index"], t["eds"]))
+    small = [i for i in t["index"] if trace[i]["n"] <= 20000][:40]
+    assert len(small) >= 20
+    for i in small:
+        A, B = synth.request_pair(trace[i])
+        assert orc.lv_omp(A, B, -1, 1) == got[i], i
 
 
 @pytest.mark.parametrize("idx", [0, 1])
@@ -53,8 +98,9 @@ def test_paper_shape_recomputed(gold, orc):
     assert orc.lv_omp(A, B) == g["ed"]
 
 
-def test_batch_prefix_recomputed(gold, orc):
-    b = gold["batch"]
+@pytest.mark.parametrize("which", [0, 2])
+def test_batch_prefix_recomputed(gold, orc, which):
+    b = gold["batch"][which]
     specs = synth.batch_specs(b["count"], b["seed"])
     for i in range(64):
         n, k, ps = specs[i]

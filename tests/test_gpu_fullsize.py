@@ -87,6 +87,8 @@ def test_n1e8_alphabet4(ed, ctxs, name, engine):
     assert st["bits_per_char"] == 2
     assert k == spec["ed"]
     assert st["rounds"] == spec["ed"]
+    if engine == "hash":
+        check_collision_bound(ed, ctxs, spec, st)
 
 
 @pytest.mark.parametrize("name,engine", _cases("big"))
@@ -97,11 +99,37 @@ def test_n1e9_zipf_and_periodic(ed, ctxs, name, engine):
     assert st["bits_per_char"] == 8
     assert k == spec["ed"]
     if engine == "hash":
-        # union bound on an undetected collision over every "equal" verdict
-        # (none when every LCP ends within the direct steps that precede the
-        # hash search)
-        assert 0 <= st["collision_bound"] < 1e-3
-        assert (st["hash_probes"] > 0) == (st["collision_bound"] > 0)
+        check_collision_bound(ed, ctxs, spec, st)
+
+
+# Largest accepted probability, over the hash base drawn from the seed, that a
+# hash-engine distance is wrong: one run in a million.  collision_bound is the
+# Schwartz-Zippel union bound over the verdicts that decided the run's hash
+# searches (the first "unequal" probe of each galloping and narrowing step,
+# (L - 1) / (2^61 - 1 - 2^21) for strings of length L).  A run above this
+# target is checked instead: ED_FLAG_CERTIFY traces the path back and compares
+# every run of matches on it directly, and must agree without a retry.
+COLLISION_TARGET = 1e-6
+
+
+def check_collision_bound(ed, ctxs, spec, st):
+    bound = st["collision_bound"]
+    say("collision bound %.3g over %d hash queries" % (bound, st["hash_queries"]))
+    assert bound >= 0
+    if bound <= COLLISION_TARGET:
+        return
+    import torch
+    tA, tB = device_pair(spec)
+    ctx = ed.ed_init(0, engine=ed.ENGINE_HASH, flags=ed.FLAG_CERTIFY)
+    try:
+        pair = ed.ed_prepare(ctx, tA, tB, stream=torch.cuda.current_stream())
+        try:
+            assert ed.ed_distance(ctx, pair) == spec["ed"]
+            assert ed.ed_pair_stats(pair)["certify_retries"] == 0
+        finally:
+            ed.ed_release(pair)
+    finally:
+        ed.ed_shutdown(ctx)
 
 
 @pytest.mark.parametrize("name,engine", _cases("paper"))
@@ -123,12 +151,13 @@ def _gen_pairs(specs):
         return list(ex.map(one, specs))
 
 
+@pytest.mark.parametrize("seed", [0, 1, 2])
 @pytest.mark.parametrize("engine", ["direct", "hash"])
-def test_batch4096(ed, ctxs, engine):
+def test_batch4096(ed, ctxs, engine, seed):
     _cache.clear()
-    g = GOLD["batch"]
+    g = next(b for b in GOLD["batch"] if b["seed"] == seed)
     specs = synth.batch_specs(g["count"], g["seed"])
-    say("batch4096", engine, "generating")
+    say("batch4096", engine, "seed", seed, "generating")
     pairs_h = _gen_pairs(specs)
     ctx = ctxs[engine]
     pairs = [ed.ed_prepare(ctx, A, B) for A, B in pairs_h]
@@ -164,3 +193,41 @@ def test_serve40(ed, ctxs, engine):
     # sampled sizes span the whole range
     ns = np.array([r["n"] for r in trace])
     assert ns.min() < 10 ** 3 and ns.max() > 10 ** 6
+
+
+def _trace_cases():
+    cases = [(t["sigma"], t["seed"], "direct") for t in GOLD.get("serve_trace", [])]
+    cases += [(t["sigma"], t["seed"], "hash") for t in GOLD.get("serve_trace", []) if t["seed"] == 0]
+    return cases
+
+
+@pytest.mark.parametrize("sigma,seed,engine", _trace_cases())
+def test_serve_trace_2200(ed, ctxs, sigma, seed, engine):
+    """The serving trace at its measured size (2200 requests, one alphabet):
+    every request through the continuous-batching server at once; each sampled
+    request equals its stored oracle value, every other one lies within the
+    bounds its planted edits fix (|n - m| <= ED <= k_planted)."""
+    _cache.clear()
+    t = next(g for g in GOLD["serve_trace"] if g["sigma"] == sigma and g["seed"] == seed)
+    trace = synth.arrival_trace(t["count"], seed, rate_per_s=1.0, sigmas=(sigma,))
+    say("serve trace", sigma, seed, engine, "generating")
+    with ThreadPoolExecutor(8) as ex:
+        reqs = list(ex.map(synth.request_pair, trace))
+    say("serve trace", sigma, seed, engine, "serving")
+    srv = ed.ed_serve_open(ctxs[engine], 64 << 30, 256)
+    try:
+        for tag, (A, B) in enumerate(reqs):
+            assert ed.ed_serve_submit(srv, A, B, tag) == 0, ed.ed_last_error()
+        ed.ed_serve_drain(srv)
+        res = ed.ed_serve_poll(srv, len(reqs) + 1)
+    finally:
+        ed.ed_serve_close(srv)
+    assert len(res) == len(reqs) and all(r["status"] == 0 for r in res)
+    got = {r["tag"]: r["k"] for r in res}
+    want = dict(zip(t["index"], t["eds"]))
+    bad = [i for i in want if got[i] != want[i]]
+    assert not bad, "requests %s differ from the oracle (first: got %d want %d)" % (
+        bad[:10], got[bad[0]], want[bad[0]])
+    for i, (A, B) in enumerate(reqs):
+        assert abs(len(A) - len(B)) <= got[i] <= trace[i]["k"], i
+    say("serve trace", sigma, seed, engine, "%d sampled exact, %d bounded" % (len(want), len(reqs) - len(want)))
