@@ -636,6 +636,7 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
     fp.engine = static_cast<int32_t>(p->engine);
     fp.lane_words = static_cast<int32_t>(lane_words);
     fp.block_rounds = static_cast<int32_t>(c->opt.block_rounds ? c->opt.block_rounds : kDefaultBlockRounds);
+    fp.wait_ticks = kWaitTicks;
     fp.ctl = c->d_ctl;
     fp.bar = c->d_bar;
     fp.dump = d_dump;

@@ -421,20 +421,39 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
 // waits for every flag, then publishes `epoch` in ctl->release.  Waiting
 // loops poll with relaxed loads (no cache invalidation per poll) and take one
 // acquire fence once the value arrived.
-__device__ __forceinline__ void grid_sync(FrontierCtl* ctl, unsigned int* bar, unsigned int epoch) {
+// Every wait has a deadline of `ticks` s_memrealtime ticks: a waiter that
+// reaches it sets ctl->status = 4 and goes on, so that the launch ends (with
+// that status, which the host reports as an internal error) whatever happened
+// to the workgroup it waited for.
+__device__ __forceinline__ void set_wait_error(FrontierCtl* ctl) {
+    __hip_atomic_store(&ctl->status, 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void grid_sync(FrontierCtl* ctl, unsigned int* bar, unsigned int epoch, uint64_t ticks) {
     __syncthreads();
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
     if (blockIdx.x == 0) {
         for (int g = threadIdx.x + 1; g < static_cast<int>(gridDim.x); g += blockDim.x)
-            while (__hip_atomic_load(bar + g * kBarStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch)
+            while (__hip_atomic_load(bar + g * kBarStride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+                if (__builtin_amdgcn_s_memrealtime() - t0 > ticks) {
+                    set_wait_error(ctl);
+                    break;
+                }
                 __builtin_amdgcn_s_sleep(1);
+            }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         __syncthreads();
         if (threadIdx.x == 0)
             __hip_atomic_store(&ctl->release, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else if (threadIdx.x == 0) {
         __hip_atomic_store(bar + blockIdx.x * kBarStride, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        while (__hip_atomic_load(&ctl->release, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch)
+        while (__hip_atomic_load(&ctl->release, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+            if (__builtin_amdgcn_s_memrealtime() - t0 > ticks) {
+                set_wait_error(ctl);
+                break;
+            }
             __builtin_amdgcn_s_sleep(1);
+        }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
@@ -773,8 +792,14 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
         } else {
             if (tid == 0) {
                 // relaxed polling (no cache invalidation per poll), one acquire fence
-                while (__hip_atomic_load(&ctl->phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+                const uint64_t t0 = clock_now();
+                while (__hip_atomic_load(&ctl->phase, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+                    if (clock_now() - t0 > P.wait_ticks) {
+                        set_wait_error(ctl);
+                        break;
+                    }
                     __builtin_amdgcn_s_sleep(64);
+                }
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             if (tid == 0)
@@ -791,6 +816,11 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
     // ---------------- phase B: every workgroup, H rounds per barrier ----------------
     if (!finished) {
         for (;;) {
+            // a wait gave up somewhere (set before the last barrier): every workgroup stops here
+            if (__hip_atomic_load(&ctl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 4) {
+                if (blockIdx.x == 0 && tid == 0) ctl->result_t = t;
+                break;
+            }
             // found_t only holds rounds of finished blocks once everyone passed the barrier
             const int32_t ft = __hip_atomic_load(&ctl->found_t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             int32_t status = 0, result = 0;
@@ -826,7 +856,7 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
                     round_range<kWgWords>(en, t1, gp, gc, gofs, e0 - (t1 + 2), e1 - (t1 + 2), RS, jc,
                                 dump_row_for(dump, P.dump_cap, t1), -t1, t1, cnt))
                     atomicMin(&ctl->found_t, t1);
-                grid_sync(ctl, P.bar, ++epoch);
+                grid_sync(ctl, P.bar, ++epoch, P.wait_ticks);
                 int32_t* tmp = gp;
                 gp = gc;
                 gc = tmp;
@@ -857,7 +887,7 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
                 }
                 for (int32_t i = a + tid; i <= b; i += nthr) gc[i + gofs] = rp[i + wofs];
             }
-            grid_sync(ctl, P.bar, ++epoch);
+            grid_sync(ctl, P.bar, ++epoch, P.wait_ticks);
             int32_t* tmp = gp;
             gp = gc;
             gc = tmp;

@@ -38,6 +38,11 @@ constexpr uint32_t kDefaultBlockRounds = 64;
 constexpr uint32_t kTaskDefaultLdsRounds = 1024;
 constexpr uint32_t kTaskDefaultBlockRounds = 32;
 constexpr int32_t kChunkDiags = 2048;  // diagonals per chunk task
+// a wait of the frontier kernel on another workgroup or wavefront gives up
+// after 600 s of the 100 MHz real-time clock (the launch then reports an
+// error): far beyond any wait of a working launch, so that only a launch that
+// would never end is cut
+constexpr uint64_t kWaitTicks = 60000000000ull;
 
 }  // namespace ed
 

@@ -100,6 +100,8 @@ struct FrontierParams {
     int32_t engine;
     int32_t lane_words;
     int32_t pad_;
+    uint64_t wait_ticks;  // a wait on another workgroup or wavefront gives up after this many
+                          // s_memrealtime ticks (100 MHz) and the launch ends with status 4
     FrontierCtl* ctl;
     unsigned int* bar;  // kMaxGrid lines of kBarStride uint32
     int32_t* dump;     // optional per-round rows (device), row t at t*t

@@ -272,6 +272,7 @@ FRONTIER_MODES = [
     ("blk1", dict(lds_rounds=4, block_rounds=1)),
     ("blk7g3", dict(lds_rounds=4, block_rounds=7, grid_blocks=3)),
     ("g1", dict(lds_rounds=2, block_rounds=5, grid_blocks=1)),
+    ("grid7", dict(flags=2, block_rounds=7)),
 ]
 
 
@@ -398,6 +399,29 @@ def test_long_lcps_in_phase_a(ed, make_ctx, orc, case):
         ed.ed_release(p)
         assert got == orc.lv_omp(A, B)
         assert st["wg_lcps"] > 0
+
+
+@pytest.mark.parametrize("engine", [0, 1])
+@pytest.mark.parametrize("case", ["sigma4", "sigma256", "periodic"])
+def test_long_lcps_in_grid_rounds(ed, make_ctx, orc, engine, case):
+    # every round grid-wide (no one-workgroup phase), short blocks: slides
+    # longer than the wavefront steps go to the workgroup tier (or the hash
+    # search) inside the temporal blocks
+    ctx = make_ctx(engine=engine, flags=ed.FLAG_NO_PHASE_A | ed.FLAG_TIMING, block_rounds=9)
+    if case == "sigma4":
+        specs = [(600_000, 25, 4, 11), (300_000, 700, 4, 12)]
+    elif case == "sigma256":
+        specs = [(300_000, 30, 256, 13), (200_000, 900, 256, 14)]
+    else:
+        specs = [(250_000, 150, 0, 15)]
+    for n, k, sigma, seed in specs:
+        if sigma:
+            A, B, _ = synth.single_pair(n, k, seed, sigma=sigma)
+        else:
+            A = synth.periodic_string(n, synth.CharDist("uniform", 4), seed, 64)
+            B, _ = synth.plant_edits(A, k, synth.CharDist("uniform", 4), seed + 1)
+        say("long lcps grid", engine, case, n, k)
+        assert gpu_ed(ed, ctx, A, B) == orc.lv_omp(A, B)
 
 
 # ---------------------------------------------------------------------------
