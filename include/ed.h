@@ -61,6 +61,8 @@ extern "C" {
 #define ED_FLAG_TIMING 8u      /* time the prepare and frontier kernels with HIP events */
 #define ED_FLAG_CERTIFY 16u    /* ed_distance, hash engine, no k_max: check the result as ed_align
                                 * does, and answer with the direct engine if the check fails */
+#define ED_FLAG_NO_GRID_ROUNDS 64u /* direct engine: never run the first rounds on every workgroup
+                                   * (the grid tier for very long slides); workgroup 0 alone */
 #define ED_FLAG_WEAK_HASH 32u  /* fault injection for tests: hash base r = 1 (every permutation of
                                 * a string hashes alike), so that collisions happen */
 

@@ -16,23 +16,30 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_SANITIZED=1 loads the AddressSanitizer / UndefinedBehaviorSanitizer
+# build instead (the process must preload libasan; see tests/test_oracle_sanitized.py)
+_SANITIZED = os.environ.get("ORACLE_SANITIZED") == "1"
+_LIB = os.path.join(_HERE, "liboracle_san.so" if _SANITIZED else "liboracle.so")
 
 NONE = -(1 << 30)
 
 _lib = None
 
 
-def build(force=True):
-    """Compile liboracle.so (gcc -O2 -fopenmp)."""
-    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
-        return _LIB
-    tmp = _LIB + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-o", tmp, _SRC]
-    subprocess.check_call(cmd)
-    os.replace(tmp, _LIB)
-    return _LIB
+def build(force=True, sanitized=None):
+    """Compile liboracle.so (gcc -O2 -fopenmp), or with sanitized=True the
+    AddressSanitizer + UndefinedBehaviorSanitizer build liboracle_san.so."""
+    san = _SANITIZED if sanitized is None else sanitized
+    lib = os.path.join(_HERE, "liboracle_san.so" if san else "liboracle.so")
+    if not force and os.path.exists(lib) and os.path.getmtime(lib) >= os.path.getmtime(_SRC):
+        return lib
+    tmp = lib + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra"]
+    if san:
+        cmd += ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+    subprocess.check_call(cmd + ["-o", tmp, _SRC])
+    os.replace(tmp, lib)
+    return lib
 
 
 def _load():

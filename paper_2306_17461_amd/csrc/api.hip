@@ -287,7 +287,8 @@ int ed_init(ed_ctx** out, int device, const ed_options* opt) {
         hipMalloc(&c->d_cnt, sizeof(CountersDev) * (kMaxGrid + 1)) != hipSuccess ||
         hipHostMalloc(&c->h_ctl, sizeof(FrontierCtl)) != hipSuccess ||
         hipHostMalloc(&c->h_cnt, sizeof(CountersDev)) != hipSuccess ||
-        hipMalloc(&c->d_bar, static_cast<size_t>(kMaxGrid) * kBarStride * 4) != hipSuccess) {
+        hipMalloc(&c->d_bar, static_cast<size_t>(kMaxGrid) * kBarStride * 4) != hipSuccess ||
+        hipMalloc(&c->d_gpart, static_cast<size_t>(2) * kGridJobs * kMaxGrid * 4) != hipSuccess) {
         set_error("ed_init: allocation failed");
         ed_shutdown(c);
         return ED_ENOMEM;
@@ -336,6 +337,7 @@ int ed_shutdown(ed_ctx* c) {
     if (c->d_ctl) (void)hipFree(c->d_ctl);
     if (c->d_cnt) (void)hipFree(c->d_cnt);
     if (c->d_bar) (void)hipFree(c->d_bar);
+    if (c->d_gpart) (void)hipFree(c->d_gpart);
     if (c->h_ctl) (void)hipHostFree(c->h_ctl);
     if (c->h_cnt) (void)hipHostFree(c->h_cnt);
     for (hipEvent_t& e : c->ev)
@@ -637,6 +639,8 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
     fp.lane_words = static_cast<int32_t>(lane_words);
     fp.block_rounds = static_cast<int32_t>(c->opt.block_rounds ? c->opt.block_rounds : kDefaultBlockRounds);
     fp.wait_ticks = kWaitTicks;
+    fp.grid_rounds = (p->engine == ED_ENGINE_DIRECT && !(c->opt.flags & ED_FLAG_NO_GRID_ROUNDS)) ? 1 : 0;
+    fp.gpart = c->d_gpart;
     fp.ctl = c->d_ctl;
     fp.bar = c->d_bar;
     fp.dump = d_dump;

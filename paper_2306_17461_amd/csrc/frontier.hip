@@ -39,7 +39,7 @@ namespace ed {
 namespace {
 
 constexpr int kU = 2;          // diagonals per thread per pass
-constexpr int kJobHalf = 128;  // queued LCPs per round (a ring of two halves)
+constexpr int kJobHalf = kGridJobs;  // queued LCPs per round (a ring of two halves)
 constexpr int kWaveSteps = 2;  // wavefront steps before the hash search / workgroup tier
 constexpr int kWgWords = 8;      // words per thread per workgroup-tier step (single pair)
 constexpr int kWgWordsTask = 4;  // ... in the many-pair kernel (register budget)
@@ -52,6 +52,8 @@ struct RoundShared {
     int32_t jl[2 * kJobHalf];
     int32_t jcount[2];  // monotonic job counters, one per round parity
     int32_t wmin;       // workgroup-tier reduction slot
+    int32_t gmin;       // grid rounds: this workgroup's first mismatch of a job
+    int32_t jorder[kJobHalf];  // grid rounds: queued jobs in increasing diagonal order
     int32_t hres;       // hash engine: result of wavefront 0's search for the workgroup
     int32_t hskip;      // hash engine: the last searched LCP outran the direct steps
     int32_t flag;
@@ -284,7 +286,7 @@ template <int WGW, typename PrevPtr, typename CurPtr>
 __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr prev, CurPtr cur,
                                             int32_t ofs, int32_t i_begin, int32_t i_end, RoundShared& RS,
                                             JobCursor& jc, int32_t* dump_row, int32_t dlo, int32_t dhi,
-                                            Cnt& cnt) {
+                                            Cnt& cnt, int32_t* deferred = nullptr) {
     const int tid = threadIdx.x;
     constexpr int nthr = kFrontierThreads;  // every launch of the round kernels
     const int lane = tid & 63;
@@ -392,6 +394,14 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
     const int32_t jend = RS.jcount[par];
     const int32_t nj = imin(jend - jstart, kJobHalf);
     jc.start[par] = jend;
+    if (deferred) {
+        // the caller extends the queued LCPs (entries [half, half + nj) of the
+        // queue), unless the queue overflowed: then which LCPs it holds depends
+        // on the order the wavefronts pushed them, and the workgroup tier
+        // takes them here
+        *deferred = jend - jstart <= kJobHalf ? nj : 0;
+        if (*deferred) return found;
+    }
     if (nj > 0) {
         for (int j = 0; j < nj; ++j) {
             const int32_t jx = RS.jx[half + j];
@@ -704,6 +714,87 @@ __device__ void chunk_task(const TaskParams& P, int32_t pi, int32_t c, LdsState&
 
 __device__ __forceinline__ uint64_t clock_now() { return __builtin_amdgcn_s_memrealtime(); }
 
+// ---------------------------------------------------------------------------
+// Grid rounds (direct engine): for pairs whose slides run far past a
+// workgroup step (a pair within few edits of identity), the first rounds run
+// on every workgroup at once.  Each workgroup computes the whole (narrow)
+// frontier in its LDS, the same values in every one; the slides that run past
+// the wavefront steps are queued, and every workgroup takes its static share
+// of the segments of each queued slide (grid_segments over the wavefronts of
+// the launch), keeps its own first mismatch and stores it in its slot of
+// `part`.  One device-wide barrier later every workgroup reduces the slots of
+// each job and completes the same row.  No workgroup waits on another except
+// at that barrier, and only rounds with queued slides pay it.
+// ---------------------------------------------------------------------------
+template <typename CurPtr>
+__device__ __forceinline__ bool grid_round_jobs(const Engine& en, int32_t t, CurPtr cur, int32_t ofs, int32_t nj,
+                                                RoundShared& RS, int32_t* part, int32_t active_waves,
+                                                int32_t* dump_row, FrontierCtl* ctl, unsigned int* bar,
+                                                unsigned int& epoch, uint64_t ticks, Cnt& cnt, int32_t& longest) {
+    const int tid = threadIdx.x;
+    const int G = static_cast<int>(gridDim.x);
+    const int32_t n = en.A.len, m = en.B.len, target = n - m;
+    const int half = (t & 1) * kJobHalf;
+    // this wavefront's place among the wavefronts of the launch, workgroups
+    // first, so that the active ones spread over the compute units
+    const int32_t wg = (tid >> 6) * G + static_cast<int32_t>(blockIdx.x);
+    // the jobs in increasing diagonal order: every workgroup queued the same
+    // LCPs, in an order that depends on its wavefronts' timing
+    if (tid < nj) {
+        const int32_t mine = RS.ji[half + tid];
+        int32_t rank = 0;
+        for (int k = 0; k < nj; ++k) rank += RS.ji[half + k] < mine ? 1 : 0;
+        RS.jorder[rank] = tid;
+    }
+    __syncthreads();
+    // two sets of slots, by the parity of the barrier: a workgroup writes the
+    // set of the next barrier only after passing the previous one, which
+    // every workgroup reaches only after reading the set it wrote before
+    part += ((epoch + 1) & 1) * kGridJobs * kMaxGrid;
+    for (int j = 0; j < nj; ++j) {
+        const int q = half + RS.jorder[j];
+        const int32_t jx = RS.jx[q], jy = RS.jy[q], jlim = RS.jlim[q], jl = RS.jl[q];
+        if (tid == 0) RS.gmin = INT_MAX;
+        __syncthreads();
+        if (wg < active_waves) grid_segments<16>(en.A, en.B, jx, jy, jlim, jl, wg, active_waves, &RS.gmin);
+        __syncthreads();
+        if (tid == 0) part[j * kMaxGrid + static_cast<int>(blockIdx.x)] = RS.gmin;
+    }
+    grid_sync(ctl, bar, ++epoch, ticks);
+    bool found = false;
+    int32_t lmax = 0;
+    for (int j = 0; j < nj; ++j) {
+        // the first mismatch over every workgroup's share
+        int32_t v = INT_MAX;
+        for (int g = tid; g < G; g += kFrontierThreads) v = imin(v, part[j * kMaxGrid + g]);
+        v = wave_min(v);
+        if (tid == 0) RS.gmin = INT_MAX;
+        __syncthreads();
+        if ((tid & 63) == 0 && v != INT_MAX) atomicMin(&RS.gmin, v);
+        __syncthreads();
+        const int q = half + RS.jorder[j];
+        const int32_t jx = RS.jx[q], jlim = RS.jlim[q];
+        const int32_t r = imin(RS.gmin, jlim);
+        lmax = imax(lmax, r);
+        if (tid == 0) {
+            const int32_t i = RS.ji[q];
+            const int32_t f = jx + r;
+            cur[i + ofs] = f;
+            if (dump_row) dump_row[i + t] = f;
+            cnt.updates++;
+            atomicAdd(&cnt.sh->grid_lcps, 1ull);
+            cnt.lcp_chars += static_cast<unsigned long long>(r);
+            if (i == target && f == n) {
+                found = true;
+                RS.flag = 1;
+            }
+        }
+        __syncthreads();
+    }
+    longest = lmax;
+    return found;
+}
+
 }  // namespace
 
 __global__ void ctl_init_kernel(FrontierCtl* ctl, CountersDev* cnt, unsigned int* bar) {
@@ -755,14 +846,93 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
     if (blockIdx.x == 0 && tid == 0) ctl->clk_begin = clock_now();
 
     if (P.t0 == 0) {
-        // ---------------- phase A: workgroup 0, rows in LDS ----------------
-        if (blockIdx.x == 0) {
-            const int32_t off = kLdsRoundsMax + 2;  // diagonal i at row[i + off]
-            int32_t* la = L.row[0];
-            int32_t* lb = L.row[1];
-            round_range<kWgWords>(en, 0, la, la, off, -2, 3, RS, jc, dump && P.dump_cap >= 1 ? dump : nullptr, 0, 0, cnt);
-            const int32_t lr = imin(imin(P.lds_rounds, kLdsRoundsMax), K);
-            int32_t status = 0, result = 0;
+        const int32_t off = kLdsRoundsMax + 2;  // diagonal i at row[i + off]
+        int32_t* la = L.row[0];
+        int32_t* lb = L.row[1];
+        const int32_t lr = imin(imin(P.lds_rounds, kLdsRoundsMax), K);
+        int32_t status = 0, result = 0;
+        bool started = false;  // round 0 done by the grid rounds
+        bool to_b = false;     // the grid rounds reached the end of the LDS phase
+        // ---------------- grid rounds: every workgroup, rows in LDS ----------------
+        if (KIND == 0 && P.grid_rounds) {
+            // slides longer than this keep the grid rounds going: about 16
+            // workgroup-tier steps (4M characters at 2 bits), where a round of
+            // the grid tier (one pass of segments, one barrier, the
+            // reduction; about 15-30 us here) beats the workgroup's dependent
+            // steps (about 3.5 us each)
+            const int32_t big = (128 * kFrontierThreads) << en.A.lcpw;
+            const int32_t span = (64 * 16) << en.A.lcpw;  // one wavefront's segment
+            const int32_t all_waves = G * (kFrontierThreads >> 6);
+            int32_t* const dump0 = blockIdx.x == 0 ? dump : nullptr;
+            int32_t nj = 0, longest = 0, quiet = 0, est = INT_MAX;
+            auto resolve = [&](int32_t tt, int32_t* cur, int32_t* drow) {
+                longest = 0;
+                if (nj > 0) {
+                    // wavefronts for about twice the longest slide of the last round
+                    const int64_t need = est == INT_MAX ? all_waves : 2 * (static_cast<int64_t>(est) / span + 1);
+                    const int32_t aw = static_cast<int32_t>(need < 64 ? 64 : (need > all_waves ? all_waves : need));
+                    grid_round_jobs(en, tt, cur, off, nj, RS, P.gpart, aw, drow, ctl, P.bar, epoch, P.wait_ticks,
+                                    cnt, longest);
+                    est = longest;
+                }
+            };
+            round_range<kWgWords>(en, 0, la, la, off, -2, 3, RS, jc, dump0 && P.dump_cap >= 1 ? dump0 : nullptr, 0, 0,
+                                  cnt, &nj);
+            resolve(0, la, dump0 && P.dump_cap >= 1 ? dump0 : nullptr);
+            started = true;
+            for (;;) {
+                if (RS.flag) { status = 1; result = t; break; }
+                if (P.kmax >= 0 && t >= P.kmax) { status = 2; result = P.kmax + 1; break; }
+                if (t > maxnm) { status = 4; result = t; break; }
+                if (__hip_atomic_load(&ctl->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 4) {
+                    status = 4;
+                    result = t;
+                    break;
+                }
+                quiet = longest >= big ? 0 : quiet + 1;
+                if (t == 0 ? quiet > 0 : quiet >= 8) break;  // back to one workgroup
+                if (t >= lr) {
+                    to_b = true;
+                    break;
+                }
+                ++t;
+                round_range<kWgWords>(en, t, la, lb, off, -(t + 2), t + 3, RS, jc, dump_row_for(dump0, P.dump_cap, t),
+                                      -t, t, cnt, &nj);
+                resolve(t, lb, dump_row_for(dump0, P.dump_cap, t));
+                int32_t* tmp = la;
+                la = lb;
+                lb = tmp;
+            }
+            if (blockIdx.x != 0) {
+                // the same rounds as workgroup 0: counted there only
+                __syncthreads();
+                cnt.updates = cnt.lcp_chars = cnt.ne_len = 0;
+                cnt_init_shared(&L.cnt);
+                __syncthreads();
+            }
+            if (status != 0 || to_b) {
+                if (to_b && blockIdx.x == 0)
+                    for (int32_t e = tid; e < 2 * t + 5; e += nthr) gp[gofs + e - (t + 2)] = la[off + e - (t + 2)];
+                if (blockIdx.x == 0 && tid == 0) {
+                    ctl->clk_switch = clock_now();
+                    ctl->phase_t = t;
+                    if (status != 0) {
+                        ctl->result_t = result;
+                        __hip_atomic_store(&ctl->status, status, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                }
+                finished = status != 0;
+                // the row of round t is read by every workgroup in phase B
+                if (to_b) grid_sync(ctl, P.bar, ++epoch, P.wait_ticks);
+            }
+        }
+        if (status != 0 || to_b) {
+            // (decided alike by every workgroup in the grid rounds)
+        } else if (blockIdx.x == 0) {
+            // ---------------- phase A: workgroup 0, rows in LDS ----------------
+            if (!started)
+                round_range<kWgWords>(en, 0, la, la, off, -2, 3, RS, jc, dump && P.dump_cap >= 1 ? dump : nullptr, 0,
+                                      0, cnt);
             for (;;) {
                 if (RS.flag) { status = 1; result = t; break; }
                 if (P.kmax >= 0 && t >= P.kmax) { status = 2; result = P.kmax + 1; break; }

@@ -62,6 +62,7 @@ struct ed_ctx {
     hipEvent_t ev[2] = {nullptr, nullptr};  // frontier timing
     unsigned int* d_bar = nullptr;          // device-wide barrier flags
     int32_t* d_scratch = nullptr;           // this device's scratch array (ed_distance_noalloc)
+    int32_t* d_gpart = nullptr;             // grid rounds: per-workgroup first mismatches of queued LCPs
     ed::DevPool pool;
 };
 

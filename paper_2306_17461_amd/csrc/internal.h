@@ -86,6 +86,8 @@ struct FrontierCtl {
 // Device-wide barrier flags: one 128-byte line per workgroup.
 constexpr int kBarStride = 32;  // uint32 per line
 constexpr int kMaxGrid = 1024;
+// LCPs queued per round for the workgroup or grid tier
+constexpr int kGridJobs = 128;
 
 struct FrontierParams {
     PairDev p;
@@ -99,11 +101,12 @@ struct FrontierParams {
     int32_t block_rounds;  // grid-wide phase: rounds between device-wide barriers
     int32_t engine;
     int32_t lane_words;
-    int32_t pad_;
+    int32_t grid_rounds;  // 1: the first rounds may run on every workgroup (direct engine)
     uint64_t wait_ticks;  // a wait on another workgroup or wavefront gives up after this many
                           // s_memrealtime ticks (100 MHz) and the launch ends with status 4
     FrontierCtl* ctl;
     unsigned int* bar;  // kMaxGrid lines of kBarStride uint32
+    int32_t* gpart;     // grid rounds: 2 x kGridJobs x kMaxGrid per-workgroup first mismatches
     int32_t* dump;     // optional per-round rows (device), row t at t*t
     int64_t dump_cap;
     CountersDev* counters;

@@ -398,7 +398,8 @@ def test_long_lcps_in_phase_a(ed, make_ctx, orc, case):
         st = ed.ed_pair_stats(p)
         ed.ed_release(p)
         assert got == orc.lv_omp(A, B)
-        assert st["wg_lcps"] > 0
+        # extended by the workgroup tier, or by every workgroup (grid rounds)
+        assert st["wg_lcps"] + st["grid_lcps"] > 0
 
 
 @pytest.mark.parametrize("engine", [0, 1])
@@ -422,6 +423,51 @@ def test_long_lcps_in_grid_rounds(ed, make_ctx, orc, engine, case):
             B, _ = synth.plant_edits(A, k, synth.CharDist("uniform", 4), seed + 1)
         say("long lcps grid", engine, case, n, k)
         assert gpu_ed(ed, ctx, A, B) == orc.lv_omp(A, B)
+
+
+@pytest.mark.parametrize("case", ["sigma4", "sigma256", "force8", "to_grid_blocks", "kmax", "grow"])
+def test_grid_rounds(ed, make_ctx, orc, case):
+    # pairs within few edits of identity: slides far past a workgroup step,
+    # extended by every workgroup in the first rounds (direct engine); the
+    # same distances with those rounds switched off, and equal to the oracle
+    kw = {"sigma4": {}, "sigma256": {}, "force8": dict(pack_bits=8),
+          "to_grid_blocks": dict(lds_rounds=2, block_rounds=3), "kmax": {},
+          "grow": dict(lds_rounds=8, init_rows=6)}[case]
+    ctx = make_ctx(flags=ed.FLAG_TIMING, **kw)
+    ref = make_ctx(flags=ed.FLAG_TIMING | ed.FLAG_NO_GRID_ROUNDS, **kw)
+    sigma = 256 if case == "sigma256" else 4
+    specs = {"to_grid_blocks": [(24_000_000, 3, 7)], "grow": [(24_000_000, 4, 8)]}.get(
+        case, [(6_000_000, 0, 1), (6_000_000, 1, 2), (5_000_000, 5, 3), (30_000_000, 3, 4)])
+    for n, k, seed in specs:
+        A, B, _ = synth.single_pair(n, k, seed, sigma=sigma)
+        want = orc.lv_omp(A, B)
+        say("grid rounds", case, n, k, want)
+        kmax = max(want // 2, 0) if case == "kmax" else -1
+        p = ed.ed_prepare(ctx, A, B)
+        got = ed.ed_distance(ctx, p, kmax)
+        st = ed.ed_pair_stats(p)
+        ed.ed_release(p)
+        q = ed.ed_prepare(ref, A, B)
+        alone = ed.ed_distance(ref, q, kmax)
+        ed.ed_release(q)
+        expect = want if kmax < 0 or want <= kmax else kmax + 1
+        assert got == alone == expect
+        # the first slide runs past the wavefront steps: extended by the grid
+        assert st["grid_lcps"] > 0
+
+
+def test_grid_rounds_alignment(ed, make_ctx, orc):
+    # the per-round rows that the grid rounds write back are traced and checked
+    ctx = make_ctx()
+    A, B, _ = synth.single_pair(6_000_000, 7, 21)
+    want = orc.lv_omp(A, B)
+    p = ed.ed_prepare(ctx, A, B)
+    try:
+        k, script = ed.ed_align(ctx, p)
+    finally:
+        ed.ed_release(p)
+    assert k == want
+    assert sum(ln for op, ln in script if op != ed.OP_MATCH) == k
 
 
 # ---------------------------------------------------------------------------
