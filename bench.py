@@ -448,13 +448,167 @@ def serve_leg(ed, ctx, count, seed=0, warmup=0):
         p50_, p99_ = pct([b for _, b in v])
         by[key] = {"requests": len(v), "served_p50_s": s50, "served_p99_s": s99,
                    "per_pair_p50_s": p50_, "per_pair_p99_s": p99_}
-    return {"workload": "%d requests, Poisson arrivals, n log-uniform [1e2, 1e7], alphabet 4 or 20, "
-                        "k uniform [0, 0.05 n], seed %d" % (count, seed),
+    return {"workload": "quick check: %d requests, Poisson arrivals, n log-uniform [1e2, 1e7], alphabet 4 or "
+                        "20, k uniform [0, 0.05 n], seed %d (the serving workload at its measured size is "
+                        "bench.py --serve-full)" % (count, seed),
             "arrival_rate_per_s": rate, "batched_pairs_per_s": count / tb,
             "served": {"pairs_per_s": count / span, "p50_s": p50, "p99_s": p99},
             "per_pair": {"pairs_per_s": count / span2, "p50_s": q50, "p99_s": q99},
             "latency_by_bucket": by,
             "equal_to_stored_oracle": exact}
+
+
+def serve_full(ed, seeds=(0, 1, 2), sigmas=(4, 20), count=2200, warmup=200, per_pair_seeds=(0,)):
+    """The serving workload at its measured size: for each alphabet (4, 20) and
+    trace seed, `count` requests (Poisson arrivals, n log-uniform in [1e2, 1e7],
+    k uniform in [0, 0.05 n]), the first `warmup` of them excluded from the
+    latency and throughput figures.  The arrival rate is 0.7x the batched
+    throughput of the seed-0 trace of the alphabet (ed_batch over all its
+    requests, prepared).  Served (continuous batching) on every trace; the
+    per-pair form (one request at a time, prepare + ed_distance) on the same
+    arrival times for the seeds in per_pair_seeds.  Every sampled request is
+    compared with the stored oracle value, the others with the bounds of their
+    planted edits."""
+    import threading
+    from concurrent.futures import ThreadPoolExecutor
+    import numpy as np
+    import synth
+    gold = stored_oracle() or {}
+    traces = {(t["sigma"], t["seed"]): t for t in gold.get("serve_trace", [])}
+    ctx = ed.ed_init(0, engine=ed.ENGINE_DIRECT)
+    out = {"workload": "%d requests per trace (%d warm-up), Poisson arrivals, n log-uniform [1e2, 1e7], "
+                       "k uniform [0, 0.05 n], one alphabet per trace" % (count, warmup), "runs": []}
+
+    def pct(lat):
+        lat = np.asarray(lat)
+        return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+
+    def check(sigma, seed, trace, reqs, got):
+        t = traces.get((sigma, seed))
+        if t is None or t["count"] != count:
+            return None
+        want = dict(zip(t["index"], t["eds"]))
+        for i, (A, B) in enumerate(reqs):
+            if i in want and got[i] != want[i]:
+                raise SystemExit("serve: request %d of sigma=%d seed=%d: %d, oracle %d" % (i, sigma, seed, got[i], want[i]))
+            if not (abs(len(A) - len(B)) <= got[i] <= trace[i]["k"]):
+                raise SystemExit("serve: request %d outside its planted-edit bounds" % i)
+        return {"sampled_equal_to_oracle": len(want), "bounded": count - len(want)}
+
+    for sigma in sigmas:
+        rate = None
+        for seed in seeds:
+            trace = synth.arrival_trace(count, seed, rate_per_s=1.0, sigmas=(sigma,))
+            log("serve full: sigma=%d seed=%d generating" % (sigma, seed))
+            with ThreadPoolExecutor(8) as ex:
+                reqs = list(ex.map(synth.request_pair, trace))
+            if rate is None:
+                pairs = [ed.ed_prepare(ctx, A, B) for A, B in reqs]
+                t0 = time.perf_counter()
+                ed.ed_batch(ctx, pairs)
+                tb = time.perf_counter() - t0
+                for p in pairs:
+                    ed.ed_release(p)
+                batched = count / tb
+                rate = 0.7 * batched
+                log("serve full: sigma=%d batched %.1f pairs/s -> arrival rate %.1f /s" % (sigma, batched, rate))
+            gaps = np.diff([0.0] + [r["t_arrive_s"] for r in trace])
+            arrive = np.cumsum(gaps / rate)
+            # served
+            srv = ed.ed_serve_open(ctx, 128 << 30, 256)
+            start = time.perf_counter()
+
+            def submit():
+                for i, (A, B) in enumerate(reqs):
+                    d = start + arrive[i] - time.perf_counter()
+                    if d > 0:
+                        time.sleep(d)
+                    ed.ed_serve_submit(srv, A, B, i)
+
+            th = threading.Thread(target=submit)
+            th.start()
+            th.join()
+            ed.ed_serve_drain(srv)
+            res = ed.ed_serve_poll(srv, count + 1)
+            ed.ed_serve_close(srv)
+            if len(res) != count or any(r["status"] != 0 for r in res):
+                raise SystemExit("serve full: a request failed")
+            got = {r["tag"]: r["k"] for r in res}
+            exact = check(sigma, seed, trace, reqs, got)
+            meas = [r for r in res if r["tag"] >= warmup]
+            lat = [(r["t_done_ns"] - r["t_arrive_ns"]) / 1e9 for r in meas]
+            span = (max(r["t_done_ns"] for r in meas) - min(r["t_arrive_ns"] for r in meas)) / 1e9
+            p50, p99 = pct(lat)
+            run = {"sigma": sigma, "seed": seed, "arrival_rate_per_s": round(rate, 2),
+                   "served": {"pairs_per_s": round((count - warmup) / span, 2), "p50_s": p50, "p99_s": p99},
+                   "exactness": exact}
+            if seed in per_pair_seeds:
+                start = time.perf_counter()
+                lat2, done_t = [], []
+                for i, (A, B) in enumerate(reqs):
+                    d = start + arrive[i] - time.perf_counter()
+                    if d > 0:
+                        time.sleep(d)
+                    p = ed.ed_prepare(ctx, A, B)
+                    k = ed.ed_distance(ctx, p)
+                    ed.ed_release(p)
+                    if k != got[i]:
+                        raise SystemExit("serve full: per-pair distance differs")
+                    now = time.perf_counter()
+                    if i >= warmup:
+                        lat2.append(now - (start + arrive[i]))
+                        done_t.append(now)
+                q50, q99 = pct(lat2)
+                span2 = max(done_t) - (start + arrive[warmup])
+                run["per_pair"] = {"pairs_per_s": round((count - warmup) / span2, 2), "p50_s": q50, "p99_s": q99}
+            log("serve full: %s" % json.dumps(run))
+            out["runs"].append(run)
+    ed.ed_shutdown(ctx)
+    return out
+
+
+def config3_leg(ed, seeds=(0, 1, 2)):
+    """The n = 1e9 pairs (Zipf(1.0) over 256 symbols and its period-64
+    variant, k in {1e3, 1e5}, seeds 0..2), both engines, from device-resident
+    inputs: prepare and frontier kernel times (HIP events), chars/s over the
+    host wall time, equal to the stored oracle values."""
+    import torch
+    import synth
+    gold = stored_oracle() or {}
+    want = {(g["periodic"], g["k"], g["seed"]): g["ed"] for g in gold.get("big", [])}
+    ctxs = {"direct": ed.ed_init(0, engine=ed.ENGINE_DIRECT, flags=ed.FLAG_TIMING),
+            "hash": ed.ed_init(0, engine=ed.ENGINE_HASH, flags=ed.FLAG_TIMING)}
+    rows = []
+    for seed in seeds:
+        for periodic in (False, True):
+            for k in (1000, 100000):
+                A, B, _ = synth.single_pair(10 ** 9, k, seed, sigma=256, kind="zipf", periodic=periodic)
+                tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+                del A, B
+                for name, ctx in ctxs.items():
+                    log("config3: %s k=%d seed=%d %s" % ("periodic" if periodic else "zipf", k, seed, name))
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    p = ed.ed_prepare(ctx, tA, tB)
+                    d = ed.ed_distance(ctx, p)
+                    wall = time.perf_counter() - t0
+                    st = ed.ed_pair_stats(p)
+                    ed.ed_release(p)
+                    w = want.get((periodic, k, seed))
+                    if w is not None and w != d:
+                        raise SystemExit("config3: distance %d, oracle %d" % (d, w))
+                    rows.append({"kind": "periodic64" if periodic else "zipf", "k_planted": k, "seed": seed,
+                                 "engine": name, "ed": d, "equal_to_stored_oracle": None if w is None else True,
+                                 "prepare_kernel_ms": round(st["gpu_ns_prepare_kernel"] / 1e6, 3),
+                                 "frontier_kernel_ms": round(st["gpu_ns_frontier_kernel"] / 1e6, 3),
+                                 "wall_ms": round(wall * 1e3, 3), "chars_per_s": 10 ** 9 / wall,
+                                 "collision_bound": st["collision_bound"] if name == "hash" else None})
+                del tA, tB
+                torch.cuda.empty_cache()
+    for c in ctxs.values():
+        ed.ed_shutdown(c)
+    return {"workload": "n=1e9, Zipf(1.0) over 256 symbols and its period-64 variant, k in {1e3, 1e5}, seeds %s, "
+                        "8 bits per character, from device-resident inputs" % list(seeds), "runs": rows}
 
 
 def pair_stats(ed, pair):
@@ -489,6 +643,9 @@ def main():
                     help="skip the engine matrix (direct 8-bit, hash b=1, hash block sweep)")
     ap.add_argument("--serve", type=int, default=40, metavar="N",
                     help="requests of the serving leg (0 skips it)")
+    ap.add_argument("--no-config3", action="store_true", help="skip the n=1e9 Zipf / periodic leg")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="only the serving workload at its measured size (6 traces of 2200 requests)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -512,6 +669,9 @@ def main():
         return
     import synth
     import paper_2306_17461_amd as ed
+    if args.serve_full:
+        print(json.dumps({"serve_full": serve_full(ed)}))
+        return
 
     ks = [int(x) for x in args.ks.split(",")]
     n = args.n
@@ -693,6 +853,9 @@ def main():
     table = None
     if not args.no_table:
         table = table_leg(ed)
+    config3 = None
+    if not args.no_config3 and n == N:
+        config3 = config3_leg(ed)
     serve = None
     if args.serve > 0:
         serve = serve_leg(ed, ctxs["direct"], args.serve)
@@ -756,7 +919,8 @@ def main():
         "batch": batch,
         "lcp_extension": lcp,
         "table_build_8bit": table,
-        "serve": serve,
+        "config3_n1e9": config3,
+        "serve_quick": serve,
     }
     print(json.dumps(line))
 

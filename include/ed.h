@@ -323,12 +323,20 @@ typedef struct ed_result {
 /* Opens a request loop on the context: requests are admitted while their
  * device bytes fit in hbm_budget_bytes and a slot is free (max_slots); admitted
  * requests advance together in shared launches, and finished slots are refilled
- * between launches (continuous batching). */
+ * between launches (continuous batching).  The copies and packing of newly
+ * admitted requests run on a second stream while the current launch runs. */
 int ed_serve_open(ed_ctx *ctx, uint64_t hbm_budget_bytes, uint32_t max_slots, ed_server **out);
 /* Copies the strings (host memory) and queues the request.  ED_EBUSY if the
  * host queue is full; ED_ENOMEM if the request alone exceeds the budget. */
 int ed_serve_submit(ed_server *srv, const uint8_t *A, uint64_t n, const uint8_t *B, uint64_t m,
                     uint64_t tag);
+/* As ed_serve_submit, with a bound of its own for this request: k_max >= 0
+ * stops it after round k_max (the band |x - y| <= k_max of section 3.1), and
+ * its result k is then k_max + 1 when the distance is larger (status ED_OK);
+ * its frontier rows are sized for at most k_max rounds.  k_max = -1: no bound.
+ * ED_EINVAL for k_max < -1. */
+int ed_serve_submit_band(ed_server *srv, const uint8_t *A, uint64_t n, const uint8_t *B, uint64_t m,
+                         uint64_t tag, int64_t k_max);
 /* Moves up to max finished results into out; *got receives their number. */
 int ed_serve_poll(ed_server *srv, ed_result *out, uint32_t max, uint32_t *got);
 /* Blocks until every submitted request has finished. */

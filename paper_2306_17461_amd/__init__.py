@@ -101,7 +101,7 @@ EXPORTS = [
     "ed_shutdown", "ed_prepare", "ed_release", "ed_distance", "ed_distance_noalloc", "ed_distance_dump", "ed_align", "ed_batch",
     "ed_autotune_batch", "ed_pair_stats", "ed_pair_buffer", "ed_debug_lcp", "ed_debug_check_runs",
     "ed_debug_mem_latency", "ed_serve_open",
-    "ed_serve_submit",
+    "ed_serve_submit", "ed_serve_submit_band",
     "ed_serve_poll", "ed_serve_drain", "ed_serve_close", "ed_strerror", "ed_last_error",
 ]
 
@@ -138,6 +138,7 @@ def _load():
         "ed_debug_mem_latency": (i32, [vp, u64, ctypes.c_uint32, i32, P(ctypes.c_double)]),
         "ed_serve_open": (i32, [vp, u64, ctypes.c_uint32, P(vp)]),
         "ed_serve_submit": (i32, [vp, vp, u64, vp, u64, u64]),
+        "ed_serve_submit_band": (i32, [vp, vp, u64, vp, u64, u64, i64]),
         "ed_serve_poll": (i32, [vp, P(ed_result), ctypes.c_uint32, P(ctypes.c_uint32)]),
         "ed_serve_drain": (i32, [vp]),
         "ed_serve_close": (i32, [vp]),
@@ -370,6 +371,13 @@ def ed_serve_submit(srv, A, B, tag):
     B = np.ascontiguousarray(B, dtype=np.uint8)
     return lib.ed_serve_submit(srv, A.ctypes.data if A.size else None, A.size,
                                B.ctypes.data if B.size else None, B.size, tag)
+
+
+def ed_serve_submit_band(srv, A, B, tag, k_max):
+    A = np.ascontiguousarray(A, dtype=np.uint8)
+    B = np.ascontiguousarray(B, dtype=np.uint8)
+    return lib.ed_serve_submit_band(srv, A.ctypes.data if A.size else None, A.size,
+                                    B.ctypes.data if B.size else None, B.size, tag, k_max)
 
 
 def ed_serve_poll(srv, max_results=1024):

@@ -92,8 +92,8 @@ bool schedule_on_host(TaskPair& tp, int32_t pi, int32_t block_rounds, int32_t ch
     return true;
 }
 
-int tasks_run(ed_ctx* c, std::vector<TaskPair>& st, const std::vector<long long>& first, int64_t k_max,
-              uint32_t engine, hipStream_t s) {
+int tasks_start(ed_ctx* c, const std::vector<TaskPair>& st, const std::vector<long long>& first, uint32_t engine,
+                hipStream_t s, TaskRun& run) {
     const uint64_t count = st.size();
     const uint32_t solo = task_solo_rounds(c);
     const int32_t C = chunk_diags_of(c);
@@ -105,12 +105,12 @@ int tasks_run(ed_ctx* c, std::vector<TaskPair>& st, const std::vector<long long>
     const size_t pairs_bytes = count * sizeof(TaskPair);
     const size_t head = (pairs_bytes + 255) & ~size_t(255);
     const size_t qbytes = qcap * 16;
-    void* blk = c->pool.get(head + qbytes + 256);
-    if (!blk) {
+    run.blk = c->pool.get(head + qbytes + 256);
+    if (!run.blk) {
         set_error("ed_batch: device allocation failed");
         return ED_ENOMEM;
     }
-    char* base = static_cast<char*>(blk);
+    char* base = static_cast<char*>(run.blk);
     TaskParams tp;
     std::memset(&tp, 0, sizeof tp);
     tp.pairs = reinterpret_cast<TaskPair*>(base);
@@ -121,7 +121,7 @@ int tasks_run(ed_ctx* c, std::vector<TaskPair>& st, const std::vector<long long>
     tp.remaining = reinterpret_cast<int32_t*>(tp.qhead + 2);
     tp.qcap = static_cast<uint32_t>(qcap);
     tp.count = static_cast<int32_t>(count);
-    tp.kmax = k_max >= 0 ? static_cast<int32_t>(std::min<int64_t>(k_max, INT32_MAX - 1)) : -1;
+    tp.kmax = -1;  // per pair (TaskPair::kmax)
     tp.engine = static_cast<int32_t>(engine);
     tp.lane_words = static_cast<int32_t>(c->opt.lane_words ? c->opt.lane_words : 2u);
     tp.solo_rounds = static_cast<int32_t>(solo);
@@ -129,34 +129,58 @@ int tasks_run(ed_ctx* c, std::vector<TaskPair>& st, const std::vector<long long>
     tp.chunk_diags = C;
     tp.h = ctx_hash(c);
     tp.counters = c->d_cnt;
+    run.d_pairs = tp.pairs;
+    run.pairs_bytes = pairs_bytes;
     // queue image: the first tasks full, every other slot waiting for lap 0
-    std::vector<unsigned long long> seq(qcap);
-    std::vector<long long> task(qcap, 0);
-    for (uint64_t q = 0; q < qcap; ++q) seq[q] = q;
+    // (host images kept with the run until it is waited for)
+    run.seq.assign(qcap, 0);
+    run.task.assign(qcap, 0);
+    for (uint64_t q = 0; q < qcap; ++q) run.seq[q] = q;
     for (size_t q = 0; q < first.size(); ++q) {
-        seq[q] = q + 1;
-        task[q] = first[q];
+        run.seq[q] = q + 1;
+        run.task[q] = first[q];
     }
-    unsigned long long ctr[2] = {0ull, static_cast<unsigned long long>(first.size())};
-    int32_t remaining = 0;
-    for (const TaskPair& tp : st) remaining += tp.status == 0 ? 1 : 0;
+    run.ctr[0] = 0ull;
+    run.ctr[1] = static_cast<unsigned long long>(first.size());
+    run.remaining = 0;
+    for (const TaskPair& p : st) run.remaining += p.status == 0 ? 1 : 0;
     int grid = c->opt.grid_blocks ? static_cast<int>(c->opt.grid_blocks) : c->task_grid_max;
     grid = std::max(1, grid);
     hipError_t e = hipMemcpyAsync(tp.pairs, st.data(), pairs_bytes, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(tp.qseq, seq.data(), qcap * 8, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(tp.qtask, task.data(), qcap * 8, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(tp.qhead, ctr, 16, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(tp.remaining, &remaining, 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(tp.qseq, run.seq.data(), qcap * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(tp.qtask, run.task.data(), qcap * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(tp.qhead, run.ctr, 16, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(tp.remaining, &run.remaining, 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_ctl_init(c->d_ctl, c->d_cnt, nullptr, s);
-    if (e == hipSuccess && remaining > 0) e = launch_tasks(tp, grid, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(st.data(), tp.pairs, pairs_bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && run.remaining > 0) e = launch_tasks(tp, grid, s);
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(s);
+        c->pool.put(run.blk);
+        run.blk = nullptr;
+        set_error("task launch: %s", hipGetErrorString(e));
+        return ED_EDEVICE;
+    }
+    return ED_OK;
+}
+
+int tasks_wait(ed_ctx* c, std::vector<TaskPair>& st, hipStream_t s, TaskRun& run) {
+    hipError_t e = hipMemcpyAsync(st.data(), run.d_pairs, run.pairs_bytes, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    c->pool.put(blk);
+    c->pool.put(run.blk);
+    run.blk = nullptr;
     if (e != hipSuccess) {
         set_error("task launch: %s", hipGetErrorString(e));
         return ED_EDEVICE;
     }
     return ED_OK;
+}
+
+int tasks_run(ed_ctx* c, std::vector<TaskPair>& st, const std::vector<long long>& first, uint32_t engine,
+              hipStream_t s) {
+    TaskRun run;
+    int rc = tasks_start(c, st, first, engine, s, run);
+    if (rc != ED_OK) return rc;
+    return tasks_wait(c, st, s, run);
 }
 
 int batch_locked(ed_ctx* c, ed_pair* const* pairs, uint64_t count, int64_t k_max, uint64_t* k_out,
@@ -222,11 +246,12 @@ int batch_locked(ed_ctx* c, ed_pair* const* pairs, uint64_t count, int64_t k_max
         }
         tp.t_limit = INT32_MAX;
         tp.found_t = INT32_MAX;
+        tp.kmax = k_max >= 0 ? static_cast<int32_t>(std::min<int64_t>(k_max, INT32_MAX - 1)) : -1;
     }
     std::vector<long long> tasks0;
     tasks0.reserve(count);
     for (int32_t pi : order) tasks0.push_back(task_solo(pi));
-    int rc = tasks_run(c, st, tasks0, k_max, engine, s);
+    int rc = tasks_run(c, st, tasks0, engine, s);
     c->pool.put(rows_blk);
     if (rc != ED_OK) return rc;
     int first = ED_OK;

@@ -580,10 +580,11 @@ __device__ void schedule_superstep(const TaskParams& P, TaskPair* S, int32_t pi)
     const int32_t t = S->t;
     int32_t H = imin(P.block_rounds, S->K - t);
     H = imin(H, (kLdsRowLen - P.chunk_diags) / 2);  // window of a chunk must fit an LDS row
-    if (P.kmax >= 0) H = imin(H, P.kmax - t);
+    const int32_t kmax = S->kmax;
+    if (kmax >= 0) H = imin(H, kmax - t);
     H = imin(H, S->t_limit - t);
     if (H <= 0) {
-        if (P.kmax >= 0 && t >= P.kmax) pair_finish(P, S, 2, P.kmax + 1);
+        if (kmax >= 0 && t >= kmax) pair_finish(P, S, 2, kmax + 1);
         else if (t >= S->t_limit) pair_finish(P, S, 5, 0);
         else pair_finish(P, S, 3, t);
         return;
@@ -617,7 +618,7 @@ __device__ void solo_task(const TaskParams& P, int32_t pi, LdsState& L, JobCurso
     int32_t* lb = L.row[1];
     RoundShared& RS = L.rs;
     int32_t t = uni(S->t);
-    const int32_t K = uni(S->K), cur = uni(S->cur), t_limit = uni(S->t_limit);
+    const int32_t K = uni(S->K), cur = uni(S->cur), t_limit = uni(S->t_limit), kmax = uni(S->kmax);
     int32_t* g = const_cast<int32_t*>(uni(static_cast<const int32_t*>(cur ? S->f1 : S->f0)));
     if (tid == 0) RS.flag = 0;
     __syncthreads();
@@ -631,7 +632,7 @@ __device__ void solo_task(const TaskParams& P, int32_t pi, LdsState& L, JobCurso
     int32_t status = 0, result = 0;
     for (;;) {
         if (RS.flag) { status = 1; result = t; break; }
-        if (P.kmax >= 0 && t >= P.kmax) { status = 2; result = P.kmax + 1; break; }
+        if (kmax >= 0 && t >= kmax) { status = 2; result = kmax + 1; break; }
         if (t > maxnm) { status = 4; result = t; break; }
         if (t >= t_limit) { status = 5; break; }
         if (t >= lr) break;

@@ -125,8 +125,23 @@ int distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, int32
 int scratch_setup(ed_ctx* c);
 // k, an optimal path (k + 1 steps) and the direct check of its runs of matches
 int align_locked(ed_ctx* c, ed_pair* p, uint64_t* k_out, std::vector<PathStep>& path, hipStream_t s);
-int tasks_run(ed_ctx* c, std::vector<TaskPair>& st, const std::vector<long long>& first, int64_t k_max,
-              uint32_t engine, hipStream_t s);
+// One launch of the many-pair kernel over `st` (each pair's own k_max), the
+// first tasks queued: started on stream s, then waited for (pair states
+// copied back).  The run keeps its device block and host images in between.
+struct TaskRun {
+    void* blk = nullptr;
+    TaskPair* d_pairs = nullptr;
+    size_t pairs_bytes = 0;
+    std::vector<unsigned long long> seq;
+    std::vector<long long> task;
+    unsigned long long ctr[2] = {0, 0};
+    int32_t remaining = 0;
+};
+int tasks_start(ed_ctx* c, const std::vector<TaskPair>& st, const std::vector<long long>& first, uint32_t engine,
+                hipStream_t s, TaskRun& run);
+int tasks_wait(ed_ctx* c, std::vector<TaskPair>& st, hipStream_t s, TaskRun& run);
+int tasks_run(ed_ctx* c, std::vector<TaskPair>& st, const std::vector<long long>& first, uint32_t engine,
+              hipStream_t s);
 long long task_solo(int32_t pi);
 long long task_chunk(int32_t pi, int32_t c);
 int32_t block_rounds_of(const ed_ctx* c);

@@ -129,6 +129,8 @@ struct TaskPair {
     int32_t nchunks;
     int32_t chunks_left;  // chunk tasks of the super-step not finished yet
     int32_t found_t;      // smallest round reaching (n, m) in the super-step (INT32_MAX: none)
+    int32_t kmax;         // stop after round kmax with result kmax + 1 (-1: none)
+    int32_t pad_;
 };
 
 // Task encoding (always >= 0; -1 means "no task"): pair index in the low 32

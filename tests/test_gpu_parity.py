@@ -592,6 +592,29 @@ def test_serve_matches_oracle_and_alone(ed, make_ctx, orc, engine):
     assert [got1[i] for i in range(25)] == want[:25]
 
 
+@pytest.mark.parametrize("engine", [0, 1])
+def test_serve_band_per_request(ed, make_ctx, orc, engine):
+    # every request with a k_max of its own, in one mix: the distance when it
+    # is at most k_max, else k_max + 1; requests without a bound beside them
+    ctx = make_ctx(engine=engine)
+    srv = ed.ed_serve_open(ctx, 8 << 30, 64)
+    want = {}
+    for tag in range(48):
+        n = [300, 5000, 40000, 200000][tag % 4]
+        A, B, _ = synth.single_pair(n, max(1, n // 40), 700 + tag, sigma=4 if tag % 3 else 20)
+        ed_ = orc.lv_omp(A, B)
+        kmax = [-1, 0, ed_ // 2, ed_, ed_ + 3, max(ed_ - 1, 0)][tag % 6]
+        assert ed.ed_serve_submit_band(srv, A, B, tag, kmax) == 0, ed.ed_last_error()
+        want[tag] = ed_ if kmax < 0 or ed_ <= kmax else kmax + 1
+    say("serve band", engine)
+    ed.ed_serve_drain(srv)
+    res = ed.ed_serve_poll(srv, 100)
+    ed.ed_serve_close(srv)
+    assert all(r["status"] == 0 for r in res)
+    assert {r["tag"]: r["k"] for r in res} == want
+    assert ed.lib.ed_serve_submit_band(None, None, 0, None, 0, 0, -1) == ed.ED_EINVAL
+
+
 def test_serve_tiny_budget_and_growth(ed, make_ctx, orc):
     # a budget that fits about one request at a time still completes them all,
     # and a slow-converging pair outgrows its rows and keeps going
