@@ -11,7 +11,12 @@ Workloads:
   * single pairs, n = 10^9, Zipf(1.0) over 256 symbols and its period-64
     variant, k in {10^3, 10^5}, seeds 0, 1, 2;
   * the paper's own synthetic shape: n = 10^8 uniform over 256 symbols,
-    k in {10^2 .. 10^5}, seed 0 (the workload of its full-run table);
+    k in {10^2 .. 10^5}, seed 0 (the workload of its full-run table), and the
+    rest of that table's grid: n in {10^6 .. 10^9}, k in {1, 10, 10^2 .. 10^5};
+  * stand-ins for the shapes of the paper's real-data table (section 6): a
+    DNA-like string (n = 42.3M, alphabet 4 uniform) and text-like ones
+    (Zipf(1.0) over 256 symbols, n = 0.56M and 6.47M), each with three
+    numbers of planted edits taken from that table;
   * the 4096-pair batch (n log-uniform in [10^3, 10^6], k uniform in
     [0, 0.01 n], alphabet 4), seeds 0, 1, 2;
   * the first 40 requests of the mixed-alphabet serving trace (n log-uniform
@@ -28,7 +33,7 @@ Workloads:
 Entries already in the file with the same specification are kept (the
 script only computes what is missing); --force recomputes everything.
 
-Usage: python tests/golden/make_golden.py [--only single|big|paper|batch|serve|trace] [--force]
+Usage: python tests/golden/make_golden.py [--only single|big|paper|grid|shapes|batch|serve|trace] [--force]
 (the single pairs at n = 10^9 need ~10 GB of RAM).
 """
 import argparse
@@ -61,6 +66,16 @@ BIG = [dict(name="n1e9_zipf%s_k%d%s" % ("_periodic" if p else "", k, _sfx(s)), n
             kind="zipf", sigma=256, periodic=p) for s in SEEDS for p in (False, True) for k in (1000, 100000)]
 PAPER = [dict(name="n1e8_sigma256_k%d" % k, n=10 ** 8, k=k, seed=0, kind="uniform", sigma=256,
               periodic=False) for k in (100, 1000, 10000, 100000)]
+PAPER_GRID = [dict(name="n1e%d_sigma256_k%d" % (e, k), n=10 ** e, k=k, seed=0, kind="uniform", sigma=256,
+                   periodic=False) for e in (6, 7, 8, 9) for k in (1, 10, 100, 1000, 10000, 100000)
+              if not (e == 8 and k >= 100)]
+# sizes and edit counts of the real-data table's rows (section 6); synthetic strings of those shapes
+SHAPES = ([dict(name="dna_like_k%d" % k, n=42_300_000, k=k, seed=0, kind="uniform", sigma=4, periodic=False)
+           for k in (928, 9162, 91419)] +
+          [dict(name="wiki_like_k%d" % k, n=560_000, k=k, seed=0, kind="zipf", sigma=256, periodic=False)
+           for k in (439, 5578, 15026)] +
+          [dict(name="linux_like_k%d" % k, n=6_470_000, k=k, seed=0, kind="zipf", sigma=256, periodic=False)
+           for k in (236, 1447, 9559)])
 BATCH = [dict(name="batch4096_seed%d" % s, count=4096, seed=s) for s in SEEDS]
 SERVE = dict(name="serve40_seed0", count=40, seed=0)
 TRACE_COUNT = 2200
@@ -177,7 +192,7 @@ def _merge(old, specs, fn, force):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--only", choices=["single", "big", "paper", "batch", "serve", "trace"])
+    ap.add_argument("--only", choices=["single", "big", "paper", "grid", "shapes", "batch", "serve", "trace"])
     ap.add_argument("--force", action="store_true")
     args = ap.parse_args()
     oracle.build(force=False)
@@ -202,6 +217,12 @@ def main():
         save()
     if args.only in (None, "paper"):
         data["paper"] = _merge(data.get("paper"), PAPER, single, args.force)
+        save()
+    if args.only in (None, "grid"):
+        data["paper_grid"] = _merge(data.get("paper_grid"), PAPER_GRID, single, args.force)
+        save()
+    if args.only in (None, "shapes"):
+        data["shapes"] = _merge(data.get("shapes"), SHAPES, single, args.force)
         save()
     if args.only in (None, "batch"):
         data["batch"] = _merge(data.get("batch"), BATCH, batch, args.force)

@@ -32,6 +32,13 @@ def test_golden_file_complete(gold):
     assert all(g["n"] == 10 ** 9 and g["kind"] == "zipf" for g in gold["big"])
     assert [g["k"] for g in gold["paper"]] == [100, 1000, 10000, 100000]
     assert all(g["n"] == 10 ** 8 and g["sigma"] == 256 and g["kind"] == "uniform" for g in gold["paper"])
+    assert sorted((g["n"], g["k"]) for g in gold["paper_grid"]) == sorted(
+        (10 ** e, k) for e in (6, 7, 8, 9) for k in (1, 10, 100, 1000, 10000, 100000)
+        if not (e == 8 and k >= 100))
+    assert all(g["sigma"] == 256 and g["kind"] == "uniform" and g["seed"] == 0 for g in gold["paper_grid"])
+    assert sorted((g["n"], g["k"]) for g in gold["shapes"]) == sorted(
+        [(42_300_000, k) for k in (928, 9162, 91419)] + [(560_000, k) for k in (439, 5578, 15026)] +
+        [(6_470_000, k) for k in (236, 1447, 9559)])
     assert [b["seed"] for b in gold["batch"]] == list(seeds)
     assert all(len(b["eds"]) == b["count"] == 4096 for b in gold["batch"])
     assert len(gold["serve"]["eds"]) == gold["serve"]["count"] == 40
@@ -40,7 +47,7 @@ def test_golden_file_complete(gold):
     for t in gold["serve_trace"]:
         assert t["count"] >= 2200 and t["warmup"] == 200 and len(t["index"]) == len(t["eds"])
     # distance bounds of planted edits: |n - m| <= ED <= k
-    for g in gold["single"] + gold["big"] + gold["paper"]:
+    for g in gold["single"] + gold["big"] + gold["paper"] + gold["paper_grid"] + gold["shapes"]:
         assert abs(g["n"] - g["m"]) <= g["ed"] <= g["k_planted"]
 
 
@@ -87,6 +94,14 @@ def test_single_pairs_recomputed(gold, orc, idx):
     g = gold["single"][idx]
     A, B, info = synth.single_pair(g["n"], g["k"], g["seed"], sigma=g["sigma"], kind=g["kind"],
                                    periodic=g["periodic"])
+    assert len(B) == g["m"] and info["k_planted"] == g["k_planted"]
+    assert orc.lv_omp(A, B) == g["ed"]
+
+
+@pytest.mark.parametrize("group,name", [("paper_grid", "n1e6_sigma256_k1000"), ("shapes", "wiki_like_k439")])
+def test_grid_and_shape_entries_recomputed(gold, orc, group, name):
+    g = next(e for e in gold[group] if e["name"] == name)
+    A, B, info = synth.single_pair(g["n"], g["k"], g["seed"], sigma=g["sigma"], kind=g["kind"])
     assert len(B) == g["m"] and info["k_planted"] == g["k_planted"]
     assert orc.lv_omp(A, B) == g["ed"]
 

@@ -142,6 +142,30 @@ def test_n1e8_alphabet256(ed, ctxs, name, engine):
     assert st["rounds"] == spec["ed"]
 
 
+@pytest.mark.parametrize("name,engine", _cases("paper_grid"))
+def test_alphabet256_size_grid(ed, ctxs, name, engine):
+    """The rest of the grid of the paper's synthetic table: n in {1e6 .. 1e9},
+    k in {1, 10, 1e2 .. 1e5}, uniform over 256 symbols."""
+    spec = next(g for g in GOLD["paper_grid"] if g["name"] == name)
+    say("full", name, engine)
+    k, st = run_on_stream(ed, ctxs[engine], spec)
+    assert k == spec["ed"]
+    assert st["rounds"] == spec["ed"]
+
+
+@pytest.mark.parametrize("name,engine", _cases("shapes"))
+def test_real_data_shapes(ed, ctxs, name, engine):
+    """Synthetic pairs of the sizes and edit counts of the paper's real-data
+    rows (a DNA-like and two text-like strings)."""
+    spec = next(g for g in GOLD["shapes"] if g["name"] == name)
+    say("full", name, engine)
+    k, st = run_on_stream(ed, ctxs[engine], spec)
+    assert k == spec["ed"]
+    assert st["bits_per_char"] == (2 if spec["sigma"] == 4 else 8)
+    if engine == "hash":
+        check_collision_bound(ed, ctxs, spec, st)
+
+
 def _gen_pairs(specs):
     def one(s):
         n, k, ps = s
