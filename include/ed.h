@@ -63,6 +63,9 @@ extern "C" {
                                 * does, and answer with the direct engine if the check fails */
 #define ED_FLAG_NO_GRID_ROUNDS 64u /* direct engine: never run the first rounds on every workgroup
                                    * (the grid tier for very long slides); workgroup 0 alone */
+#define ED_FLAG_HASH_FIRST 128u /* hash engine: a slide that runs past the lane stage goes to the
+                                 * wavefront's hash search at once (no direct steps); for pairs
+                                 * with many long slides */
 #define ED_FLAG_WEAK_HASH 32u  /* fault injection for tests: hash base r = 1 (every permutation of
                                 * a string hashes alike), so that collisions happen */
 

@@ -24,35 +24,48 @@ __device__ __forceinline__ int32_t amin(int32_t a, int32_t b) { return a < b ? a
 // rounds of the walk stay within kTbRows + 1 diagonals of the current one:
 // the wavefront loads that band of the next kTbRows rows into LDS (one load
 // per lane and row, all in flight together), then one lane takes the steps.
+// The rows are those of rounds tb .. te restricted to the diagonals
+// [wlo, wlo + w) (row u at dump[(u - tb) * w], diagonal j at + j - wlo); the
+// walk starts on diagonal i_end of round te, so with wlo <= i_end - (te - tb)
+// - 1 and wlo + w > i_end + (te - tb) + 1 every cell it reads is in the window.
+// It ends at round tb, whose diagonal and row value it leaves in state[1],
+// state[2] (state[0]: 0 ok, 1 the walk did not end at (0, 0), 2 no candidate).
 constexpr int kTbRows = 30;
 
-__global__ __launch_bounds__(64) void traceback_kernel(const int32_t* dump, int32_t k, int32_t n, int32_t m,
-                                                       PathStep* out, int32_t* status) {
+__global__ __launch_bounds__(64) void traceback_kernel(const int32_t* dump, int32_t tb, int32_t te, int32_t i_end,
+                                                       int32_t wlo, int32_t w, int32_t n, int32_t m, PathStep* out,
+                                                       int32_t* state) {
     __shared__ int32_t band[kTbRows][64];  // band[r][l]: row t0 - 1 - r, diagonal ic - 32 + l
     __shared__ int32_t sh[4];              // i, f, t, finished
     const int lane = threadIdx.x;
     if (lane == 0) {
-        sh[0] = n - m;
-        sh[1] = dump[static_cast<int64_t>(k) * k + k + (n - m)];
-        sh[2] = k;
+        sh[0] = i_end;
+        sh[1] = dump[static_cast<int64_t>(te - tb) * w + (i_end - wlo)];
+        sh[2] = te;
         sh[3] = 0;
-        *status = 0;
+        state[0] = 0;
     }
     __syncthreads();
     for (;;) {
         const int32_t ic = sh[0], t0 = sh[2];
-        if (t0 == 0) {
+        if (t0 == tb) {
             if (lane == 0) {
-                out[0] = PathStep{sh[0], 0, sh[1], kStepStart};
-                if (sh[0] != 0) *status = 1;
+                if (tb == 0) {
+                    out[0] = PathStep{sh[0], 0, sh[1], kStepStart};
+                    if (sh[0] != 0) state[0] = 1;
+                }
+                state[1] = sh[0];
+                state[2] = sh[1];
             }
             return;
         }
-        const int32_t R = amin(kTbRows, t0);
+        const int32_t R = amin(kTbRows, t0 - tb);
         for (int32_t r = 0; r < R; ++r) {
             const int32_t u = t0 - 1 - r;
             const int32_t j = ic - 32 + lane;
-            band[r][lane] = (j >= -u && j <= u) ? dump[static_cast<int64_t>(u) * u + u + j] : kNone;
+            band[r][lane] = (j >= -u && j <= u && j >= wlo && j < wlo + w)
+                                ? dump[static_cast<int64_t>(u - tb) * w + (j - wlo)]
+                                : kNone;
         }
         __syncthreads();
         if (lane == 0) {
@@ -75,7 +88,7 @@ __global__ __launch_bounds__(64) void traceback_kernel(const int32_t* dump, int3
                     kind = kStepNone, j = i, fj = fa;
                 } else {
                     out[t] = PathStep{i, C, f, kStepFail};
-                    *status = 2;
+                    state[0] = 2;
                     failed = true;
                     break;
                 }
@@ -85,7 +98,7 @@ __global__ __launch_bounds__(64) void traceback_kernel(const int32_t* dump, int3
             }
             sh[0] = i;
             sh[1] = f;
-            sh[2] = failed ? 0 : t0 - R;
+            sh[2] = failed ? tb : t0 - R;
             sh[3] = failed ? 1 : 0;
         }
         __syncthreads();
@@ -116,9 +129,9 @@ __global__ __launch_bounds__(256) void verify_kernel(PairDev p, const VerifySeg*
     if (ballot(diff != 0) && lane == 0) atomicOr(bad, 1u);
 }
 
-hipError_t launch_traceback(const int32_t* dump, int32_t k, int32_t n, int32_t m, PathStep* out, int32_t* status,
-                            hipStream_t s) {
-    hipLaunchKernelGGL(traceback_kernel, dim3(1), dim3(64), 0, s, dump, k, n, m, out, status);
+hipError_t launch_traceback(const int32_t* dump, int32_t tb, int32_t te, int32_t i_end, int32_t wlo, int32_t w,
+                            int32_t n, int32_t m, PathStep* out, int32_t* state, hipStream_t s) {
+    hipLaunchKernelGGL(traceback_kernel, dim3(1), dim3(64), 0, s, dump, tb, te, i_end, wlo, w, n, m, out, state);
     return hipGetLastError();
 }
 

@@ -1,11 +1,19 @@
-// ed_align and the check behind ED_FLAG_CERTIFY (host side): k from the
-// frontier (or from the pair's last unbounded distance on the same engine),
-// the frontier rounds again with every row kept in device memory,
-// the path traced back on the device, its geometry checked here, and its runs
-// of matches re-compared on the device.
+// ed_align and the check behind ED_FLAG_CERTIFY (host side).
+//
+// Forward: the frontier rounds run in segments of S rounds (one launch
+// each, resumed from the previous segment's last row), and the row at each
+// segment's end is kept; the last segment ends where the end cell is reached,
+// which gives k.  Backward, last segment first: the segment's rounds run
+// again from its kept first row with the rows kept for the diagonals that the
+// path can reach from its known end (within one diagonal per round), and the
+// path is traced back on the device through them to the segment's first
+// round.  Device memory is about k^2 / S + 2 S^2 entries instead of the
+// (k + 1)^2 of every row.  The path's geometry is checked here, its runs of
+// matches re-compared on the device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -68,56 +76,224 @@ int64_t path_cost(const std::vector<PathStep>& path, int64_t n, int64_t m) {
     return cost;
 }
 
+// Rounds per segment between kept rows.  The kept rows of a distance k take
+// about k^2 / S entries and one segment's window of rows about 2 S^2, least
+// for S near (k^2 / 4)^(1/3); S grows with the rounds when k is not known
+// yet.  At least kMinSegment rounds, so that a launch does real work.
+constexpr int64_t kMinSegment = 256;
+
+int64_t segment_rounds(int64_t k) {
+    const double kk = static_cast<double>(std::max<int64_t>(k, 1));
+    return std::max<int64_t>(kMinSegment, static_cast<int64_t>(std::llround(std::cbrt(kk * kk / 4.0))));
+}
+
+// A kept row: round t, diagonals -(t + 2) .. t + 2 at row[0 ..] (nullptr for
+// round 0, which a launch from round 0 computes itself, and for round k).
+struct Checkpoint {
+    int64_t t;
+    int32_t* row;
+};
+
 }  // namespace
 
 int ed::align_locked(ed_ctx* c, ed_pair* p, uint64_t* k_out, std::vector<PathStep>& path, hipStream_t s) {
-    uint64_t k = 0;
-    int rc = ED_OK;
-    if (p->known_k >= 0 && p->known_engine == p->engine)
-        k = static_cast<uint64_t>(p->known_k);  // computed before on this pair and engine
-    else
-        rc = distance_locked(c, p, -1, &k, nullptr, 0, s);
+    FrontierParams fp;
+    int rc = frontier_setup(c, p, fp);
     if (rc != ED_OK) return rc;
     const int64_t n = static_cast<int64_t>(p->len[0]), m = static_cast<int64_t>(p->len[1]);
-    const uint64_t cap = (k + 1) * (k + 1);
-    const size_t dump_bytes = cap * 4;
-    size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || dump_bytes + (size_t(256) << 20) > free_b) {
-        set_error("ed_align: the rows of %llu rounds need %zu bytes of device memory", (unsigned long long)(k + 1),
-                  dump_bytes);
-        return ED_ENOMEM;
-    }
+    const int64_t maxnm = std::max(n, m);
+    const int64_t known = (p->known_k >= 0 && p->known_engine == p->engine) ? p->known_k : -1;
     DevBufs db;
-    int32_t* d_dump = static_cast<int32_t*>(db.get(dump_bytes));
-    PathStep* d_path = static_cast<PathStep*>(db.get((k + 1) * sizeof(PathStep) + 64));
-    if (!d_dump || !d_path) {
+    // the two frontier rows (pooled), grown like the distance's
+    int64_t K = std::max<int64_t>(1, std::min<int64_t>(maxnm, known >= 0 ? known : int64_t(1) << 17));
+    struct Rows {
+        ed_ctx* c;
+        int32_t* r[2] = {nullptr, nullptr};
+        ~Rows() {
+            c->pool.put(r[0]);
+            c->pool.put(r[1]);
+        }
+    } rows{c};
+    rows.r[0] = static_cast<int32_t*>(c->pool.get(static_cast<size_t>(2 * K + 5) * 4));
+    rows.r[1] = static_cast<int32_t*>(c->pool.get(static_cast<size_t>(2 * K + 5) * 4));
+    if (!rows.r[0] || !rows.r[1]) {
         set_error("ed_align: device allocation failed");
         return ED_ENOMEM;
     }
-    int32_t* d_status = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(d_path) + (k + 1) * sizeof(PathStep));
-    uint64_t k2 = 0;
-    rc = distance_locked(c, p, static_cast<int64_t>(k), &k2, nullptr, 0, s, d_dump, cap);
-    if (rc != ED_OK) return rc;
-    if (k2 != k) {
-        set_error("ed_align: the second run gave %llu, the first %llu", (unsigned long long)k2,
-                  (unsigned long long)k);
-        return ED_EINTERNAL;
+    int cur = 0;  // rows.r[cur] holds the current round's row
+    // checkpoint rows, bump-allocated from chunks: row of round t at
+    // row[i + t + 2] for diagonals -(t + 2) .. t + 2
+    std::vector<Checkpoint> ck{Checkpoint{0, nullptr}};
+    int32_t* chunk = nullptr;
+    int64_t chunk_left = 0;
+    auto ck_alloc = [&](int64_t len) -> int32_t* {
+        if (len > chunk_left) {
+            const int64_t sz = std::max<int64_t>(len, int64_t(1) << 24);
+            chunk = static_cast<int32_t*>(db.get(static_cast<size_t>(sz) * 4));
+            if (!chunk) return nullptr;
+            chunk_left = sz;
+        }
+        int32_t* r = chunk;
+        chunk += len;
+        chunk_left -= len;
+        return r;
+    };
+    double gpu_ns = 0;
+    auto launch = [&](int64_t t0, int64_t t1) -> int {
+        fp.f0 = rows.r[cur];
+        fp.f1 = rows.r[1 - cur];
+        fp.K = static_cast<int32_t>(K);
+        fp.t0 = static_cast<int32_t>(t0);
+        fp.kmax = static_cast<int32_t>(t1);
+        return frontier_once(c, fp, s, &gpu_ns);
+    };
+
+    // forward: the rounds in segments, the row at each segment's end kept
+    // (with k unknown, these launches are the distance's)
+    int64_t k = -1;
+    CountersDev total;
+    std::memset(&total, 0, sizeof total);
+    int launches = 0;
+    for (int64_t t = 0; k < 0;) {
+        const int64_t t1 = std::min(maxnm, t + segment_rounds(known >= 0 ? known : t));
+        if (known >= 0 && t1 >= known) {
+            k = known;
+            break;
+        }
+        if (t1 <= t && t > 0) {  // (t1 = t = 0 only for two empty strings)
+            set_error("ed_align: no end found by round %lld", (long long)t);
+            return ED_EINTERNAL;
+        }
+        if (t1 > K) {
+            const int64_t K2 = std::min<int64_t>(maxnm, std::max<int64_t>(2 * K, t1));
+            int32_t* g0 = static_cast<int32_t*>(c->pool.get(static_cast<size_t>(2 * K2 + 5) * 4));
+            int32_t* g1 = static_cast<int32_t*>(c->pool.get(static_cast<size_t>(2 * K2 + 5) * 4));
+            hipError_t e = (g0 && g1) ? hipSuccess : hipErrorOutOfMemory;
+            if (e == hipSuccess && t > 0)
+                e = hipMemcpyAsync(g0 + (K2 + 2) - (t + 2), rows.r[cur] + (K + 2) - (t + 2),
+                                   static_cast<size_t>(2 * t + 5) * 4, hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            c->pool.put(rows.r[0]);
+            c->pool.put(rows.r[1]);
+            rows.r[0] = g0;
+            rows.r[1] = g1;
+            cur = 0;
+            if (e != hipSuccess) {
+                set_error("ed_align: growing the rows failed: %s", hipGetErrorString(e));
+                return e == hipErrorOutOfMemory ? ED_ENOMEM : ED_EDEVICE;
+            }
+            K = K2;
+        }
+        fp.dump = nullptr;
+        rc = launch(t, t1);
+        if (rc != ED_OK) return rc;
+        ++launches;
+        counters_add(total, *c->h_cnt);
+        const FrontierCtl& st = *c->h_ctl;
+        if (st.status == 1) {
+            k = st.result_t;
+            break;
+        }
+        if (st.status != 2) {
+            set_error("ed_align: frontier kernel ended with status %d at t=%d", st.status, st.result_t);
+            return ED_EINTERNAL;
+        }
+        if (st.wbuf != 0) cur = 1 - cur;  // the row of round t1
+        int32_t* r = ck_alloc(2 * t1 + 5);
+        if (!r) {
+            set_error("ed_align: device allocation failed (checkpoint row of round %lld)", (long long)t1);
+            return ED_ENOMEM;
+        }
+        const hipError_t e = hipMemcpyAsync(r, rows.r[cur] + (K + 2) - (t1 + 2), static_cast<size_t>(2 * t1 + 5) * 4,
+                                            hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) {
+            set_error("ed_align: checkpoint copy failed: %s", hipGetErrorString(e));
+            return ED_EDEVICE;
+        }
+        ck.push_back(Checkpoint{t1, r});
+        t = t1;
+    }
+    if (known < 0) {
+        p->known_k = k;
+        p->known_engine = p->engine;
+        p->rounds = static_cast<uint64_t>(k);
+        p->counters = total;
+        p->launches_distance = launches;
+        p->gpu_ns_frontier = gpu_ns;
+        p->rounds_phase_a = 0;
+        p->us_phase_a = p->us_phase_b = 0;
+    }
+    ck.push_back(Checkpoint{k, nullptr});
+
+    // backward: each segment's rounds again from its first row, the rows kept
+    // for the diagonals the path can reach, and the path traced through them
+    int64_t seg_cap = 0;
+    for (size_t j = 0; j + 1 < ck.size(); ++j) {
+        const int64_t L = ck[j + 1].t - ck[j].t;
+        seg_cap = std::max(seg_cap, (L + 1) * (2 * L + 5));
+    }
+    int32_t* d_seg = static_cast<int32_t*>(db.get(static_cast<size_t>(seg_cap) * 4));
+    PathStep* d_path = static_cast<PathStep*>(db.get((k + 1) * sizeof(PathStep) + 64));
+    if (!d_seg || !d_path) {
+        set_error("ed_align: device allocation failed");
+        return ED_ENOMEM;
+    }
+    int32_t* d_state = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(d_path) + (k + 1) * sizeof(PathStep));
+    int32_t state[4] = {0, static_cast<int32_t>(n - m), 0, 0};
+    for (size_t j = ck.size() - 1; j-- > 0;) {
+        const int64_t tb = ck[j].t, te = ck[j + 1].t, L = te - tb;
+        const int64_t i_end = state[1];
+        const int64_t wlo = i_end - L - 2, w = 2 * L + 5;
+        hipError_t e = hipSuccess;
+        if (tb > 0) {
+            // the segment's first row: into the frontier row, and its window into the dump
+            e = hipMemcpyAsync(rows.r[cur] + (K + 2) - (tb + 2), ck[j].row, static_cast<size_t>(2 * tb + 5) * 4,
+                               hipMemcpyDeviceToDevice, s);
+            const int64_t d0 = std::max(wlo, -tb), d1 = std::min(wlo + w - 1, tb);
+            if (e == hipSuccess && d0 <= d1)
+                e = hipMemcpyAsync(d_seg + (d0 - wlo), ck[j].row + (d0 + tb + 2), static_cast<size_t>(d1 - d0 + 1) * 4,
+                                   hipMemcpyDeviceToDevice, s);
+        }
+        if (e != hipSuccess) {
+            set_error("ed_align: row copy failed: %s", hipGetErrorString(e));
+            return ED_EDEVICE;
+        }
+        fp.dump = d_seg;
+        fp.dump_cap = (L + 1) * w;
+        fp.dump_t0 = static_cast<int32_t>(tb);
+        fp.dump_lo = static_cast<int32_t>(wlo);
+        fp.dump_w = static_cast<int32_t>(w);
+        rc = launch(tb, te);
+        if (rc != ED_OK) return rc;
+        const FrontierCtl& st = *c->h_ctl;
+        const bool last = te == k;
+        if (st.status != (last ? 1 : 2) || st.result_t != (last ? k : te + 1)) {
+            set_error("ed_align: segment [%lld, %lld] ended with status %d at t=%d", (long long)tb, (long long)te,
+                      st.status, st.result_t);
+            return ED_EINTERNAL;
+        }
+        e = launch_traceback(d_seg, static_cast<int32_t>(tb), static_cast<int32_t>(te), static_cast<int32_t>(i_end),
+                             static_cast<int32_t>(wlo), static_cast<int32_t>(w), static_cast<int32_t>(n),
+                             static_cast<int32_t>(m), d_path, d_state, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(state, d_state, 3 * 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            set_error("ed_align: traceback failed: %s", hipGetErrorString(e));
+            return ED_EDEVICE;
+        }
+        if (state[0] != 0) break;
     }
     path.assign(k + 1, PathStep{});
-    int32_t status = -1;
-    hipError_t e = launch_traceback(d_dump, static_cast<int32_t>(k), static_cast<int32_t>(n),
-                                    static_cast<int32_t>(m), d_path, d_status, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(path.data(), d_path, (k + 1) * sizeof(PathStep), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(&status, d_status, 4, hipMemcpyDeviceToHost, s);
+    hipError_t e = hipMemcpyAsync(path.data(), d_path, (k + 1) * sizeof(PathStep), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
-        set_error("ed_align: traceback failed: %s", hipGetErrorString(e));
+        set_error("ed_align: path copy failed: %s", hipGetErrorString(e));
         return ED_EDEVICE;
     }
-    const int64_t cost = status == 0 ? path_cost(path, n, m) : -1;
-    if (cost < 0 || cost > static_cast<int64_t>(k)) {
-        set_error("ed_align: the traced path is not a valid alignment (status %d, cost %lld, k %llu)", status,
-                  (long long)cost, (unsigned long long)k);
+    const int64_t cost = state[0] == 0 ? path_cost(path, n, m) : -1;
+    if (cost < 0 || cost > k) {
+        set_error("ed_align: the traced path is not a valid alignment (status %d, cost %lld, k %lld)", state[0],
+                  (long long)cost, (long long)k);
         return ED_EINTERNAL;
     }
     // the runs of matches, in segments of at most 2048 characters
@@ -145,7 +321,7 @@ int ed::align_locked(ed_ctx* c, ed_pair* p, uint64_t* k_out, std::vector<PathSte
             return ED_EDEVICE;
         }
     }
-    *k_out = k;
+    *k_out = static_cast<uint64_t>(k);
     if (bad) {
         set_error("ed_align: a run of matches on the traced path does not match (hash collision)");
         return ED_ECOLLISION;

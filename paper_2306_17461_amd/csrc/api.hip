@@ -241,6 +241,11 @@ int ed::ctx_set_hash(ed_ctx* c, uint64_t r) {
     rt[kRtabMmaK] = hsub(hmul(128, wblk), hmul(1ull << 19, geo));
     if (!c->d_pow) {
         HIP_TRY(hipMalloc(&c->d_pow, kPowEntries * sizeof(uint64_t)));
+    } else {
+        // pack and table kernels of an earlier ed_prepare may still read the
+        // old tables on a caller's stream (one that does not wait for the
+        // null stream); the copy below must not overtake them
+        HIP_TRY(hipDeviceSynchronize());
     }
     HIP_TRY(hipMemcpy(c->d_pow, h.data(), kPowEntries * sizeof(uint64_t), hipMemcpyHostToDevice));
     c->r = r;
@@ -573,13 +578,7 @@ static int frontier_grid(const ed_ctx* c) {
     return std::max(1, std::min(g, c->frontier_grid_max));
 }
 
-int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, int32_t* rows,
-                        uint64_t rows_cap, hipStream_t s, int32_t* dev_dump, uint64_t dev_cap,
-                        int32_t* fixed_rows, int64_t fixed_K) {
-    if (fixed_rows && (k_max < 0 || k_max > fixed_K || rows || dev_dump)) {
-        set_error("distance_locked: fixed rows need 0 <= k_max <= %lld", (long long)fixed_K);
-        return ED_EINVAL;
-    }
+int ed::frontier_setup(ed_ctx* c, ed_pair* p, FrontierParams& fp) {
     if (p->engine == ED_ENGINE_HASH && (!p->tab[0] || !p->tab[1])) {
         set_error("ed_distance: pair has no prefix tables");
         return ED_EINVAL;
@@ -588,6 +587,70 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
         int rc = ctx_set_hash(c, p->r);
         if (rc != ED_OK) return rc;
     }
+    const uint32_t lds_rounds = c->opt.lds_rounds ? c->opt.lds_rounds : kDefaultLdsRounds;
+    const uint32_t lane_words = c->opt.lane_words ? c->opt.lane_words
+                                                  : (p->engine == ED_ENGINE_HASH ? 1u : 2u);
+    std::memset(&fp, 0, sizeof fp);
+    fp.p = pair_dev(p);
+    fp.h = ctx_hash(c);
+    fp.kmax = -1;
+    fp.lds_rounds = (c->opt.flags & ED_FLAG_NO_PHASE_A) ? 0 : static_cast<int32_t>(lds_rounds);
+    fp.engine = static_cast<int32_t>(p->engine);
+    fp.lane_words = static_cast<int32_t>(lane_words);
+    fp.block_rounds = static_cast<int32_t>(c->opt.block_rounds ? c->opt.block_rounds : kDefaultBlockRounds);
+    fp.wait_ticks = kWaitTicks;
+    fp.grid_rounds = (p->engine == ED_ENGINE_DIRECT && !(c->opt.flags & ED_FLAG_NO_GRID_ROUNDS)) ? 1 : 0;
+    fp.gpart = c->d_gpart;
+    fp.hash_first = (p->engine == ED_ENGINE_HASH && (c->opt.flags & ED_FLAG_HASH_FIRST)) ? 1 : 0;
+    fp.ctl = c->d_ctl;
+    fp.bar = c->d_bar;
+    fp.counters = c->d_cnt;
+    return ED_OK;
+}
+
+void ed::counters_add(CountersDev& a, const CountersDev& b) {
+    a.updates += b.updates;
+    a.lcp_chars += b.lcp_chars;
+    a.wave_lcps += b.wave_lcps;
+    a.grid_lcps += b.grid_lcps;
+    a.wg_lcps += b.wg_lcps;
+    a.hash_queries += b.hash_queries;
+    a.hash_probes += b.hash_probes;
+    a.hash_ne_len += b.hash_ne_len;
+    a.collisions += b.collisions;
+}
+
+int ed::frontier_once(ed_ctx* c, const FrontierParams& fp, hipStream_t s, double* gpu_ns) {
+    const bool timed = (c->opt.flags & ED_FLAG_TIMING) != 0;
+    hipError_t e = launch_ctl_init(c->d_ctl, c->d_cnt, c->d_bar, s);
+    if (e == hipSuccess && timed) e = hipEventRecord(c->ev[0], s);
+    if (e == hipSuccess) e = launch_frontier(fp, frontier_grid(c), s);
+    if (e == hipSuccess && timed) e = hipEventRecord(c->ev[1], s);
+    if (e == hipSuccess) e = launch_counters_sum(c->d_cnt, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->h_ctl, c->d_ctl, sizeof(FrontierCtl), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->h_cnt, c->d_cnt + kMaxGrid, sizeof(CountersDev), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        set_error("ed_distance: frontier launch failed: %s", hipGetErrorString(e));
+        return ED_EDEVICE;
+    }
+    if (timed && gpu_ns) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) *gpu_ns += 1e6 * ms;
+    }
+    return ED_OK;
+}
+
+int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, int32_t* rows,
+                        uint64_t rows_cap, hipStream_t s, int32_t* fixed_rows, int64_t fixed_K) {
+    if (fixed_rows && (k_max < 0 || k_max > fixed_K || rows)) {
+        set_error("distance_locked: fixed rows need 0 <= k_max <= %lld", (long long)fixed_K);
+        return ED_EINVAL;
+    }
+    FrontierParams fp;
+    int rc = frontier_setup(c, p, fp);
+    if (rc != ED_OK) return rc;
     const int64_t n = static_cast<int64_t>(p->len[0]), m = static_cast<int64_t>(p->len[1]);
     const int64_t maxnm = std::max(n, m);
     int64_t K = std::min<int64_t>(maxnm, c->opt.init_rows ? int64_t(c->opt.init_rows) : int64_t(1) << 17);
@@ -595,18 +658,12 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
     K = std::max<int64_t>(K, 1);
     // caller-owned rows: sized for every round up to k_max, never grown
     if (fixed_rows) K = std::max<int64_t>(k_max, 1);
-    const uint32_t lds_rounds = c->opt.lds_rounds ? c->opt.lds_rounds : kDefaultLdsRounds;
-    const uint32_t lane_words = c->opt.lane_words ? c->opt.lane_words
-                                                  : (p->engine == ED_ENGINE_HASH ? 1u : 2u);
     int32_t* d_dump = nullptr;
     void* dump_buf = nullptr;
     if (rows) {
         dump_buf = c->pool.get(std::max<uint64_t>(rows_cap, 1) * 4);
         if (!dump_buf) return ED_ENOMEM;
         d_dump = static_cast<int32_t*>(dump_buf);
-    } else if (dev_dump) {
-        d_dump = dev_dump;
-        rows_cap = dev_cap;
     }
     auto alloc_rows = [&](int64_t Kn, void** a, void** b) -> bool {
         if (fixed_rows) {
@@ -629,23 +686,9 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
         c->pool.put(dump_buf);
         return ED_ENOMEM;
     }
-    FrontierParams fp;
-    std::memset(&fp, 0, sizeof fp);
-    fp.p = pair_dev(p);
-    fp.h = ctx_hash(c);
     fp.kmax = k_max >= 0 ? static_cast<int32_t>(std::min<int64_t>(k_max, INT32_MAX - 1)) : -1;
-    fp.lds_rounds = (c->opt.flags & ED_FLAG_NO_PHASE_A) ? 0 : static_cast<int32_t>(lds_rounds);
-    fp.engine = static_cast<int32_t>(p->engine);
-    fp.lane_words = static_cast<int32_t>(lane_words);
-    fp.block_rounds = static_cast<int32_t>(c->opt.block_rounds ? c->opt.block_rounds : kDefaultBlockRounds);
-    fp.wait_ticks = kWaitTicks;
-    fp.grid_rounds = (p->engine == ED_ENGINE_DIRECT && !(c->opt.flags & ED_FLAG_NO_GRID_ROUNDS)) ? 1 : 0;
-    fp.gpart = c->d_gpart;
-    fp.ctl = c->d_ctl;
-    fp.bar = c->d_bar;
     fp.dump = d_dump;
     fp.dump_cap = static_cast<int64_t>(rows_cap);
-    fp.counters = c->d_cnt;
     int32_t t0 = 0;
     int launches = 0;
     double gpu_ns = 0;
@@ -653,43 +696,16 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
     double us_a = 0, us_b = 0;
     CountersDev total;
     std::memset(&total, 0, sizeof total);
-    int rc = ED_OK;
     uint64_t result = 0;
     for (;;) {
         fp.f0 = static_cast<int32_t*>(f0);
         fp.f1 = static_cast<int32_t*>(f1);
         fp.K = static_cast<int32_t>(K);
         fp.t0 = t0;
-        const bool timed = (c->opt.flags & ED_FLAG_TIMING) != 0;
-        hipError_t e = launch_ctl_init(c->d_ctl, c->d_cnt, c->d_bar, s);
-        if (e == hipSuccess && timed) e = hipEventRecord(c->ev[0], s);
-        if (e == hipSuccess) e = launch_frontier(fp, frontier_grid(c), s);
-        if (e == hipSuccess && timed) e = hipEventRecord(c->ev[1], s);
-        if (e == hipSuccess) e = launch_counters_sum(c->d_cnt, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(c->h_ctl, c->d_ctl, sizeof(FrontierCtl), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(c->h_cnt, c->d_cnt + kMaxGrid, sizeof(CountersDev), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) {
-            set_error("ed_distance: frontier launch failed: %s", hipGetErrorString(e));
-            rc = ED_EDEVICE;
-            break;
-        }
+        rc = frontier_once(c, fp, s, &gpu_ns);
+        if (rc != ED_OK) break;
         ++launches;
-        if (timed) {
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) gpu_ns += 1e6 * ms;
-        }
-        const CountersDev& cd = *c->h_cnt;
-        total.updates += cd.updates;
-        total.lcp_chars += cd.lcp_chars;
-        total.wave_lcps += cd.wave_lcps;
-        total.grid_lcps += cd.grid_lcps;
-        total.wg_lcps += cd.wg_lcps;
-        total.hash_queries += cd.hash_queries;
-        total.hash_probes += cd.hash_probes;
-        total.hash_ne_len += cd.hash_ne_len;
-        total.collisions += cd.collisions;
+        counters_add(total, *c->h_cnt);
         const FrontierCtl& st = *c->h_ctl;
         if (launches == 1) {
             rounds_a = static_cast<uint64_t>(st.phase_t);
@@ -717,7 +733,7 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
             }
             void* srcrow = st.wbuf == 0 ? f0 : f1;
             // entries [-(t+2), t+2] of the old row -> same diagonals of the new row
-            e = hipMemcpyAsync(static_cast<int32_t*>(g0) + (K2 + 2) - (t + 2),
+            hipError_t e = hipMemcpyAsync(static_cast<int32_t*>(g0) + (K2 + 2) - (t + 2),
                                static_cast<int32_t*>(srcrow) + (K + 2) - (t + 2),
                                static_cast<size_t>(2 * t + 5) * 4, hipMemcpyDeviceToDevice, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -741,7 +757,7 @@ int ed::distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, i
     if (rc == ED_OK) {
         *k_out = result;
         p->rounds = result;
-        if (k_max < 0 && !dev_dump && !rows) {
+        if (k_max < 0 && !rows) {
             p->known_k = static_cast<int64_t>(result);
             p->known_engine = p->engine;
         }

@@ -389,6 +389,7 @@ struct Engine {
     HashQ q;
     int32_t kind;        // 0 direct, 1 hash
     int32_t lane_words;
+    int32_t hash_first;  // hash engine: a slide past the lane stage goes to the hash search at once
 };
 
 __device__ __forceinline__ int32_t slide(const Engine& en, bool valid, int32_t x, int32_t y,

@@ -199,7 +199,14 @@ __device__ __forceinline__ void wave_extend(const Engine& en, bool pend, int32_t
         const int32_t jx = shfl_i32(c, src), jy = shfl_i32(c - i, src);
         const int32_t jlim = shfl_i32(lim, src), jl = shfl_i32(l, src);
         bool done = false;
-        int32_t r = lcp_wave_steps(en.A, en.B, jx, jy, jlim, jl, kWaveSteps, done);
+        int32_t r;
+        if (en.kind == 1 && en.hash_first) {
+            // long-LCP form: the wavefront's hash search, no direct steps
+            r = lcp_wave_hash(en.A, en.B, en.TA, en.TB, en.q, jx, jy, jlim, jl, cnt);
+            done = true;
+        } else {
+            r = lcp_wave_steps(en.A, en.B, jx, jy, jlim, jl, kWaveSteps, done);
+        }
         if (lane == 0) atomicAdd(&cnt.sh->wave_lcps, 1ull);
         if (!done) {
             // the workgroup tier takes it after the round's barrier
@@ -523,11 +530,35 @@ __device__ __forceinline__ Engine make_engine(const PairDev& p, const HashDev& h
     }
     en.kind = KIND;
     en.lane_words = uni(lane_words);
+    en.hash_first = 0;
     return en;
 }
 
-__device__ __forceinline__ int32_t* dump_row_for(int32_t* dump, int64_t cap, int32_t t) {
-    return (dump && static_cast<int64_t>(t + 1) * (t + 1) <= cap) ? dump + static_cast<int64_t>(t) * t : nullptr;
+// Where round t's row goes in the dump: entry for diagonal i at row[i + t],
+// for i in [lo, hi] (the caller's range cut to the dump's window); row is
+// nullptr before the dump's first round, past its capacity, or without a dump.
+struct DumpAt {
+    int32_t* row;
+    int32_t lo, hi;
+};
+
+__device__ __forceinline__ DumpAt dump_at(const FrontierParams& P, int32_t* dump, int32_t t, int32_t lo,
+                                          int32_t hi) {
+    DumpAt d{nullptr, lo, hi};
+    if (!dump || t < P.dump_t0) return d;
+    if (P.dump_w > 0) {
+        const int64_t r = t - P.dump_t0;
+        if ((r + 1) * P.dump_w > P.dump_cap) return d;
+        d.lo = imax(lo, P.dump_lo);
+        d.hi = imin(hi, P.dump_lo + P.dump_w - 1);
+        // row[i + t] = dump[r * w + i - lo] for i in [lo, hi]
+        d.row = dump + (r * P.dump_w - P.dump_lo - t);
+    } else {
+        const int64_t base = static_cast<int64_t>(P.dump_t0) * P.dump_t0;
+        if (static_cast<int64_t>(t + 1) * (t + 1) - base > P.dump_cap) return d;
+        d.row = dump + (static_cast<int64_t>(t) * t - base);
+    }
+    return d;
 }
 
 // ---------------------------------------------------------------------------
@@ -730,7 +761,7 @@ __device__ __forceinline__ uint64_t clock_now() { return __builtin_amdgcn_s_memr
 template <typename CurPtr>
 __device__ __forceinline__ bool grid_round_jobs(const Engine& en, int32_t t, CurPtr cur, int32_t ofs, int32_t nj,
                                                 RoundShared& RS, int32_t* part, int32_t active_waves,
-                                                int32_t* dump_row, FrontierCtl* ctl, unsigned int* bar,
+                                                const DumpAt& dump, FrontierCtl* ctl, unsigned int* bar,
                                                 unsigned int& epoch, uint64_t ticks, Cnt& cnt, int32_t& longest) {
     const int tid = threadIdx.x;
     const int G = static_cast<int>(gridDim.x);
@@ -781,7 +812,7 @@ __device__ __forceinline__ bool grid_round_jobs(const Engine& en, int32_t t, Cur
             const int32_t i = RS.ji[q];
             const int32_t f = jx + r;
             cur[i + ofs] = f;
-            if (dump_row) dump_row[i + t] = f;
+            if (dump.row && i >= dump.lo && i <= dump.hi) dump.row[i + t] = f;
             cnt.updates++;
             atomicAdd(&cnt.sh->grid_lcps, 1ull);
             cnt.lcp_chars += static_cast<unsigned long long>(r);
@@ -831,7 +862,8 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
     rs_init(L.rs, jc);
     if (KIND == 1) load_lut32(L.lut32, P.h.rtab, tid, nthr);
     __syncthreads();
-    const Engine en = make_engine<KIND>(P.p, P.h, P.lane_words, L.lut32);
+    Engine en = make_engine<KIND>(P.p, P.h, P.lane_words, L.lut32);
+    en.hash_first = KIND == 1 ? uni(P.hash_first) : 0;
     int32_t* const dump = DUMP ? P.dump : nullptr;
     RoundShared& RS = L.rs;
     const int32_t n = en.A.len, m = en.B.len;
@@ -866,7 +898,7 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
             const int32_t all_waves = G * (kFrontierThreads >> 6);
             int32_t* const dump0 = blockIdx.x == 0 ? dump : nullptr;
             int32_t nj = 0, longest = 0, quiet = 0, est = INT_MAX;
-            auto resolve = [&](int32_t tt, int32_t* cur, int32_t* drow) {
+            auto resolve = [&](int32_t tt, int32_t* cur, const DumpAt& drow) {
                 longest = 0;
                 if (nj > 0) {
                     // wavefronts for about twice the longest slide of the last round
@@ -877,9 +909,11 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
                     est = longest;
                 }
             };
-            round_range<kWgWords>(en, 0, la, la, off, -2, 3, RS, jc, dump0 && P.dump_cap >= 1 ? dump0 : nullptr, 0, 0,
-                                  cnt, &nj);
-            resolve(0, la, dump0 && P.dump_cap >= 1 ? dump0 : nullptr);
+            {
+                const DumpAt d = dump_at(P, dump0, 0, 0, 0);
+                round_range<kWgWords>(en, 0, la, la, off, -2, 3, RS, jc, d.row, d.lo, d.hi, cnt, &nj);
+                resolve(0, la, d);
+            }
             started = true;
             for (;;) {
                 if (RS.flag) { status = 1; result = t; break; }
@@ -897,9 +931,9 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
                     break;
                 }
                 ++t;
-                round_range<kWgWords>(en, t, la, lb, off, -(t + 2), t + 3, RS, jc, dump_row_for(dump0, P.dump_cap, t),
-                                      -t, t, cnt, &nj);
-                resolve(t, lb, dump_row_for(dump0, P.dump_cap, t));
+                const DumpAt d = dump_at(P, dump0, t, -t, t);
+                round_range<kWgWords>(en, t, la, lb, off, -(t + 2), t + 3, RS, jc, d.row, d.lo, d.hi, cnt, &nj);
+                resolve(t, lb, d);
                 int32_t* tmp = la;
                 la = lb;
                 lb = tmp;
@@ -912,10 +946,11 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
                 __syncthreads();
             }
             if (status != 0 || to_b) {
-                if (to_b && blockIdx.x == 0)
+                if ((to_b || status == 2) && blockIdx.x == 0)
                     for (int32_t e = tid; e < 2 * t + 5; e += nthr) gp[gofs + e - (t + 2)] = la[off + e - (t + 2)];
                 if (blockIdx.x == 0 && tid == 0) {
                     ctl->clk_switch = clock_now();
+                    ctl->wbuf = 0;
                     ctl->phase_t = t;
                     if (status != 0) {
                         ctl->result_t = result;
@@ -931,25 +966,29 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
             // (decided alike by every workgroup in the grid rounds)
         } else if (blockIdx.x == 0) {
             // ---------------- phase A: workgroup 0, rows in LDS ----------------
-            if (!started)
-                round_range<kWgWords>(en, 0, la, la, off, -2, 3, RS, jc, dump && P.dump_cap >= 1 ? dump : nullptr, 0,
-                                      0, cnt);
+            if (!started) {
+                const DumpAt d = dump_at(P, dump, 0, 0, 0);
+                round_range<kWgWords>(en, 0, la, la, off, -2, 3, RS, jc, d.row, d.lo, d.hi, cnt);
+            }
             for (;;) {
                 if (RS.flag) { status = 1; result = t; break; }
                 if (P.kmax >= 0 && t >= P.kmax) { status = 2; result = P.kmax + 1; break; }
                 if (t > maxnm) { status = 4; result = t; break; }
                 if (t >= lr) break;
                 ++t;
-                round_range<kWgWords>(en, t, la, lb, off, -(t + 2), t + 3, RS, jc, dump_row_for(dump, P.dump_cap, t), -t, t, cnt);
+                const DumpAt d = dump_at(P, dump, t, -t, t);
+                round_range<kWgWords>(en, t, la, lb, off, -(t + 2), t + 3, RS, jc, d.row, d.lo, d.hi, cnt);
                 int32_t* tmp = la;
                 la = lb;
                 lb = tmp;
             }
-            if (status == 0)
+            // (also when k_max stopped the rounds: the state a later launch resumes from)
+            if (status == 0 || status == 2)
                 for (int32_t e = tid; e < 2 * t + 5; e += nthr) gp[gofs + e - (t + 2)] = la[off + e - (t + 2)];
             __syncthreads();
             if (tid == 0) {
                 ctl->clk_switch = clock_now();
+                ctl->wbuf = 0;
                 if (status != 0) {
                     ctl->result_t = result;
                     ctl->phase_t = t;
@@ -1023,9 +1062,9 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
                 const int32_t c1 = (total1 + G - 1) / G;
                 const int32_t e0 = imin(total1, static_cast<int32_t>(blockIdx.x) * c1);
                 const int32_t e1 = imin(total1, e0 + c1);
-                if (e0 < e1 &&
-                    round_range<kWgWords>(en, t1, gp, gc, gofs, e0 - (t1 + 2), e1 - (t1 + 2), RS, jc,
-                                dump_row_for(dump, P.dump_cap, t1), -t1, t1, cnt))
+                const DumpAt d = dump_at(P, dump, t1, -t1, t1);
+                if (e0 < e1 && round_range<kWgWords>(en, t1, gp, gc, gofs, e0 - (t1 + 2), e1 - (t1 + 2), RS, jc,
+                                                     d.row, d.lo, d.hi, cnt))
                     atomicMin(&ctl->found_t, t1);
                 grid_sync(ctl, P.bar, ++epoch, P.wait_ticks);
                 int32_t* tmp = gp;
@@ -1049,8 +1088,9 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
                 int32_t* rc = L.row[1];
                 for (int32_t s = 1; s <= H; ++s) {
                     const int32_t tt = t + s;
-                    if (round_range<kWgWords>(en, tt, rp, rc, wofs, a - (H - s), b + (H - s) + 1, RS, jc,
-                                    dump_row_for(dump, P.dump_cap, tt), imax(a, -tt), imin(b, tt), cnt))
+                    const DumpAt d = dump_at(P, dump, tt, imax(a, -tt), imin(b, tt));
+                    if (round_range<kWgWords>(en, tt, rp, rc, wofs, a - (H - s), b + (H - s) + 1, RS, jc, d.row, d.lo,
+                                              d.hi, cnt))
                         atomicMin(&ctl->found_t, tt);
                     int32_t* tmp = rp;
                     rp = rc;

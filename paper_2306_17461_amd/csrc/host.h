@@ -113,13 +113,20 @@ PairDev pair_dev(const ed_pair* p);
 HashDev ctx_hash(const ed_ctx* c);
 int prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B, uint64_t m,
                    int on_device, hipStream_t s, ed_pair** out);
-// rows: host copy of every round's frontier row (ed_distance_dump); dev_dump:
-// the same rows kept in device memory (dev_cap entries), for the traceback
+// The fields of a frontier launch that depend only on the context, its
+// options and the pair (the hash tables of the pair's base made current);
+// rows, t0, K, k_max and the dump are the caller's.
+int frontier_setup(ed_ctx* c, ed_pair* p, FrontierParams& fp);
+// One frontier launch, its control block reset first; the control block and
+// the summed counters are left in c->h_ctl and c->h_cnt, and gpu_ns (if
+// given) gains the kernel's time under ED_FLAG_TIMING.
+int frontier_once(ed_ctx* c, const FrontierParams& fp, hipStream_t s, double* gpu_ns);
+void counters_add(CountersDev& a, const CountersDev& b);
+// rows: host copy of every round's frontier row (ed_distance_dump);
 // fixed_rows: two rows of 2 fixed_K + 5 entries that the caller owns (no
 // allocation and no growth; needs 0 <= k_max <= fixed_K)
 int distance_locked(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, int32_t* rows,
-                    uint64_t rows_cap, hipStream_t s, int32_t* dev_dump = nullptr, uint64_t dev_cap = 0,
-                    int32_t* fixed_rows = nullptr, int64_t fixed_K = 0);
+                    uint64_t rows_cap, hipStream_t s, int32_t* fixed_rows = nullptr, int64_t fixed_K = 0);
 // device address of this device's scratch array (noalloc.hip), taken once at
 // ed_init with the device current
 int scratch_setup(ed_ctx* c);

@@ -102,13 +102,24 @@ struct FrontierParams {
     int32_t engine;
     int32_t lane_words;
     int32_t grid_rounds;  // 1: the first rounds may run on every workgroup (direct engine)
+    int32_t hash_first;   // 1: hash engine, slides past the lane stage go to the hash search at once
+    int32_t pad2_;
     uint64_t wait_ticks;  // a wait on another workgroup or wavefront gives up after this many
                           // s_memrealtime ticks (100 MHz) and the launch ends with status 4
     FrontierCtl* ctl;
     unsigned int* bar;  // kMaxGrid lines of kBarStride uint32
     int32_t* gpart;     // grid rounds: 2 x kGridJobs x kMaxGrid per-workgroup first mismatches
-    int32_t* dump;     // optional per-round rows (device), row t at t*t
+    // optional per-round rows (device) from round dump_t0 on (a resumed launch
+    // dumps from its start round): with dump_w = 0 every diagonal, row t at
+    // t*t - dump_t0*dump_t0 and diagonal i at + t + i; with dump_w > 0 only
+    // diagonals [dump_lo, dump_lo + dump_w), row t at (t - dump_t0) * dump_w
+    // and diagonal i at + i - dump_lo.  Rows past dump_cap entries are dropped.
+    int32_t* dump;
     int64_t dump_cap;
+    int32_t dump_t0;
+    int32_t dump_lo;
+    int32_t dump_w;
+    int32_t pad3_;
     CountersDev* counters;
 };
 
@@ -251,10 +262,13 @@ struct VerifySeg {
 };
 
 hipError_t launch_ctl_init(FrontierCtl* ctl, CountersDev* cnt, unsigned int* bar, hipStream_t s);
-// Path of an optimal alignment from the per-round frontier rows (row t at
-// dump[t^2], diagonal i at dump[t^2 + t + i]); status 0 ok, 1 bad start, 2 no candidate.
-hipError_t launch_traceback(const int32_t* dump, int32_t k, int32_t n, int32_t m, PathStep* out, int32_t* status,
-                            hipStream_t s);
+// The steps of an optimal path for rounds te .. tb + 1 (and round 0 when tb
+// = 0) from the frontier rows of rounds tb .. te kept for diagonals [wlo, wlo
+// + w) (row u at dump[(u - tb) * w], diagonal i at + i - wlo), starting on
+// diagonal i_end of round te; state: [0] 0 ok, 1 bad start, 2 no candidate;
+// [1], [2] the path's diagonal and row value at round tb.
+hipError_t launch_traceback(const int32_t* dump, int32_t tb, int32_t te, int32_t i_end, int32_t wlo, int32_t w,
+                            int32_t n, int32_t m, PathStep* out, int32_t* state, hipStream_t s);
 // Sets *bad (nonzero) when some segment's characters differ.
 hipError_t launch_verify(const PairDev& p, const VerifySeg* segs, int64_t count, uint32_t* bad, int grid,
                          hipStream_t s);

@@ -60,6 +60,6 @@ int ed_distance_noalloc(ed_ctx* c, ed_pair* p, int64_t k_max, uint64_t* k_out, v
         set_error("ed_distance_noalloc: hipSetDevice(%d) failed", c->device);
         return ED_EDEVICE;
     }
-    return distance_locked(c, p, k_max, k_out, nullptr, 0, static_cast<hipStream_t>(hip_stream), nullptr, 0,
-                           c->d_scratch, static_cast<int64_t>(ED_NOALLOC_MAX_K));
+    return distance_locked(c, p, k_max, k_out, nullptr, 0, static_cast<hipStream_t>(hip_stream), c->d_scratch,
+                           static_cast<int64_t>(ED_NOALLOC_MAX_K));
 }

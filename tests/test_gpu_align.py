@@ -127,7 +127,7 @@ def test_certified_hash_distance(ed, make_ctx, orc, block):
 
 
 def test_align_large_pair_both_engines(ed, make_ctx, orc):
-    # 10^6 characters, about 2000 edits: rows of 2001 rounds (16 MB) in device memory
+    # 10^6 characters, about 2000 edits: segments of 256 rounds between kept rows
     A, B, _ = synth.single_pair(10 ** 6, 2000, 21)
     want = orc.lv_omp(A, B)
     for engine in (0, 1):
@@ -138,6 +138,53 @@ def test_align_large_pair_both_engines(ed, make_ctx, orc):
         ed.ed_release(p)
         assert k == want
         assert apply_script(ed, A, B, script) == k
+
+
+@pytest.mark.parametrize("engine", [0, 1])
+def test_align_segments_known_and_unknown_k(ed, make_ctx, orc, engine):
+    # about 5000 edits: 20 segments of 256 rounds; the path crosses every
+    # segment boundary.  Without a distance before, the segments' launches
+    # compute k; after one, the last forward segment is skipped.
+    A, B, _ = synth.single_pair(300000, 5000, 23, sigma=4)
+    want = orc.lv_omp(A, B)
+    ctx = make_ctx(engine=engine)
+    for first in ("align", "distance"):
+        say("align segments", engine, first)
+        p = ed.ed_prepare(ctx, A, B)
+        try:
+            if first == "distance":
+                assert ed.ed_distance(ctx, p) == want
+            k, script = ed.ed_align(ctx, p)
+            st = ed.ed_pair_stats(p)
+        finally:
+            ed.ed_release(p)
+        assert k == want
+        assert st["rounds"] == want
+        assert apply_script(ed, A, B, script) == k
+
+
+def test_align_beyond_every_row_in_memory(ed, make_ctx):
+    # about 3e5 edits: every frontier row of every round would take (k + 1)^2
+    # int32 = 360 GB, more than the device holds; the kept rows take ~130 MB.
+    # The distance is the one of ed_distance (whose full-size values are pinned
+    # to the oracle elsewhere), and the script, applied to A, gives B with
+    # exactly that many edits.
+    A, B, info = synth.single_pair(20_000_000, 300_000, 24, sigma=4)
+    ctx = make_ctx(engine=ed.ENGINE_DIRECT)
+    say("align k=3e5 distance")
+    p = ed.ed_prepare(ctx, A, B)
+    want = ed.ed_distance(ctx, p)
+    ed.ed_release(p)
+    assert abs(len(A) - len(B)) <= want <= info["k_planted"]
+    assert want > 250_000
+    say("align k=3e5 script")
+    p = ed.ed_prepare(ctx, A, B)
+    try:
+        k, script = ed.ed_align(ctx, p)
+    finally:
+        ed.ed_release(p)
+    assert k == want
+    assert apply_script(ed, A, B, script) == k
 
 
 @pytest.mark.parametrize("pack_bits", [0, 8])

@@ -143,6 +143,27 @@ def test_table_bit_exact(ed, make_ctx, orc, b, alpha):
         ed.ed_release(p)
 
 
+def test_base_switch_after_prepare_on_side_stream(ed, make_ctx, orc):
+    # a prepare queued on a stream that does not wait for the null stream,
+    # then a new hash base at once: the pair's tables must still be those of
+    # its own base (the context's power tables are rewritten only after the
+    # queued kernels that read them)
+    import torch
+    ctx = make_ctx(engine=ed.ENGINE_HASH, block=32, hash_seed=501)
+    A = synth.random_string(1 << 25, synth.CharDist("uniform", 256), 41)
+    B = synth.random_string(5000, synth.CharDist("uniform", 4), 42)
+    tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    say("base switch on side stream")
+    p = ed.ed_prepare(ctx, tA, tB, stream=side)
+    ed.ed_set_options(ctx, engine=ed.ENGINE_HASH, block=32, hash_seed=502)
+    side.synchronize()
+    TA = ed.ed_pair_buffer(ctx, p, 0, ed.BUF_TABLE)
+    ed.ed_release(p)
+    np.testing.assert_array_equal(TA, orc.horner_table(A, 32, orc.hash_base(501)))
+
+
 @pytest.mark.parametrize("b,sigma", [(32, 4), (4096, 4), (32, 256), (64, 256)])
 def test_table_bit_exact_multi_chunk_scan(ed, make_ctx, orc, b, sigma):
     # more than 8192 tiles of 16384 characters: the scan of the tile hashes
