@@ -71,7 +71,8 @@ extern "C" {
 
 typedef struct ed_options {
     uint32_t engine;    /* ED_ENGINE_DIRECT or ED_ENGINE_HASH */
-    uint32_t pack_bits; /* 0 = automatic (2-bit when every character is 0..3), 2 or 8 */
+    uint32_t pack_bits; /* 0 = automatic (2-bit when every character is 0..3; direct engine:
+                         * 4-bit when every character is 0..15), 2 or 8 */
     uint32_t block;     /* hash block size b (power of two, 1..4096); 0 = 32 */
     uint32_t flags;     /* ED_FLAG_* */
     uint64_t hash_seed; /* the hash base r is derived from this seed (see ed_hash_base) */
@@ -115,7 +116,9 @@ int ed_shutdown(ed_ctx *ctx);
 /*
  * Copies A[0..n) and B[0..m) into buffers owned by a new pair, detects the
  * alphabet (bitwise OR of all characters; 2-bit packing when it is <= 3 and
- * pack_bits is 0 or 2), packs, and -- for the hash engine -- builds the prefix
+ * pack_bits is 0 or 2; for the direct engine with pack_bits = 0, 4-bit
+ * packing when it is <= 15; else an 8-bit copy), packs, and -- for the hash
+ * engine -- builds the prefix
  * tables T_A, T_B of section 3.3.  A and B are device pointers when
  * inputs_on_device != 0, host pointers otherwise; the caller keeps ownership
  * and may free them once `hip_stream` has synchronised.  A may be NULL iff
@@ -211,7 +214,7 @@ int ed_batch(ed_ctx *ctx, ed_pair *const *pairs, uint64_t count, int64_t k_max, 
 /* ---- introspection ---------------------------------------------------------- */
 typedef struct ed_stats {
     uint64_t n, m;
-    uint32_t bits_per_char;  /* 2 or 8, as detected */
+    uint32_t bits_per_char;  /* 2, 4 or 8, as detected */
     uint32_t engine;
     uint64_t rounds;          /* k of the last ed_distance (or batch) */
     uint64_t updates;         /* diagonal updates over all rounds */
@@ -246,6 +249,10 @@ typedef struct ed_stats {
     /* ED_FLAG_CERTIFY: hash-engine distances whose check failed (then answered
      * by the direct engine) */
     uint64_t certify_retries;
+    /* last ed_align (or certified distance): device bytes of its kept rows,
+     * segment rows and path, and the rounds per segment between kept rows */
+    uint64_t align_device_bytes;
+    uint64_t align_segment_rounds;
 } ed_stats;
 
 int ed_pair_stats(const ed_pair *pair, ed_stats *out);
@@ -275,6 +282,8 @@ int ed_autotune_batch(ed_ctx *ctx, ed_pair *const *pairs, uint64_t count, int64_
 #define ED_BUF_PACKED2 0 /* 2-bit words, char j at bits [2(j mod 32), +2) of word j/32 */
 #define ED_BUF_BYTES 1   /* 8-bit copy (only when bits_per_char = 8) */
 #define ED_BUF_TABLE 2   /* prefix table, floor(len/b) + 1 uint64 entries */
+#define ED_BUF_PACKED4 3 /* 4-bit words, char j at bits [4(j mod 16), +4) of word j/16 (only when
+                          * bits_per_char = 4) */
 /* Copies a pair buffer of string `which` (0 = A, 1 = B) to host memory `out`
  * (cap bytes); *len_out receives the byte length of the valid part. */
 int ed_pair_buffer(ed_ctx *ctx, const ed_pair *pair, int which, int kind, void *out, uint64_t cap,

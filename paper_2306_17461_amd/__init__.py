@@ -43,6 +43,7 @@ OP_MATCH, OP_SUB, OP_DEL, OP_INS = 0, 1, 2, 3
 BUF_PACKED2 = 0
 BUF_BYTES = 1
 BUF_TABLE = 2
+BUF_PACKED4 = 3
 NONE = -(1 << 30)
 NOALLOC_MAX_K = 500000
 MAX_LEN = 2146435072
@@ -83,7 +84,8 @@ class ed_stats(ctypes.Structure):
                 ("rounds_phase_a", ctypes.c_uint64), ("us_phase_a", ctypes.c_double),
                 ("us_phase_b", ctypes.c_double), ("gpu_ns_lcp_kernel", ctypes.c_double),
                 ("wg_lcps", ctypes.c_uint64), ("gpu_ns_table_kernel", ctypes.c_double),
-                ("certify_retries", ctypes.c_uint64)]
+                ("certify_retries", ctypes.c_uint64), ("align_device_bytes", ctypes.c_uint64),
+                ("align_segment_rounds", ctypes.c_uint64)]
 
 
 class ed_op_run(ctypes.Structure):

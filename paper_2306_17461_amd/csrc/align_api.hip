@@ -126,12 +126,14 @@ int ed::align_locked(ed_ctx* c, ed_pair* p, uint64_t* k_out, std::vector<PathSte
     std::vector<Checkpoint> ck{Checkpoint{0, nullptr}};
     int32_t* chunk = nullptr;
     int64_t chunk_left = 0;
+    uint64_t ck_bytes = 0;
     auto ck_alloc = [&](int64_t len) -> int32_t* {
         if (len > chunk_left) {
             const int64_t sz = std::max<int64_t>(len, int64_t(1) << 24);
             chunk = static_cast<int32_t*>(db.get(static_cast<size_t>(sz) * 4));
             if (!chunk) return nullptr;
             chunk_left = sz;
+            ck_bytes += static_cast<uint64_t>(sz) * 4;
         }
         int32_t* r = chunk;
         chunk += len;
@@ -239,6 +241,8 @@ int ed::align_locked(ed_ctx* c, ed_pair* p, uint64_t* k_out, std::vector<PathSte
         return ED_ENOMEM;
     }
     int32_t* d_state = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(d_path) + (k + 1) * sizeof(PathStep));
+    p->align_bytes = ck_bytes + static_cast<uint64_t>(seg_cap) * 4 + (k + 1) * sizeof(PathStep) + 64;
+    p->align_seg = static_cast<uint64_t>(segment_rounds(known >= 0 ? known : k));
     int32_t state[4] = {0, static_cast<int32_t>(n - m), 0, 0};
     for (size_t j = ck.size() - 1; j-- > 0;) {
         const int64_t tb = ck[j].t, te = ck[j + 1].t, L = te - tb;

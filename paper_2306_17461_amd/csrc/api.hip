@@ -367,7 +367,7 @@ void ed::pair_free(ed_pair* p) {
             (void)hipEventDestroy(e);
             e = nullptr;
         }
-    for (void** q : {&p->w2[0], &p->w2[1], &p->w8[0], &p->w8[1], &p->tab[0], &p->tab[1], &p->misc,
+    for (void** q : {&p->w2[0], &p->w2[1], &p->w4[0], &p->w4[1], &p->w8[0], &p->w8[1], &p->tab[0], &p->tab[1], &p->misc,
                      &p->stage[0], &p->stage[1], &p->f0, &p->f1}) {
         pool.put(*q);
         *q = nullptr;
@@ -379,6 +379,8 @@ PairDev ed::pair_dev(const ed_pair* p) {
     std::memset(&d, 0, sizeof d);
     d.a.w2 = static_cast<const uint64_t*>(p->w2[0]);
     d.b.w2 = static_cast<const uint64_t*>(p->w2[1]);
+    d.a.w4 = static_cast<const uint64_t*>(p->w4[0]);
+    d.b.w4 = static_cast<const uint64_t*>(p->w4[1]);
     d.a.w8 = static_cast<const uint64_t*>(p->w8[0]);
     d.b.w8 = static_cast<const uint64_t*>(p->w8[1]);
     d.a.tab = static_cast<const uint64_t*>(p->tab[0]);
@@ -428,6 +430,9 @@ int ed::prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B
     }
     p->r = c->r;
     const bool table = p->engine == ED_ENGINE_HASH;
+    // 4-bit words for alphabets up to 16 symbols: the direct engine reads any
+    // power-of-two width; the hash engine's partial-block hashes take 2 or 8
+    const bool nib = !table && c->opt.pack_bits == 0;
     const uint8_t* src[2] = {A, B};
     int32_t tiles[2];
     for (int s2 = 0; s2 < 2; ++s2) {
@@ -435,8 +440,9 @@ int ed::prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B
         tiles[s2] = static_cast<int32_t>(std::max<uint64_t>(1, (len + kTileChars - 1) / kTileChars));
         p->w2[s2] = c->pool.get((static_cast<size_t>(tiles[s2]) * kTileWords2 + kPadWords) * 8);
         p->w8[s2] = c->pool.get((static_cast<size_t>(tiles[s2]) * kTileWords8 + kPadWords) * 8);
+        if (nib) p->w4[s2] = c->pool.get((static_cast<size_t>(tiles[s2]) * kTileWords4 + kPadWords) * 8);
         if (table) p->tab[s2] = c->pool.get(((len >> p->log2b) + 1) * 8);
-        if (!p->w2[s2] || !p->w8[s2] || (table && !p->tab[s2])) {
+        if (!p->w2[s2] || !p->w8[s2] || (nib && !p->w4[s2]) || (table && !p->tab[s2])) {
             pair_free(p);
             delete p;
             set_error("ed_prepare: device allocation failed");
@@ -487,6 +493,7 @@ int ed::prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B
     for (int s2 = 0; s2 < 2; ++s2) {
         pp.s[s2].raw = raw[s2];
         pp.s[s2].w2 = static_cast<uint64_t*>(p->w2[s2]);
+        pp.s[s2].w4 = static_cast<uint64_t*>(p->w4[s2]);
         pp.s[s2].w8 = static_cast<uint64_t*>(p->w8[s2]);
         pp.s[s2].tab = static_cast<uint64_t*>(p->tab[s2]);
         pp.s[s2].len = static_cast<int32_t>(p->len[s2]);
@@ -834,7 +841,7 @@ int ed_pair_stats(const ed_pair* p, ed_stats* o) {
         set_error("ed_pair_stats: copy failed");
         return ED_EDEVICE;
     }
-    o->bits_per_char = (alpha <= 3u && !p->force8) ? 2 : 8;
+    o->bits_per_char = (alpha <= 3u && !p->force8) ? 2 : ((alpha <= 15u && p->w4[0] && !p->force8) ? 4 : 8);
     o->engine = p->engine;
     o->rounds = p->rounds;
     o->updates = p->counters.updates;
@@ -855,6 +862,8 @@ int ed_pair_stats(const ed_pair* p, ed_stats* o) {
     o->collision_bound = static_cast<double>(p->counters.hash_ne_len) / static_cast<double>(kP - (1ull << 21));
     o->launches = static_cast<uint64_t>(p->launches_distance);
     o->certify_retries = p->certify_retries;
+    o->align_device_bytes = p->align_bytes;
+    o->align_segment_rounds = p->align_seg;
     o->ns_prepare = p->ns_prepare;
     o->ns_distance = p->ns_distance;
     o->gpu_ns_frontier_kernel = p->gpu_ns_frontier;
@@ -887,6 +896,13 @@ int ed_pair_buffer(ed_ctx* c, const ed_pair* p, int which, int kind, void* out, 
     } else if (kind == ED_BUF_BYTES) {
         src = p->w8[which];
         bytes = len;
+    } else if (kind == ED_BUF_PACKED4) {
+        src = p->w4[which];
+        bytes = (len + 15) / 16 * 8;
+        if (!src) {
+            set_error("ed_pair_buffer: no 4-bit layout (hash engine or fixed pack_bits)");
+            return ED_EINVAL;
+        }
     } else if (kind == ED_BUF_TABLE) {
         src = p->tab[which];
         bytes = ((len >> p->log2b) + 1) * 8;

@@ -50,8 +50,8 @@ typedef const uint64_t __attribute__((address_space(1))) gword;
 struct SView {
     gword* w;
     int32_t len;
-    int32_t lcpw;  // 5 (2-bit) or 3 (8-bit)
-    int32_t bpc;   // 2 or 8
+    int32_t lcpw;  // 5 (2-bit), 4 (4-bit) or 3 (8-bit)
+    int32_t bpc;   // 2, 4 or 8
     int32_t lbpc;  // log2(bpc): shifts instead of divisions
 };
 
@@ -66,13 +66,14 @@ __device__ __forceinline__ uint64_t fetch(const SView& s, int32_t pos) {
 
 __device__ __forceinline__ void pair_views(const PairDev& p, uint32_t alpha, SView& A, SView& B) {
     const bool two = (alpha <= 3u) && !p.force8;
-    A.w = (gword*)(two ? p.a.w2 : p.a.w8);
-    B.w = (gword*)(two ? p.b.w2 : p.b.w8);
+    const bool four = !two && alpha <= 15u && !p.force8 && p.a.w4 && p.b.w4;
+    A.w = (gword*)(two ? p.a.w2 : (four ? p.a.w4 : p.a.w8));
+    B.w = (gword*)(two ? p.b.w2 : (four ? p.b.w4 : p.b.w8));
     A.len = p.a.len;
     B.len = p.b.len;
-    A.lcpw = B.lcpw = two ? 5 : 3;
-    A.bpc = B.bpc = two ? 2 : 8;
-    A.lbpc = B.lbpc = two ? 1 : 3;
+    A.lcpw = B.lcpw = two ? 5 : (four ? 4 : 3);
+    A.bpc = B.bpc = two ? 2 : (four ? 4 : 8);
+    A.lbpc = B.lbpc = two ? 1 : (four ? 2 : 3);
 }
 
 // ---------------------------------------------------------------------------

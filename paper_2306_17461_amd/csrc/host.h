@@ -74,6 +74,7 @@ struct ed_pair {
     int32_t force8 = 0;
     uint64_t r = 0;  // hash base its tables were built with
     void* w2[2] = {nullptr, nullptr};
+    void* w4[2] = {nullptr, nullptr};  // direct engine with automatic packing only
     void* w8[2] = {nullptr, nullptr};
     void* tab[2] = {nullptr, nullptr};
     void* stage[2] = {nullptr, nullptr};
@@ -94,6 +95,8 @@ struct ed_pair {
     double gpu_ns_frontier = 0;
     double gpu_ns_lcp = 0;  // last ed_debug_lcp with the grid tier (ED_FLAG_TIMING)
     uint64_t certify_retries = 0;  // ED_FLAG_CERTIFY: hash results whose check failed
+    uint64_t align_bytes = 0;      // last alignment: device bytes of kept rows, segment rows, path
+    uint64_t align_seg = 0;        // last alignment: rounds per segment
     // ed_align: a script that did not fit the caller's buffer, kept for the retry
     std::vector<ed_op_run> script;
     uint64_t script_k = 0;

@@ -20,11 +20,13 @@ constexpr int kPrepThreads = 256;
 constexpr int kSegChars = 64;
 constexpr int kTileChars = kPrepThreads * kSegChars;  // 16384
 constexpr int kTileWords2 = kTileChars / 32;          // 512 packed words per tile
+constexpr int kTileWords4 = kTileChars / 16;          // 1024 4-bit words per tile
 constexpr int kTileWords8 = kTileChars / 8;           // 2048 byte-words per tile
 // Streaming pass: one wavefront per chunk of 64 lanes x 64 characters.
 constexpr int kChunkChars = 64 * kSegChars;           // 4096
 constexpr int kTileChunks = kTileChars / kChunkChars;  // 4
 constexpr int kChunkWords2 = kChunkChars / 32;        // 128
+constexpr int kChunkWords4 = kChunkChars / 16;        // 256
 constexpr int kChunkWords8 = kChunkChars / 8;         // 512
 // Words of zero padding after the last tile of every packed buffer.
 constexpr int kPadWords = 256;
@@ -33,6 +35,8 @@ constexpr int kPadWords = 256;
 // One string as the kernels see it.
 struct StrDev {
     const uint64_t* w2;   // 2-bit packed words (complete when the pair is packable)
+    const uint64_t* w4;   // 4-bit words (direct engine; complete when every character is below 16
+                          // and above 3 somewhere), or nullptr
     const uint64_t* w8;   // 8-bit copy as words (written when not packable)
     const uint64_t* tab;  // prefix table (hash engine) or nullptr
     int32_t len;
@@ -174,6 +178,7 @@ struct TaskParams {
 struct PrepString {
     const uint8_t* raw;    // input bytes (device), 16-byte aligned
     uint64_t* w2;          // packed output
+    uint64_t* w4;          // 4-bit output (nullptr: no 4-bit layout for this pair)
     uint64_t* w8;          // 8-bit copy output
     uint64_t* tab;         // prefix table output (nullptr: no table)
     int32_t len;
@@ -195,8 +200,10 @@ struct PrepParams {
     uint64_t* chunk_tot;   // per chunk of 2048 tiles of each string: its hash (prefix scan)
     uint64_t* lane_excl;   // 64 per tile: hash of the tile's characters before each lane's 256
     uint32_t* alpha;       // OR of all characters (atomicOr), zeroed before launch
-    uint32_t* packed_any;  // nonzero when some chunk had no character > 3 (zeroed before launch)
-    uint8_t* chunk_big;    // per chunk (kTileChunks per tile): 1 if it has a character > 3
+    uint32_t* packed_any;  // bit c set when some chunk is of class c < 2 (zeroed before launch)
+    uint8_t* chunk_big;    // per chunk (kTileChunks per tile) its class: 0 no character > 3 (2-bit
+                           // words written), 1 some above 3, none above 15 and a 4-bit layout (4-bit
+                           // words written), 2 otherwise (8-bit copy written)
     const uint64_t* rtab;  // the kRtab* layout below
 };
 

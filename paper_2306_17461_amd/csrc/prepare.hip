@@ -41,6 +41,7 @@ struct TableShared {
 struct StrSel {
     const uint8_t* raw;
     uint64_t* w2;
+    uint64_t* w4;
     uint64_t* w8;
     uint64_t* tab;
     int32_t len;
@@ -48,6 +49,7 @@ struct StrSel {
     __device__ __forceinline__ StrSel(const PrepParams& P, bool second)
         : raw(second ? P.s[1].raw : P.s[0].raw),
           w2(second ? P.s[1].w2 : P.s[0].w2),
+          w4(second ? P.s[1].w4 : P.s[0].w4),
           w8(second ? P.s[1].w8 : P.s[0].w8),
           tab(second ? P.s[1].tab : P.s[0].tab),
           len(second ? P.s[1].len : P.s[0].len),
@@ -59,6 +61,11 @@ __device__ __forceinline__ int32_t imin32(int32_t a, int32_t b) { return a < b ?
 __device__ __forceinline__ uint32_t pack_dword(uint32_t d) {
     // four 8-bit characters -> four 2-bit codes (low bits of each byte)
     return (d & 3u) | ((d >> 6) & 0xCu) | ((d >> 12) & 0x30u) | ((d >> 18) & 0xC0u);
+}
+
+__device__ __forceinline__ uint64_t pack_nibbles(uint32_t d) {
+    // four 8-bit characters -> four 4-bit codes (low bits of each byte)
+    return (d & 0xFu) | ((d >> 4) & 0xF0u) | ((d >> 8) & 0xF00u) | ((d >> 12) & 0xF000u);
 }
 
 // Hash of a unit of U characters of a packed word (U = 4, 8, 16, 32; unit u
@@ -182,7 +189,7 @@ __global__ __launch_bounds__(kPrepThreads) void pack_kernel(PrepParams P) {
     // the block this lane ends up with in pair q: 64 q + lam
     const int32_t lam = (lane & 15) + 16 * (g4 >> 1) + 32 * (g4 & 1);
     uint32_t orr = 0;
-    uint32_t packed_any = 0;  // this wavefront packed a chunk (no character > 3)
+    uint32_t packed_any = 0;  // bit c: this wavefront wrote a chunk of class c < 2
     // chunk c (of its string) in v
     auto load = [&](const StrSel& str, int32_t c, u32x4 (&v)[4]) {
         const int32_t cbase = c * kChunkChars;
@@ -203,27 +210,35 @@ __global__ __launch_bounds__(kPrepThreads) void pack_kernel(PrepParams P) {
             }
         }
     };
-    // alphabet OR, 2-bit words or 8-bit copy, chunk flag
+    // alphabet OR, 2-bit words, 4-bit words or 8-bit copy, chunk class
     auto pack = [&](const StrSel& str, int32_t c, const u32x4 (&v)[4]) {
         uint32_t o = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) o |= v[k].x | v[k].y | v[k].z | v[k].w;
         orr |= o;
         const bool big = ballot((o & 0xFCFCFCFCu) != 0u) != 0;
+        const bool nib = big && str.w4 && ballot((o & 0xF0F0F0F0u) != 0u) == 0;
         if (!big) {
             uint32_t* dst = reinterpret_cast<uint32_t*>(str.w2 + static_cast<int64_t>(c) * kChunkWords2);
 #pragma unroll
             for (int k = 0; k < 4; ++k)
                 dst[k * 64 + (off >> 4)] = pack_dword(v[k].x) | (pack_dword(v[k].y) << 8) | (pack_dword(v[k].z) << 16) |
                                            (pack_dword(v[k].w) << 24);
+        } else if (nib) {
+            uint64_t* dst = str.w4 + static_cast<int64_t>(c) * kChunkWords4;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                dst[k * 64 + (off >> 4)] = pack_nibbles(v[k].x) | (pack_nibbles(v[k].y) << 16) |
+                                           (pack_nibbles(v[k].z) << 32) | (pack_nibbles(v[k].w) << 48);
         }
-        if (big || P.force8) {
+        if ((big && !nib) || P.force8) {
             u32x4* dst = reinterpret_cast<u32x4*>(str.w8 + static_cast<int64_t>(c) * kChunkWords8);
 #pragma unroll
             for (int k = 0; k < 4; ++k) dst[k * 64 + (off >> 4)] = v[k];
         }
-        if (lane == 0) P.chunk_big[str.tile0 * kTileChunks + c] = big ? 1 : 0;
-        packed_any |= big ? 0u : 1u;
+        const uint32_t cls = !big ? 0u : (nib ? 1u : 2u);
+        if (lane == 0) P.chunk_big[str.tile0 * kTileChunks + c] = static_cast<uint8_t>(cls);
+        packed_any |= cls < 2u ? (1u << cls) : 0u;
     };
     u32x4 v[4];
     if (!fuse) {
@@ -315,8 +330,9 @@ __global__ __launch_bounds__(kPrepThreads) void pack_kernel(PrepParams P) {
         for (int w = 0; w < kPrepThreads / 64; ++w) o |= wor[w];
         const uint32_t cur = __hip_atomic_load(P.alpha, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if ((cur | (o & 0xFFu)) != cur) atomicOr(P.alpha, o & 0xFFu);
-        if ((o >> 8) && !__hip_atomic_load(P.packed_any, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-            atomicOr(P.packed_any, 1u);
+        const uint32_t pa = o >> 8;
+        const uint32_t had = __hip_atomic_load(P.packed_any, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((had | pa) != had) atomicOr(P.packed_any, pa);
     }
 }
 
@@ -718,33 +734,51 @@ __global__ __launch_bounds__(kScanThreads) void table_scan_kernel(PrepParams P, 
     for (int i = tid; i < k.cn; i += kScanThreads) pre[i] = buf[i];
 }
 
-// Second pass for pairs that cannot be packed: 8-bit copy of the chunks the
-// first pass packed instead.  Exits at once when the pair is packable, or when
-// no chunk was packed.  Each wavefront reads the flags of 64 chunks at a time.
+// Second pass, once the pair's alphabet is known: the layout it is read in
+// (2-bit when no character is above 3; else 4-bit when none is above 15 and
+// the pair has a 4-bit layout; else 8-bit) for the chunks the first pass
+// wrote in a narrower one (chunk classes below the layout's).  Exits at once
+// when the 2-bit words are complete or no chunk needs it.  Each wavefront
+// reads the classes of 64 chunks at a time.
 __global__ __launch_bounds__(kPrepThreads) void copy8_rest_kernel(PrepParams P) {
     const uint32_t alpha = *P.alpha;
-    if (alpha <= 3u || P.force8 || *P.packed_any == 0u) return;
+    if (alpha <= 3u || P.force8) return;
+    const bool four = alpha <= 15u && P.s[0].w4 && P.s[1].w4;
+    const uint32_t below = four ? 1u : 2u;  // classes to rewrite: those below this
+    if ((*P.packed_any & ((1u << below) - 1u)) == 0u) return;
     const int lane = threadIdx.x & 63;
     const int32_t wave = __builtin_amdgcn_readfirstlane(static_cast<int32_t>((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
     const int32_t nwaves = static_cast<int32_t>((gridDim.x * blockDim.x) >> 6);
     const int32_t total = P.total_tiles * kTileChunks;
     const int32_t split = P.s[1].tile0 * kTileChunks;
     for (int32_t g0 = wave * 64; g0 < total; g0 += nwaves * 64) {
-        uint64_t todo = ballot(g0 + lane < total && !P.chunk_big[g0 + lane]);
+        uint64_t todo = ballot(g0 + lane < total && P.chunk_big[g0 + lane] < below);
         while (todo) {
             const int32_t g = g0 + ctz64(todo);
             todo &= todo - 1;
             const StrSel str(P, g >= split);
             const int32_t c = g - str.tile0 * kTileChunks;
             const int32_t seg_start = c * kChunkChars + lane * kSegChars;
-            uint64_t* dst = str.w8 + static_cast<int64_t>(c) * kChunkWords8 + lane * 8;
-            for (int k = 0; k < 8; ++k) {
-                uint64_t v = 0;
-                for (int j = 0; j < 8; ++j) {
-                    const int32_t p = seg_start + 8 * k + j;
-                    if (p < str.len) v |= static_cast<uint64_t>(str.raw[p]) << (8 * j);
+            if (four) {
+                uint64_t* dst = str.w4 + static_cast<int64_t>(c) * kChunkWords4 + lane * 4;
+                for (int k = 0; k < 4; ++k) {
+                    uint64_t v = 0;
+                    for (int j = 0; j < 16; ++j) {
+                        const int32_t p = seg_start + 16 * k + j;
+                        if (p < str.len) v |= static_cast<uint64_t>(str.raw[p] & 0xFu) << (4 * j);
+                    }
+                    dst[k] = v;
                 }
-                dst[k] = v;
+            } else {
+                uint64_t* dst = str.w8 + static_cast<int64_t>(c) * kChunkWords8 + lane * 8;
+                for (int k = 0; k < 8; ++k) {
+                    uint64_t v = 0;
+                    for (int j = 0; j < 8; ++j) {
+                        const int32_t p = seg_start + 8 * k + j;
+                        if (p < str.len) v |= static_cast<uint64_t>(str.raw[p]) << (8 * j);
+                    }
+                    dst[k] = v;
+                }
             }
         }
     }

@@ -68,5 +68,8 @@ def test_binding_constants_match_the_header():
                      ("ED_FLAG_SHUFFLE", "FLAG_SHUFFLE"), ("ED_FLAG_TIMING", "FLAG_TIMING"),
                      ("ED_FLAG_CERTIFY", "FLAG_CERTIFY"), ("ED_FLAG_WEAK_HASH", "FLAG_WEAK_HASH"),
                      ("ED_OP_MATCH", "OP_MATCH"), ("ED_OP_SUB", "OP_SUB"), ("ED_OP_DEL", "OP_DEL"),
-                     ("ED_OP_INS", "OP_INS"), ("ED_ECOLLISION", "ED_ECOLLISION"), ("ED_EINVAL", "ED_EINVAL")]:
+                     ("ED_OP_INS", "OP_INS"), ("ED_ECOLLISION", "ED_ECOLLISION"), ("ED_EINVAL", "ED_EINVAL"),
+                     ("ED_FLAG_NO_GRID_ROUNDS", "FLAG_NO_GRID_ROUNDS"), ("ED_FLAG_HASH_FIRST", "FLAG_HASH_FIRST"),
+                     ("ED_BUF_PACKED2", "BUF_PACKED2"), ("ED_BUF_BYTES", "BUF_BYTES"), ("ED_BUF_TABLE", "BUF_TABLE"),
+                     ("ED_BUF_PACKED4", "BUF_PACKED4")]:
         assert int(consts[name]) == getattr(ed, py), name

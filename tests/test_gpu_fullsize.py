@@ -102,6 +102,22 @@ def test_n1e9_zipf_and_periodic(ed, ctxs, name, engine):
         check_collision_bound(ed, ctxs, spec, st)
 
 
+@pytest.mark.parametrize("name", [g["name"] for g in GOLD["big"] if g["seed"] == 0])
+def test_n1e9_long_lcp_mode(ed, name):
+    """The hash engine's long-LCP mode (full prefix tables, b = 1; every slide
+    past the lane stage straight to the hash search) on the n = 1e9 pairs."""
+    spec = next(g for g in GOLD["big"] if g["name"] == name)
+    say("full", name, "long-LCP mode")
+    ctx = ed.ed_init(0, engine=ed.ENGINE_HASH, block=1, flags=ed.FLAG_TIMING | ed.FLAG_HASH_FIRST)
+    try:
+        k, st = run_on_stream(ed, ctx, spec)
+    finally:
+        ed.ed_shutdown(ctx)
+    assert k == spec["ed"]
+    assert st["hash_queries"] > 0 and st["wg_lcps"] == 0
+    check_collision_bound(ed, None, spec, st)
+
+
 # Largest accepted probability, over the hash base drawn from the seed, that a
 # hash-engine distance is wrong: one run in a million.  collision_bound is the
 # Schwartz-Zippel union bound over the verdicts that decided the run's hash
