@@ -55,6 +55,17 @@ PAPER_N1E8_SECONDS = {100: {"b_hash": 0.026, "hash": 0.052}, 1000: {"b_hash": 0.
                       10000: {"b_hash": 0.625, "hash": 0.538}, 100000: {"b_hash": 11.8, "hash": 9.46}}
 
 
+# The rest of that table (appendix, full runs): n = 10^6 .. 10^9, k = 1 .. 10^5,
+# the better of BFS-B-Hash and BFS-Hash (build + query, seconds; None where the
+# paper prints "< .001").
+PAPER_GRID_SECONDS = {
+    10 ** 6: {1: None, 10: None, 100: 0.002, 1000: 0.022, 10000: 0.362, 100000: 6.79},
+    10 ** 7: {1: 0.005, 10: 0.004, 100: 0.007, 1000: 0.028, 10000: 0.391, 100000: 8.03},
+    10 ** 8: {1: 0.022, 10: 0.028, 100: 0.026, 1000: 0.077, 10000: 0.538, 100000: 9.46},
+    10 ** 9: {1: 0.200, 10: 0.204, 100: 0.214, 1000: 0.268, 10000: 0.978, 100000: 12.0},
+}
+
+
 def paper_context(ks, n):
     if n != N or any(k not in PAPER_N1E8_SECONDS for k in ks):
         return None
@@ -339,9 +350,12 @@ def paper_shape_leg(ed, stream, reps=3):
 
 def align_leg(ed, dev, ks, want, stream, only=(1000, 10000, 100000)):
     """Checked (certified) hash-engine results: ed_align on the single pairs
-    (hash engine, b = 32): k, the edit script traced back through every
-    round's frontier row kept in device memory ((k+1)^2 * 4 bytes), and every
-    run of matches re-compared; wall time against the plain ed_distance."""
+    (hash engine, b = 32): k, the edit script traced back segment by segment
+    (the row at every S-th round kept, each segment's rounds run again with the
+    rows kept for the diagonals the path can reach), and every run of matches
+    re-compared; wall time against the plain ed_distance, first on a pair whose
+    k is known from that distance, then on a fresh pair (the segments' launches
+    then compute k)."""
     ctx = ed.ed_init(0, engine=ed.ENGINE_HASH)
     out = {}
     for i, k in enumerate(ks):
@@ -356,12 +370,21 @@ def align_leg(ed, dev, ks, want, stream, only=(1000, 10000, 100000)):
         t0 = time.perf_counter()
         ka, script = ed.ed_align(ctx, p, stream=stream)
         ta = time.perf_counter() - t0
+        st = ed.ed_pair_stats(p)
+        ed.ed_release(p)
+        p = ed.ed_prepare(ctx, tA, tB, stream=stream)
+        t0 = time.perf_counter()
+        kf, _ = ed.ed_align(ctx, p, stream=stream)
+        tf = time.perf_counter() - t0
         ed.ed_release(p)
         edits = sum(L for op, L in script if op != ed.OP_MATCH)
-        if not (kd == ka == want[i] == edits):
-            raise SystemExit("align leg: k=%d distance %d align %d edits %d want %d" % (k, kd, ka, edits, want[i]))
+        if not (kd == ka == kf == want[i] == edits):
+            raise SystemExit("align leg: k=%d distance %d align %d/%d edits %d want %d" % (k, kd, ka, kf, edits,
+                                                                                          want[i]))
         out[str(k)] = {"ed": ka, "script_runs": len(script), "distance_ms": round(td * 1e3, 3),
-                       "align_ms": round(ta * 1e3, 3), "rows_bytes": (ka + 1) ** 2 * 4, "checked": True}
+                       "align_after_distance_ms": round(ta * 1e3, 3), "align_fresh_pair_ms": round(tf * 1e3, 3),
+                       "segment_rounds": st["align_segment_rounds"], "device_bytes": st["align_device_bytes"],
+                       "every_row_bytes": (ka + 1) ** 2 * 4, "checked": True}
     ed.ed_shutdown(ctx)
     return out
 
@@ -569,15 +592,20 @@ def serve_full(ed, seeds=(0, 1, 2), sigmas=(4, 20), count=2200, warmup=200, per_
 
 def config3_leg(ed, seeds=(0, 1, 2)):
     """The n = 1e9 pairs (Zipf(1.0) over 256 symbols and its period-64
-    variant, k in {1e3, 1e5}, seeds 0..2), both engines, from device-resident
-    inputs: prepare and frontier kernel times (HIP events), chars/s over the
-    host wall time, equal to the stored oracle values."""
+    variant, k in {1e3, 1e5}, seeds 0..2), both engines and the hash engine's
+    long-LCP mode, from device-resident inputs: prepare and frontier kernel
+    times (HIP events), chars/s over the host wall time, equal to the stored
+    oracle values."""
     import torch
     import synth
     gold = stored_oracle() or {}
     want = {(g["periodic"], g["k"], g["seed"]): g["ed"] for g in gold.get("big", [])}
     ctxs = {"direct": ed.ed_init(0, engine=ed.ENGINE_DIRECT, flags=ed.FLAG_TIMING),
-            "hash": ed.ed_init(0, engine=ed.ENGINE_HASH, flags=ed.FLAG_TIMING)}
+            "hash": ed.ed_init(0, engine=ed.ENGINE_HASH, flags=ed.FLAG_TIMING),
+            # the long-LCP mode: full prefix tables (b = 1), every slide past the
+            # lane stage straight to the hash search
+            "hash_long_lcp": ed.ed_init(0, engine=ed.ENGINE_HASH, block=1,
+                                        flags=ed.FLAG_TIMING | ed.FLAG_HASH_FIRST)}
     rows = []
     for seed in seeds:
         for periodic in (False, True):
@@ -602,13 +630,66 @@ def config3_leg(ed, seeds=(0, 1, 2)):
                                  "prepare_kernel_ms": round(st["gpu_ns_prepare_kernel"] / 1e6, 3),
                                  "frontier_kernel_ms": round(st["gpu_ns_frontier_kernel"] / 1e6, 3),
                                  "wall_ms": round(wall * 1e3, 3), "chars_per_s": 10 ** 9 / wall,
-                                 "collision_bound": st["collision_bound"] if name == "hash" else None})
+                                 "collision_bound": st["collision_bound"] if name != "direct" else None})
                 del tA, tB
                 torch.cuda.empty_cache()
     for c in ctxs.values():
         ed.ed_shutdown(c)
     return {"workload": "n=1e9, Zipf(1.0) over 256 symbols and its period-64 variant, k in {1e3, 1e5}, seeds %s, "
                         "8 bits per character, from device-resident inputs" % list(seeds), "runs": rows}
+
+
+def paper_grid_leg(ed, reps=3):
+    """The paper's synthetic grid (uniform over 256 symbols, n = 1e6 .. 1e9,
+    k = 1 .. 1e5) and the stand-ins for its real-data rows (a DNA-like string of
+    42.3M characters over 4 symbols; text-like strings over Zipf-256 of 0.56M
+    and 6.47M characters), from device-resident inputs, both engines: prepare +
+    distance wall time (best of `reps`), every distance equal to the stored
+    oracle value, beside the paper's best full-run total where it has one."""
+    import torch
+    import synth
+    gold = stored_oracle() or {}
+    specs = ([("grid", g) for g in gold.get("paper_grid", [])] +
+             [("grid", g) for g in gold.get("paper", [])] +
+             [("shape", g) for g in gold.get("shapes", [])])
+    ctxs = {"direct": ed.ed_init(0, engine=ed.ENGINE_DIRECT), "hash": ed.ed_init(0, engine=ed.ENGINE_HASH)}
+    rows = []
+    for group, g in sorted(specs, key=lambda s: (s[0], s[1]["n"], s[1]["k"])):
+        A, B, _ = synth.single_pair(g["n"], g["k"], g["seed"], sigma=g["sigma"], kind=g["kind"])
+        tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        del A, B
+        row = {"set": group, "name": g["name"], "n": g["n"], "k_planted": g["k"], "ed": g["ed"]}
+        for name, ctx in ctxs.items():
+            log("paper grid: %s %s" % (g["name"], name))
+            best = None
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                p = ed.ed_prepare(ctx, tA, tB)
+                d = ed.ed_distance(ctx, p)
+                wall = time.perf_counter() - t0
+                ed.ed_release(p)
+                if d != g["ed"]:
+                    raise SystemExit("paper grid: %s %s distance %d, oracle %d" % (g["name"], name, d, g["ed"]))
+                best = wall if best is None else min(best, wall)
+            row[name + "_s"] = round(best, 6)
+        row["equal_to_stored_oracle"] = True
+        if group == "grid":
+            ps = PAPER_GRID_SECONDS.get(g["n"], {}).get(g["k"])
+            row["paper_s"] = ps
+            if ps:
+                row["paper_over_this"] = round(ps / min(row["direct_s"], row["hash_s"]), 1)
+        rows.append(row)
+        del tA, tB
+        torch.cuda.empty_cache()
+    for c in ctxs.values():
+        ed.ed_shutdown(c)
+    return {"workload": "uniform over 256 symbols, n in {1e6 .. 1e9}, k in {1, 10, 1e2 .. 1e5}, seed 0; "
+                        "DNA-like (42.3M, alphabet 4) and text-like (Zipf-256, 0.56M and 6.47M) pairs with the "
+                        "edit counts of the paper's real-data rows; prepare + distance from device-resident "
+                        "inputs, best of %d" % reps,
+            "paper_hardware": "96 cores (4x Intel Xeon Gold 6252), better of BFS-B-Hash and BFS-Hash, "
+                              "Monte Carlo hashing", "runs": rows}
 
 
 def pair_stats(ed, pair):
@@ -646,6 +727,8 @@ def main():
     ap.add_argument("--no-config3", action="store_true", help="skip the n=1e9 Zipf / periodic leg")
     ap.add_argument("--serve-full", action="store_true",
                     help="only the serving workload at its measured size (6 traces of 2200 requests)")
+    ap.add_argument("--paper-grid", action="store_true",
+                    help="only the paper's synthetic grid and the real-data shapes (stored oracle values)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -671,6 +754,9 @@ def main():
     import paper_2306_17461_amd as ed
     if args.serve_full:
         print(json.dumps({"serve_full": serve_full(ed)}))
+        return
+    if args.paper_grid:
+        print(json.dumps({"paper_grid": paper_grid_leg(ed)}))
         return
 
     ks = [int(x) for x in args.ks.split(",")]
