@@ -450,11 +450,16 @@ int ed::prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B
         }
     }
     const int32_t total = tiles[0] + tiles[1];
-    // alphabet word | tile hashes | chunk flags | tile prefixes | [lane prefixes | scan chunk hashes]
+    // pack: two workgroups per CU, each taking many chunks (more workgroups
+    // measured slower)
+    const int stream_grid = std::max(1, std::min(total, c->num_cu * 2));
+    // alphabet word | tile hashes | chunk flags | tile prefixes | pack workgroup slots |
+    // [lane prefixes | scan chunk hashes]
     const size_t agg_off = kMiscAlpha + 64;
     const size_t big_off = agg_off + static_cast<size_t>(total) * 8;
     const size_t pre_off = big_off + ((static_cast<size_t>(total) * kTileChunks + 7) & ~size_t(7));
-    const size_t lane_off = pre_off + static_cast<size_t>(total) * 8;
+    const size_t wor_off = pre_off + static_cast<size_t>(total) * 8;
+    const size_t lane_off = wor_off + ((static_cast<size_t>(stream_grid) * 4 + 7) & ~size_t(7));
     const size_t tot_off = lane_off + (table ? static_cast<size_t>(total) * 64 * 8 : 0);
     p->misc = c->pool.get(tot_off + (table ? 2 * 64 * 8 : 0));
     if (!p->misc) {
@@ -514,13 +519,12 @@ int ed::prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B
     pp.alpha = reinterpret_cast<uint32_t*>(misc + kMiscAlpha);
     pp.packed_any = reinterpret_cast<uint32_t*>(misc + kMiscAlpha + 4);
     pp.chunk_big = reinterpret_cast<uint8_t*>(misc + big_off);
+    pp.wg_or = reinterpret_cast<uint32_t*>(misc + wor_off);
+    pp.pack_grid = stream_grid;
+    pp.scan_chunks = (tiles[0] + kScanChunkTiles - 1) / kScanChunkTiles + (tiles[1] + kScanChunkTiles - 1) / kScanChunkTiles;
     pp.rtab = c->d_pow + 2 * 65536;
-    // pack: two workgroups per CU, each taking many chunks (more workgroups
-    // measured slower); table passes: as many workgroups as fit by LDS (at
-    // most one tile per wavefront)
-    const int stream_grid = std::max(1, std::min(total, c->num_cu * 2));
+    // table passes: as many workgroups as fit by LDS (at most one tile per wavefront)
     const int table_grid = c->num_cu * 4;
-    HIP_TRY(launch_prep_clear(pp, s));
     if (c->opt.flags & ED_FLAG_TIMING) {
         HIP_TRY(hipEventCreate(&p->ev_prep[0]));
         HIP_TRY(hipEventCreate(&p->ev_prep[1]));
@@ -529,14 +533,13 @@ int ed::prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B
         p->prep_timed = true;
     }
     HIP_TRY(launch_pack(pp, stream_grid, s));
-    // usually exits at once (packable pair): a small grid keeps that cheap
-    if (c->opt.pack_bits != 2) HIP_TRY(launch_copy8_rest(pp, std::max(1, std::min(total, c->num_cu)), s));
-    if (table) {
-        if (p->prep_timed) HIP_TRY(hipEventRecord(p->ev_prep[2], s));
-        HIP_TRY(launch_table(pp, table_grid, s));
-    }
+    if (table && p->prep_timed) HIP_TRY(hipEventRecord(p->ev_prep[2], s));
+    // the rest pass usually has nothing to do (a packable pair): a small grid
+    // keeps that cheap
+    HIP_TRY(launch_after_pack(pp, std::max(1, std::min(total, c->num_cu)), s));
+    if (table) HIP_TRY(launch_table(pp, table_grid, s));
     if (p->prep_timed) HIP_TRY(hipEventRecord(p->ev_prep[1], s));
-    p->launches_prepare = 2 + (c->opt.pack_bits != 2 ? 1 : 0) + (table ? 1 : 0);
+    p->launches_prepare = 2 + (table ? (pp.fuse_table ? 2 : 4) : 0);
     if (c->opt.pack_bits == 2) {
         uint32_t alpha = 0;
         HIP_TRY(hipMemcpyAsync(&alpha, pp.alpha, 4, hipMemcpyDeviceToHost, s));

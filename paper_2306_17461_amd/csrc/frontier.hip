@@ -289,7 +289,7 @@ __device__ __forceinline__ void grid_segments(const SView& A, const SView& B, in
 // direct engine queues the LCP and the whole workgroup extends it after the
 // round barrier (the queue and its counter alternate with the round parity,
 // so the next round's pushes never meet this round's reads).
-template <int WGW, typename PrevPtr, typename CurPtr>
+template <int WGW, int KU = kU, typename PrevPtr, typename CurPtr>
 __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr prev, CurPtr cur,
                                             int32_t ofs, int32_t i_begin, int32_t i_end, RoundShared& RS,
                                             JobCursor& jc, int32_t* dump_row, int32_t dlo, int32_t dhi,
@@ -309,12 +309,12 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
     // diagonals all lie past i_end is skipped by the whole wavefront
     const int32_t wbase = __builtin_amdgcn_readfirstlane(tid & ~63);
     const int32_t qmask = (1 << en.A.lcpw) - 1;
-    for (int32_t base = i_begin; base < i_end; base += nthr * kU) {
-        int32_t iv[kU], c[kU], l[kU], lim[kU];
-        bool val[kU], act[kU], pend[kU], queued[kU], slot[kU];
-        uint64_t wa[kU][2], wb[kU][2];
+    for (int32_t base = i_begin; base < i_end; base += nthr * KU) {
+        int32_t iv[KU], c[KU], l[KU], lim[KU];
+        bool val[KU], act[KU], pend[KU], queued[KU], slot[KU];
+        uint64_t wa[KU][2], wb[KU][2];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
+        for (int u = 0; u < KU; ++u) {
             slot[u] = base + u * nthr + wbase < i_end;
             const int32_t i = base + u * nthr + tid;
             iv[u] = i;
@@ -344,7 +344,7 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
         // from any offset), issued for every slot before any use: one memory
         // latency per pass.  Idle lanes read word 0 (always there).
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
+        for (int u = 0; u < KU; ++u) {
             if (!slot[u]) continue;
             const bool go = lim[u] > 0;
             const int32_t qa = go ? c[u] >> en.A.lcpw : 0;
@@ -355,7 +355,7 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
             wb[u][1] = en.B.w[qb + 1];
         }
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
+        for (int u = 0; u < KU; ++u) {
             l[u] = 0;
             pend[u] = false;
             queued[u] = false;
@@ -375,12 +375,12 @@ __device__ __forceinline__ bool round_range(const Engine& en, int32_t t, PrevPtr
         }
         // (2)/(3) the wavefront extends its lanes' long LCPs
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
+        for (int u = 0; u < KU; ++u) {
             if (!slot[u]) continue;
             wave_extend(en, pend[u], c[u], iv[u], lim[u], l[u], queued[u], RS, par, half, jstart, lane, cnt);
         }
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
+        for (int u = 0; u < KU; ++u) {
             if (!slot[u]) continue;
             // (a queued diagonal is written by the workgroup tier)
             const int32_t f = val[u] ? c[u] + l[u] : kNone;
@@ -1089,9 +1089,14 @@ __global__ __launch_bounds__(kFrontierThreads) void frontier_kernel(FrontierPara
                 for (int32_t s = 1; s <= H; ++s) {
                     const int32_t tt = t + s;
                     const DumpAt d = dump_at(P, dump, tt, imax(a, -tt), imin(b, tt));
-                    if (round_range<kWgWords>(en, tt, rp, rc, wofs, a - (H - s), b + (H - s) + 1, RS, jc, d.row, d.lo,
-                                              d.hi, cnt))
-                        atomicMin(&ctl->found_t, tt);
+                    // one diagonal per thread when the window fits the workgroup
+                    const bool one = (b - a + 1) + 2 * (H - s) <= kFrontierThreads;
+                    const bool hit =
+                        one ? round_range<kWgWords, 1>(en, tt, rp, rc, wofs, a - (H - s), b + (H - s) + 1, RS, jc,
+                                                       d.row, d.lo, d.hi, cnt)
+                            : round_range<kWgWords, kU>(en, tt, rp, rc, wofs, a - (H - s), b + (H - s) + 1, RS, jc,
+                                                        d.row, d.lo, d.hi, cnt);
+                    if (hit) atomicMin(&ctl->found_t, tt);
                     int32_t* tmp = rp;
                     rp = rc;
                     rc = tmp;

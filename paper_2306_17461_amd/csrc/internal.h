@@ -30,6 +30,8 @@ constexpr int kChunkWords4 = kChunkChars / 16;        // 256
 constexpr int kChunkWords8 = kChunkChars / 8;         // 512
 // Words of zero padding after the last tile of every packed buffer.
 constexpr int kPadWords = 256;
+// Tiles per chunk of the scan of the tile hashes (one workgroup per chunk).
+constexpr int kScanChunkTiles = 2048;
 
 
 // One string as the kernels see it.
@@ -199,8 +201,11 @@ struct PrepParams {
     uint64_t* tile_prefix; // total_tiles entries: hash of its string before each tile
     uint64_t* chunk_tot;   // per chunk of 2048 tiles of each string: its hash (prefix scan)
     uint64_t* lane_excl;   // 64 per tile: hash of the tile's characters before each lane's 256
-    uint32_t* alpha;       // OR of all characters (atomicOr), zeroed before launch
-    uint32_t* packed_any;  // bit c set when some chunk is of class c < 2 (zeroed before launch)
+    uint32_t* alpha;       // OR of all characters (written by after_pack_kernel)
+    uint32_t* packed_any;  // bit c set when some chunk is of class c < 2 (after_pack_kernel)
+    uint32_t* wg_or;       // pack_grid slots: each pack workgroup's OR | classes << 8
+    int32_t pack_grid;     // workgroups of the pack launch
+    int32_t scan_chunks;   // workgroups of the scan: chunks of kScanChunk tiles of both strings
     uint8_t* chunk_big;    // per chunk (kTileChunks per tile) its class: 0 no character > 3 (2-bit
                            // words written), 1 some above 3, none above 15 and a 4-bit layout (4-bit
                            // words written), 2 otherwise (8-bit copy written)
@@ -244,10 +249,11 @@ struct LcpQueryParams {
 };
 
 // Kernel launchers (defined in the .hip files).
-hipError_t launch_prep_clear(const PrepParams& pp, hipStream_t s);
 hipError_t launch_pack(const PrepParams& pp, int grid, hipStream_t s);
+// after the pack kernel, always: the pair's alphabet and chunk classes, the
+// rest pass, and (block hashes taken by the pack kernel) the chunk totals
+hipError_t launch_after_pack(const PrepParams& pp, int grid, hipStream_t s);
 hipError_t launch_table(const PrepParams& pp, int grid, hipStream_t s);
-hipError_t launch_copy8_rest(const PrepParams& pp, int grid, hipStream_t s);
 // cnt: kMaxGrid + 1 counter slots (one per workgroup, then their sum)
 // One step of a traced path: at round t the path is on diagonal i, its run of
 // matches is [c, f) (x = characters of A consumed), and (c, c - i) follows from

@@ -1,13 +1,14 @@
 // Prepare a pair: the input bytes of both strings are read once.
 //   pack_kernel   streaming, one wavefront per 4096-character chunk:
 //                 alphabet detection (bitwise OR of every character; 2-bit
-//                 packing is possible when the OR is <= 3), 2-bit packing of
-//                 every chunk without a character > 3, and an 8-bit copy of
-//                 every chunk with one (the rest of the copy, when the pair
-//                 cannot be packed, is written by copy8_rest_kernel); with
-//                 prefix tables of block size 32 it also takes the block
-//                 hashes of the input bytes on the matrix cores and the first
-//                 table pass;
+//                 packing is possible when the OR is <= 3), each chunk in the
+//                 narrowest layout its characters allow (2-bit words, 4-bit
+//                 words, or the 8-bit copy); with prefix tables of block size
+//                 32 it also takes the block hashes of the input bytes on the
+//                 matrix cores and the first table pass;
+//   after_pack_kernel  the pair's alphabet from the pack workgroups' slots,
+//                 the chunks the pair's layout still lacks (rest pass), and
+//                 at b = 32 the chunk totals of the tile-hash scan;
 //   table_*       (hash engine) prefix table T[j] = h(S[0..jb)) mod 2^61-1
 //                 (sections 3.2 and 3.3, Algorithm 2 "Build"): block hashes
 //                 (matrix products at b = 32, else LDS lookup tables over the
@@ -91,13 +92,6 @@ __device__ __forceinline__ uint64_t word_hash8(const TableShared& S, uint64_t w)
 
 }  // namespace
 
-__global__ void prep_clear_kernel(PrepParams P) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i == 0) {
-        *P.alpha = 0u;
-        *P.packed_any = 0u;
-    }
-}
 
 // Block hashes of 32 characters on the matrix cores.  h of a block is linear
 // in its characters, h = sum_j c_j r^(31 - j), and with each weight written
@@ -316,8 +310,8 @@ __global__ __launch_bounds__(kPrepThreads) void pack_kernel(PrepParams P) {
             cc = ncc;
         }
     }
-    // one atomic per workgroup at most, and none when the bits are already
-    // there: atomics on one address from every wavefront serialise
+    // this workgroup's alphabet OR and chunk classes in a slot of its own
+    // (no atomics, nothing to clear first); after_pack_kernel reduces them
     __shared__ uint32_t wor[kPrepThreads / 64];
     orr |= orr >> 16;
     orr |= orr >> 8;
@@ -328,16 +322,12 @@ __global__ __launch_bounds__(kPrepThreads) void pack_kernel(PrepParams P) {
     if (threadIdx.x == 0) {
         uint32_t o = 0;
         for (int w = 0; w < kPrepThreads / 64; ++w) o |= wor[w];
-        const uint32_t cur = __hip_atomic_load(P.alpha, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((cur | (o & 0xFFu)) != cur) atomicOr(P.alpha, o & 0xFFu);
-        const uint32_t pa = o >> 8;
-        const uint32_t had = __hip_atomic_load(P.packed_any, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((had | pa) != had) atomicOr(P.packed_any, pa);
+        P.wg_or[blockIdx.x] = o;
     }
 }
 
 // Prefix tables of both strings (hash engine), after pack_kernel (and
-// copy8_rest_kernel), in three passes with no shared counter.  A tile of
+// after_pack_kernel), in three passes with no shared counter.  A tile of
 // 16384 characters is one wavefront's work, 256 consecutive characters per
 // lane; tiles are assigned statically to wavefronts.
 //   table_tiles_kernel<false>  per tile: the hash of each lane's characters
@@ -630,6 +620,8 @@ __global__ __launch_bounds__(kPrepThreads) void table_tiles_kernel(PrepParams P,
 // the padding only follows the last real tile.  Powers of R come from the
 // host.
 constexpr int kScanThreads = 256, kScanPer = 8, kScanChunk = kScanThreads * kScanPer;  // 2048 tiles
+static_assert(kScanChunk == kScanChunkTiles, "scan chunk size");
+static_assert(kScanThreads == kPrepThreads, "after_pack_kernel folds chunks with the pack block size");
 constexpr int kScanWaves = kScanThreads / 64;
 
 struct ScanChunk {
@@ -673,7 +665,7 @@ __device__ __forceinline__ uint64_t scan_fold(const uint64_t* agg, int32_t cn, c
     return h;
 }
 
-__global__ __launch_bounds__(kScanThreads) void table_total_kernel(PrepParams P, const uint64_t* rtab) {
+__device__ __forceinline__ void chunk_total(const PrepParams& P, const uint64_t* rtab) {
     __shared__ uint64_t wtot[kScanWaves];
     const int tid = threadIdx.x;
     const ScanChunk k = scan_chunk(P);
@@ -687,6 +679,10 @@ __global__ __launch_bounds__(kScanThreads) void table_total_kernel(PrepParams P,
         for (int w = 0; w < kScanWaves; ++w) x = mp_add(mp_mul(x, Rw), wtot[w]);
         P.chunk_tot[blockIdx.x] = x;
     }
+}
+
+__global__ __launch_bounds__(kScanThreads) void table_total_kernel(PrepParams P, const uint64_t* rtab) {
+    chunk_total(P, rtab);
 }
 
 __global__ __launch_bounds__(kScanThreads) void table_scan_kernel(PrepParams P, const uint64_t* rtab) {
@@ -737,15 +733,14 @@ __global__ __launch_bounds__(kScanThreads) void table_scan_kernel(PrepParams P, 
 // Second pass, once the pair's alphabet is known: the layout it is read in
 // (2-bit when no character is above 3; else 4-bit when none is above 15 and
 // the pair has a 4-bit layout; else 8-bit) for the chunks the first pass
-// wrote in a narrower one (chunk classes below the layout's).  Exits at once
+// wrote in a narrower one (chunk classes below the layout's).  Nothing to do
 // when the 2-bit words are complete or no chunk needs it.  Each wavefront
 // reads the classes of 64 chunks at a time.
-__global__ __launch_bounds__(kPrepThreads) void copy8_rest_kernel(PrepParams P) {
-    const uint32_t alpha = *P.alpha;
+__device__ __forceinline__ void rest_pass(const PrepParams& P, uint32_t alpha, uint32_t classes) {
     if (alpha <= 3u || P.force8) return;
     const bool four = alpha <= 15u && P.s[0].w4 && P.s[1].w4;
     const uint32_t below = four ? 1u : 2u;  // classes to rewrite: those below this
-    if ((*P.packed_any & ((1u << below) - 1u)) == 0u) return;
+    if ((classes & ((1u << below) - 1u)) == 0u) return;
     const int lane = threadIdx.x & 63;
     const int32_t wave = __builtin_amdgcn_readfirstlane(static_cast<int32_t>((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
     const int32_t nwaves = static_cast<int32_t>((gridDim.x * blockDim.x) >> 6);
@@ -784,16 +779,34 @@ __global__ __launch_bounds__(kPrepThreads) void copy8_rest_kernel(PrepParams P) 
     }
 }
 
+// The kernel after pack_kernel: every workgroup reduces the pack kernel's
+// per-workgroup slots to the pair's alphabet OR and chunk classes (workgroup
+// 0 stores them for the later kernels and the host), runs the rest pass, and
+// with block hashes taken by the pack kernel the first scan_chunks workgroups
+// also fold their chunk of tile hashes (the first pass of the scan below).
+__global__ __launch_bounds__(kPrepThreads) void after_pack_kernel(PrepParams P, const uint64_t* rtab) {
+    __shared__ uint32_t red[kPrepThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63;
+    uint32_t v = 0;
+    for (int i = tid; i < P.pack_grid; i += kPrepThreads) v |= P.wg_or[i];
+    for (int s = 32; s > 0; s >>= 1) v |= __shfl_xor(v, s);
+    if (lane == 0) red[tid >> 6] = v;
+    __syncthreads();
+    uint32_t o = 0;
+    for (int w = 0; w < kPrepThreads / 64; ++w) o |= red[w];
+    const uint32_t alpha = o & 0xFFu, classes = o >> 8;
+    if (blockIdx.x == 0 && tid == 0) {
+        *P.alpha = alpha;
+        *P.packed_any = classes;
+    }
+    rest_pass(P, alpha, classes);
+    if (P.fuse_table && static_cast<int32_t>(blockIdx.x) < P.scan_chunks) chunk_total(P, rtab);
+}
+
 __global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x)
         p[i] = v;
-}
-
-hipError_t launch_prep_clear(const PrepParams& pp, hipStream_t s) {
-    const int blocks = (pp.total_tiles + 255) / 256 + 1;
-    hipLaunchKernelGGL(prep_clear_kernel, dim3(blocks), dim3(256), 0, s, pp);
-    return hipGetLastError();
 }
 
 hipError_t launch_pack(const PrepParams& pp, int grid, hipStream_t s) {
@@ -812,11 +825,12 @@ hipError_t launch_table(const PrepParams& pp, int grid, hipStream_t s) {
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    const int32_t t1 = pp.s[1].tile0;
-    const int chunks = (t1 + kScanChunk - 1) / kScanChunk + (pp.total_tiles - t1 + kScanChunk - 1) / kScanChunk;
-    hipLaunchKernelGGL(table_total_kernel, dim3(chunks), dim3(kScanThreads), 0, s, pp, pp.rtab);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    const int chunks = pp.scan_chunks;
+    if (!pp.fuse_table) {  // else after_pack_kernel folded the chunks
+        hipLaunchKernelGGL(table_total_kernel, dim3(chunks), dim3(kScanThreads), 0, s, pp, pp.rtab);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(table_scan_kernel, dim3(chunks), dim3(kScanThreads), 0, s, pp, pp.rtab);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -829,8 +843,9 @@ hipError_t launch_table(const PrepParams& pp, int grid, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_copy8_rest(const PrepParams& pp, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(copy8_rest_kernel, dim3(grid), dim3(kPrepThreads), 0, s, pp);
+hipError_t launch_after_pack(const PrepParams& pp, int grid, hipStream_t s) {
+    if (pp.fuse_table && grid < pp.scan_chunks) grid = pp.scan_chunks;
+    hipLaunchKernelGGL(after_pack_kernel, dim3(grid), dim3(kPrepThreads), 0, s, pp, pp.rtab);
     return hipGetLastError();
 }
 
