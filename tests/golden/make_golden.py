@@ -17,6 +17,8 @@ Workloads:
     DNA-like string (n = 42.3M, alphabet 4 uniform) and text-like ones
     (Zipf(1.0) over 256 symbols, n = 0.56M and 6.47M), each with three
     numbers of planted edits taken from that table;
+  * a pair of the longest strings the library accepts (n = 2^31 - 2^20 - 64,
+    alphabet 4, 10 planted edits);
   * the 4096-pair batch (n log-uniform in [10^3, 10^6], k uniform in
     [0, 0.01 n], alphabet 4), seeds 0, 1, 2;
   * the first 40 requests of the mixed-alphabet serving trace (n log-uniform
@@ -33,7 +35,7 @@ Workloads:
 Entries already in the file with the same specification are kept (the
 script only computes what is missing); --force recomputes everything.
 
-Usage: python tests/golden/make_golden.py [--only single|big|paper|grid|shapes|batch|serve|trace] [--force]
+Usage: python tests/golden/make_golden.py [--only single|big|paper|grid|shapes|maxlen|batch|serve|trace] [--force]
 (the single pairs at n = 10^9 need ~10 GB of RAM).
 """
 import argparse
@@ -76,6 +78,9 @@ SHAPES = ([dict(name="dna_like_k%d" % k, n=42_300_000, k=k, seed=0, kind="unifor
            for k in (439, 5578, 15026)] +
           [dict(name="linux_like_k%d" % k, n=6_470_000, k=k, seed=0, kind="zipf", sigma=256, periodic=False)
            for k in (236, 1447, 9559)])
+# the longest strings the library accepts (both below 2^31 - 2^20 characters)
+MAXLEN = [dict(name="maxlen_sigma4_k10", n=2 ** 31 - 2 ** 20 - 64, k=10, seed=0, kind="uniform", sigma=4,
+               periodic=False)]
 BATCH = [dict(name="batch4096_seed%d" % s, count=4096, seed=s) for s in SEEDS]
 SERVE = dict(name="serve40_seed0", count=40, seed=0)
 TRACE_COUNT = 2200
@@ -192,7 +197,8 @@ def _merge(old, specs, fn, force):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--only", choices=["single", "big", "paper", "grid", "shapes", "batch", "serve", "trace"])
+    ap.add_argument("--only", choices=["single", "big", "paper", "grid", "shapes", "maxlen", "batch", "serve",
+                                       "trace"])
     ap.add_argument("--force", action="store_true")
     args = ap.parse_args()
     oracle.build(force=False)
@@ -223,6 +229,9 @@ def main():
         save()
     if args.only in (None, "shapes"):
         data["shapes"] = _merge(data.get("shapes"), SHAPES, single, args.force)
+        save()
+    if args.only in (None, "maxlen"):
+        data["maxlen"] = _merge(data.get("maxlen"), MAXLEN, single, args.force)
         save()
     if args.only in (None, "batch"):
         data["batch"] = _merge(data.get("batch"), BATCH, batch, args.force)

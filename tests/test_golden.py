@@ -39,6 +39,8 @@ def test_golden_file_complete(gold):
     assert sorted((g["n"], g["k"]) for g in gold["shapes"]) == sorted(
         [(42_300_000, k) for k in (928, 9162, 91419)] + [(560_000, k) for k in (439, 5578, 15026)] +
         [(6_470_000, k) for k in (236, 1447, 9559)])
+    assert [(g["n"], g["k"]) for g in gold["maxlen"]] == [(2 ** 31 - 2 ** 20 - 64, 10)]
+    assert all(g["n"] < 2 ** 31 - 2 ** 20 and g["m"] < 2 ** 31 - 2 ** 20 for g in gold["maxlen"])
     assert [b["seed"] for b in gold["batch"]] == list(seeds)
     assert all(len(b["eds"]) == b["count"] == 4096 for b in gold["batch"])
     assert len(gold["serve"]["eds"]) == gold["serve"]["count"] == 40
@@ -47,7 +49,7 @@ def test_golden_file_complete(gold):
     for t in gold["serve_trace"]:
         assert t["count"] >= 2200 and t["warmup"] == 200 and len(t["index"]) == len(t["eds"])
     # distance bounds of planted edits: |n - m| <= ED <= k
-    for g in gold["single"] + gold["big"] + gold["paper"] + gold["paper_grid"] + gold["shapes"]:
+    for g in gold["single"] + gold["big"] + gold["paper"] + gold["paper_grid"] + gold["shapes"] + gold["maxlen"]:
         assert abs(g["n"] - g["m"]) <= g["ed"] <= g["k_planted"]
 
 

@@ -182,6 +182,28 @@ def test_real_data_shapes(ed, ctxs, name, engine):
         check_collision_bound(ed, ctxs, spec, st)
 
 
+@pytest.mark.parametrize("engine", ["direct", "hash"])
+def test_longest_accepted_strings(ed, ctxs, engine):
+    """Both strings just below the length limit (2^31 - 2^20 characters), 10
+    planted edits: every position and offset of the kernels stays in range."""
+    spec = GOLD["maxlen"][0]
+    assert spec["n"] < ed.ED_MAX_LEN and spec["m"] < ed.ED_MAX_LEN
+    say("full", spec["name"], engine)
+    k, st = run_on_stream(ed, ctxs[engine], spec)
+    assert k == spec["ed"]
+    assert st["rounds"] == spec["ed"] and st["bits_per_char"] == 2
+
+
+def test_length_limit_rejected(ed, ctxs):
+    # a string of ED_MAX_LEN characters is refused before anything is read
+    import ctypes
+    buf = np.zeros(64, np.uint8)
+    out = ctypes.c_void_p()
+    for n, m in ((ed.ED_MAX_LEN, 1), (1, ed.ED_MAX_LEN)):
+        rc = ed.lib.ed_prepare(ctxs["direct"], buf.ctypes.data, n, buf.ctypes.data, m, 0, None, ctypes.byref(out))
+        assert rc == ed.ED_EINVAL and not out.value
+
+
 def _gen_pairs(specs):
     def one(s):
         n, k, ps = s
