@@ -609,8 +609,9 @@ __global__ __launch_bounds__(kPrepThreads) void table_tiles_kernel(PrepParams P,
 
 // Pass 2: prefix[u] = h(S[0 .. 16384 u)) from the tile hashes, with
 // R = r^16384, in chunks of kScanChunk tiles, one workgroup per chunk of each
-// string (the chunks of string 0 first), in two launches: table_total_kernel
-// folds each chunk to its hash (Horner's rule), table_scan_kernel takes the
+// string (the chunks of string 0 first), in two launches: chunk_total (in
+// after_pack_kernel at b = 32, else table_total_kernel) folds each chunk to
+// its hash (Horner's rule), table_scan_kernel takes the
 // hash of the string before its chunk from those of the earlier chunks (one
 // term per lane, times R^(kScanChunk d), summed over the wavefront) and scans
 // its chunk with it.  Within a chunk each thread folds 8 consecutive tiles,
