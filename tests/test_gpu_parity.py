@@ -294,6 +294,8 @@ FRONTIER_MODES = [
     ("blk7g3", dict(lds_rounds=4, block_rounds=7, grid_blocks=3)),
     ("g1", dict(lds_rounds=2, block_rounds=5, grid_blocks=1)),
     ("grid7", dict(flags=2, block_rounds=7)),
+    # hash engine: long slides straight to the hash search, full table (no-op for the direct engine)
+    ("hfirst", dict(flags=128, block=1, lds_rounds=4, block_rounds=5)),
 ]
 
 
@@ -328,6 +330,26 @@ def test_frontier_rows(ed, make_ctx, orc, engine, mode):
 # ---------------------------------------------------------------------------
 # distances
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("block", [1, 32])
+def test_hash_first_mode_distances(ed, make_ctx, orc, block):
+    # the long-LCP mode: every slide past the lane stage goes to the hash
+    # search (alphabet 4 and 256, a period-64 string, long planted runs)
+    ctx = make_ctx(engine=ed.ENGINE_HASH, block=block, flags=ed.FLAG_HASH_FIRST)
+    d4, d256 = synth.CharDist("uniform", 4), synth.CharDist("uniform", 256)
+    cases = [synth.single_pair(200000, 300, 61), synth.single_pair(300000, 50, 62, sigma=256)]
+    P = synth.periodic_string(400000, d4, 63, period=64)
+    Q, _ = synth.plant_edits(P, 80, d4, 64)
+    cases.append((P, Q, None))
+    for i, (A, B, _) in enumerate(cases):
+        say("hash first", block, i)
+        p = ed.ed_prepare(ctx, A, B)
+        try:
+            k = ed.ed_distance(ctx, p)
+            st = ed.ed_pair_stats(p)
+        finally:
+            ed.ed_release(p)
+        assert k == orc.lv_omp(A, B, -1, 1), i
+        assert st["wg_lcps"] == 0
 def test_config1_all_seeds_direct(ed, make_ctx, orc):
     ctx = make_ctx(engine=0)
     for seed in range(100):
