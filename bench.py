@@ -350,12 +350,13 @@ def paper_shape_leg(ed, stream, reps=3):
 
 def align_leg(ed, dev, ks, want, stream, only=(1000, 10000, 100000)):
     """Checked (certified) hash-engine results: ed_align on the single pairs
-    (hash engine, b = 32): k, the edit script traced back segment by segment
-    (the row at every S-th round kept, each segment's rounds run again with the
-    rows kept for the diagonals the path can reach), and every run of matches
-    re-compared; wall time against the plain ed_distance, first on a pair whose
-    k is known from that distance, then on a fresh pair (the segments' launches
-    then compute k)."""
+    (hash engine, b = 32): k, the edit script traced back, and every run of
+    matches re-compared; wall time against the plain ed_distance, first on a
+    pair whose k is known from that distance (one launch keeps the cone of rows
+    the path can reach, when it fits an eighth of the free device memory), then
+    on a fresh pair (segments: the row at every S-th round kept, k computed by
+    the segments' launches, each segment run again with the rows kept for the
+    diagonals the path can reach)."""
     ctx = ed.ed_init(0, engine=ed.ENGINE_HASH)
     out = {}
     for i, k in enumerate(ks):

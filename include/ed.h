@@ -66,6 +66,8 @@ extern "C" {
 #define ED_FLAG_HASH_FIRST 128u /* hash engine: a slide that runs past the lane stage goes to the
                                  * wavefront's hash search at once (no direct steps); for pairs
                                  * with many long slides */
+#define ED_FLAG_ALIGN_SEGMENTS 256u /* ed_align: keep rows in segments even when k is known and the
+                                    * cone of rows fits (tests of the segmented form) */
 #define ED_FLAG_WEAK_HASH 32u  /* fault injection for tests: hash base r = 1 (every permutation of
                                 * a string hashes alike), so that collisions happen */
 
@@ -129,7 +131,9 @@ int ed_shutdown(ed_ctx *ctx);
 int ed_prepare(ed_ctx *ctx, const uint8_t *A, uint64_t n, const uint8_t *B, uint64_t m,
                int inputs_on_device, void *hip_stream, ed_pair **out);
 
-/* Frees the pair's device buffers. */
+/* Frees the pair's device buffers (back to the context's pool).  Waits for the
+ * pair's prepare kernels if they are still queued on the caller's stream (every
+ * other call on a pair returns after its work), not for the whole device. */
 int ed_release(ed_pair *pair);
 
 /*

@@ -38,6 +38,7 @@ FLAG_CERTIFY = 16
 FLAG_WEAK_HASH = 32
 FLAG_NO_GRID_ROUNDS = 64
 FLAG_HASH_FIRST = 128
+FLAG_ALIGN_SEGMENTS = 256
 ED_MAX_LEN = 2146435072  # 2^31 - 2^20 characters
 OP_MATCH, OP_SUB, OP_DEL, OP_INS = 0, 1, 2, 3
 BUF_PACKED2 = 0

@@ -24,23 +24,26 @@ __device__ __forceinline__ int32_t amin(int32_t a, int32_t b) { return a < b ? a
 // rounds of the walk stay within kTbRows + 1 diagonals of the current one:
 // the wavefront loads that band of the next kTbRows rows into LDS (one load
 // per lane and row, all in flight together), then one lane takes the steps.
-// The rows are those of rounds tb .. te restricted to the diagonals
-// [wlo, wlo + w) (row u at dump[(u - tb) * w], diagonal j at + j - wlo); the
-// walk starts on diagonal i_end of round te, so with wlo <= i_end - (te - tb)
-// - 1 and wlo + w > i_end + (te - tb) + 1 every cell it reads is in the window.
-// It ends at round tb, whose diagonal and row value it leaves in state[1],
-// state[2] (state[0]: 0 ok, 1 the walk did not end at (0, 0), 2 no candidate).
+// The rows are those of rounds tb .. te in layout L (row u holds diagonals
+// [lo(u), hi(u)]); the walk starts on diagonal i_end of round te, and every
+// cell it reads lies within te - u + 1 diagonals of i_end at row u, which
+// the layout keeps.  It ends at round tb, whose diagonal and row value it
+// leaves in state[1], state[2] (state[0]: 0 ok, 1 the walk did not end at
+// (0, 0), 2 no candidate).
 constexpr int kTbRows = 30;
 
-__global__ __launch_bounds__(64) void traceback_kernel(const int32_t* dump, int32_t tb, int32_t te, int32_t i_end,
-                                                       int32_t wlo, int32_t w, int32_t n, int32_t m, PathStep* out,
+__global__ __launch_bounds__(64) void traceback_kernel(const int32_t* dump, KeepLayout L, int32_t tb, int32_t te,
+                                                       int32_t i_end, int32_t n, int32_t m, PathStep* out,
                                                        int32_t* state) {
     __shared__ int32_t band[kTbRows][64];  // band[r][l]: row t0 - 1 - r, diagonal ic - 32 + l
     __shared__ int32_t sh[4];              // i, f, t, finished
     const int lane = threadIdx.x;
     if (lane == 0) {
+        int32_t lo, hi;
+        int64_t off;
+        keep_row(L, te, lo, hi, off);
         sh[0] = i_end;
-        sh[1] = dump[static_cast<int64_t>(te - tb) * w + (i_end - wlo)];
+        sh[1] = dump[off + (i_end - lo)];
         sh[2] = te;
         sh[3] = 0;
         state[0] = 0;
@@ -63,9 +66,10 @@ __global__ __launch_bounds__(64) void traceback_kernel(const int32_t* dump, int3
         for (int32_t r = 0; r < R; ++r) {
             const int32_t u = t0 - 1 - r;
             const int32_t j = ic - 32 + lane;
-            band[r][lane] = (j >= -u && j <= u && j >= wlo && j < wlo + w)
-                                ? dump[static_cast<int64_t>(u - tb) * w + (j - wlo)]
-                                : kNone;
+            int32_t lo, hi;
+            int64_t off;
+            keep_row(L, u, lo, hi, off);
+            band[r][lane] = (j >= -u && j <= u && j >= lo && j <= hi) ? dump[off + (j - lo)] : kNone;
         }
         __syncthreads();
         if (lane == 0) {
@@ -129,9 +133,9 @@ __global__ __launch_bounds__(256) void verify_kernel(PairDev p, const VerifySeg*
     if (ballot(diff != 0) && lane == 0) atomicOr(bad, 1u);
 }
 
-hipError_t launch_traceback(const int32_t* dump, int32_t tb, int32_t te, int32_t i_end, int32_t wlo, int32_t w,
+hipError_t launch_traceback(const int32_t* dump, const KeepLayout& L, int32_t tb, int32_t te, int32_t i_end,
                             int32_t n, int32_t m, PathStep* out, int32_t* state, hipStream_t s) {
-    hipLaunchKernelGGL(traceback_kernel, dim3(1), dim3(64), 0, s, dump, tb, te, i_end, wlo, w, n, m, out, state);
+    hipLaunchKernelGGL(traceback_kernel, dim3(1), dim3(64), 0, s, dump, L, tb, te, i_end, n, m, out, state);
     return hipGetLastError();
 }
 

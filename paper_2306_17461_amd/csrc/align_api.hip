@@ -79,8 +79,10 @@ int64_t path_cost(const std::vector<PathStep>& path, int64_t n, int64_t m) {
 // Rounds per segment between kept rows.  The kept rows of a distance k take
 // about k^2 / S entries and one segment's window of rows about 2 S^2, least
 // for S near (k^2 / 4)^(1/3); S grows with the rounds when k is not known
-// yet.  At least kMinSegment rounds, so that a launch does real work.
-constexpr int64_t kMinSegment = 256;
+// yet.  At least kMinSegment rounds, so that the launches (a few tens of
+// microseconds each, with a traceback and a synchronisation per segment) stay
+// few.
+constexpr int64_t kMinSegment = 1024;
 
 int64_t segment_rounds(int64_t k) {
     const double kk = static_cast<double>(std::max<int64_t>(k, 1));
@@ -150,9 +152,21 @@ int ed::align_locked(ed_ctx* c, ed_pair* p, uint64_t* k_out, std::vector<PathSte
         return frontier_once(c, fp, s, &gpu_ns);
     };
 
+    // with k known, one launch may keep every row the path can reach (the
+    // cone of diagonals within k - u of the end at round u, about k^2 / 2
+    // entries) when that fits an eighth of the free device memory: no kept
+    // rows, no segments
+    const int64_t iend = n - m;
+    bool cone = false;
+    if (known >= 0 && !(c->opt.flags & ED_FLAG_ALIGN_SEGMENTS)) {
+        size_t free_b = 0, total_b = 0;
+        cone = hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
+               static_cast<uint64_t>(cone_total(known)) * 4 <= free_b / 8;
+    }
+
     // forward: the rounds in segments, the row at each segment's end kept
     // (with k unknown, these launches are the distance's)
-    int64_t k = -1;
+    int64_t k = cone ? known : -1;
     CountersDev total;
     std::memset(&total, 0, sizeof total);
     int launches = 0;
@@ -227,65 +241,107 @@ int ed::align_locked(ed_ctx* c, ed_pair* p, uint64_t* k_out, std::vector<PathSte
     }
     ck.push_back(Checkpoint{k, nullptr});
 
-    // backward: each segment's rounds again from its first row, the rows kept
-    // for the diagonals the path can reach, and the path traced through them
-    int64_t seg_cap = 0;
-    for (size_t j = 0; j + 1 < ck.size(); ++j) {
-        const int64_t L = ck[j + 1].t - ck[j].t;
-        seg_cap = std::max(seg_cap, (L + 1) * (2 * L + 5));
-    }
-    int32_t* d_seg = static_cast<int32_t*>(db.get(static_cast<size_t>(seg_cap) * 4));
     PathStep* d_path = static_cast<PathStep*>(db.get((k + 1) * sizeof(PathStep) + 64));
-    if (!d_seg || !d_path) {
+    if (!d_path) {
         set_error("ed_align: device allocation failed");
         return ED_ENOMEM;
     }
     int32_t* d_state = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(d_path) + (k + 1) * sizeof(PathStep));
-    p->align_bytes = ck_bytes + static_cast<uint64_t>(seg_cap) * 4 + (k + 1) * sizeof(PathStep) + 64;
-    p->align_seg = static_cast<uint64_t>(segment_rounds(known >= 0 ? known : k));
-    int32_t state[4] = {0, static_cast<int32_t>(n - m), 0, 0};
-    for (size_t j = ck.size() - 1; j-- > 0;) {
-        const int64_t tb = ck[j].t, te = ck[j + 1].t, L = te - tb;
-        const int64_t i_end = state[1];
-        const int64_t wlo = i_end - L - 2, w = 2 * L + 5;
-        hipError_t e = hipSuccess;
-        if (tb > 0) {
-            // the segment's first row: into the frontier row, and its window into the dump
-            e = hipMemcpyAsync(rows.r[cur] + (K + 2) - (tb + 2), ck[j].row, static_cast<size_t>(2 * tb + 5) * 4,
-                               hipMemcpyDeviceToDevice, s);
-            const int64_t d0 = std::max(wlo, -tb), d1 = std::min(wlo + w - 1, tb);
-            if (e == hipSuccess && d0 <= d1)
-                e = hipMemcpyAsync(d_seg + (d0 - wlo), ck[j].row + (d0 + tb + 2), static_cast<size_t>(d1 - d0 + 1) * 4,
-                                   hipMemcpyDeviceToDevice, s);
+    int32_t state[4] = {0, static_cast<int32_t>(iend), 0, 0};
+    if (cone) {
+        // one launch from round 0 with the cone of rows kept, one traceback
+        const int64_t tot = cone_total(k);
+        int32_t* d_keep = static_cast<int32_t*>(db.get(static_cast<size_t>(tot) * 4));
+        if (!d_keep) {
+            set_error("ed_align: device allocation failed");
+            return ED_ENOMEM;
         }
-        if (e != hipSuccess) {
-            set_error("ed_align: row copy failed: %s", hipGetErrorString(e));
-            return ED_EDEVICE;
-        }
-        fp.dump = d_seg;
-        fp.dump_cap = (L + 1) * w;
-        fp.dump_t0 = static_cast<int32_t>(tb);
-        fp.dump_lo = static_cast<int32_t>(wlo);
-        fp.dump_w = static_cast<int32_t>(w);
-        rc = launch(tb, te);
+        fp.dump = d_keep;
+        fp.dump_cap = tot;
+        fp.dump_cone = 1;
+        fp.dump_t0 = 0;
+        fp.dump_iend = static_cast<int32_t>(iend);
+        fp.dump_kend = static_cast<int32_t>(k);
+        rc = launch(0, k);
         if (rc != ED_OK) return rc;
         const FrontierCtl& st = *c->h_ctl;
-        const bool last = te == k;
-        if (st.status != (last ? 1 : 2) || st.result_t != (last ? k : te + 1)) {
-            set_error("ed_align: segment [%lld, %lld] ended with status %d at t=%d", (long long)tb, (long long)te,
-                      st.status, st.result_t);
+        if (st.status != 1 || st.result_t != k) {
+            set_error("ed_align: the rounds ended with status %d at t=%d, the distance is %lld", st.status,
+                      st.result_t, (long long)k);
             return ED_EINTERNAL;
         }
-        e = launch_traceback(d_seg, static_cast<int32_t>(tb), static_cast<int32_t>(te), static_cast<int32_t>(i_end),
-                             static_cast<int32_t>(wlo), static_cast<int32_t>(w), static_cast<int32_t>(n),
-                             static_cast<int32_t>(m), d_path, d_state, s);
+        const KeepLayout L{1, 0, 0, 0, static_cast<int32_t>(iend), static_cast<int32_t>(k)};
+        hipError_t e = launch_traceback(d_keep, L, 0, static_cast<int32_t>(k), static_cast<int32_t>(iend),
+                             static_cast<int32_t>(n), static_cast<int32_t>(m), d_path, d_state, s);
         if (e == hipSuccess) e = hipMemcpyAsync(state, d_state, 3 * 4, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) {
             set_error("ed_align: traceback failed: %s", hipGetErrorString(e));
             return ED_EDEVICE;
         }
-        if (state[0] != 0) break;
+        p->align_bytes = static_cast<uint64_t>(tot) * 4 + (k + 1) * sizeof(PathStep) + 64;
+        p->align_seg = static_cast<uint64_t>(k);
+    } else {
+        // backward: each segment's rounds again from its first row, the rows
+        // kept for the diagonals the path can reach, and the path traced
+        // through them
+        int64_t seg_cap = 0;
+        for (size_t j = 0; j + 1 < ck.size(); ++j) {
+            const int64_t L = ck[j + 1].t - ck[j].t;
+            seg_cap = std::max(seg_cap, (L + 1) * (2 * L + 5));
+        }
+        int32_t* d_seg = static_cast<int32_t*>(db.get(static_cast<size_t>(seg_cap) * 4));
+        if (!d_seg) {
+            set_error("ed_align: device allocation failed");
+            return ED_ENOMEM;
+        }
+        p->align_bytes = ck_bytes + static_cast<uint64_t>(seg_cap) * 4 + (k + 1) * sizeof(PathStep) + 64;
+        p->align_seg = static_cast<uint64_t>(segment_rounds(known >= 0 ? known : k));
+        for (size_t j = ck.size() - 1; j-- > 0;) {
+            const int64_t tb = ck[j].t, te = ck[j + 1].t, L = te - tb;
+            const int64_t i_end = state[1];
+            const int64_t wlo = i_end - L - 2, w = 2 * L + 5;
+            hipError_t e = hipSuccess;
+            if (tb > 0) {
+                // the segment's first row: into the frontier row, and its window into the dump
+                e = hipMemcpyAsync(rows.r[cur] + (K + 2) - (tb + 2), ck[j].row, static_cast<size_t>(2 * tb + 5) * 4,
+                                   hipMemcpyDeviceToDevice, s);
+                const int64_t d0 = std::max(wlo, -tb), d1 = std::min(wlo + w - 1, tb);
+                if (e == hipSuccess && d0 <= d1)
+                    e = hipMemcpyAsync(d_seg + (d0 - wlo), ck[j].row + (d0 + tb + 2),
+                                       static_cast<size_t>(d1 - d0 + 1) * 4, hipMemcpyDeviceToDevice, s);
+            }
+            if (e != hipSuccess) {
+                set_error("ed_align: row copy failed: %s", hipGetErrorString(e));
+                return ED_EDEVICE;
+            }
+            fp.dump = d_seg;
+            fp.dump_cap = (L + 1) * w;
+            fp.dump_cone = 0;
+            fp.dump_t0 = static_cast<int32_t>(tb);
+            fp.dump_lo = static_cast<int32_t>(wlo);
+            fp.dump_w = static_cast<int32_t>(w);
+            rc = launch(tb, te);
+            if (rc != ED_OK) return rc;
+            const FrontierCtl& st = *c->h_ctl;
+            const bool last = te == k;
+            if (st.status != (last ? 1 : 2) || st.result_t != (last ? k : te + 1)) {
+                set_error("ed_align: segment [%lld, %lld] ended with status %d at t=%d", (long long)tb, (long long)te,
+                          st.status, st.result_t);
+                return ED_EINTERNAL;
+            }
+            const KeepLayout Lw{0, static_cast<int32_t>(tb), static_cast<int32_t>(wlo), static_cast<int32_t>(w), 0, 0};
+            e = launch_traceback(d_seg, Lw, static_cast<int32_t>(tb), static_cast<int32_t>(te),
+                                 static_cast<int32_t>(i_end), static_cast<int32_t>(n), static_cast<int32_t>(m), d_path,
+                                 d_state, s);
+            if (e == hipSuccess) e = hipMemcpyAsync(state, d_state, 3 * 4, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) {
+                set_error("ed_align: traceback failed: %s", hipGetErrorString(e));
+                return ED_EDEVICE;
+            }
+            if (state[0] != 0) break;
+        }
     }
     path.assign(k + 1, PathStep{});
     hipError_t e = hipMemcpyAsync(path.data(), d_path, (k + 1) * sizeof(PathStep), hipMemcpyDeviceToHost, s);

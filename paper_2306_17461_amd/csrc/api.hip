@@ -367,6 +367,10 @@ void ed::pair_free(ed_pair* p) {
             (void)hipEventDestroy(e);
             e = nullptr;
         }
+    if (p->ev_done) {
+        (void)hipEventDestroy(p->ev_done);
+        p->ev_done = nullptr;
+    }
     for (void** q : {&p->w2[0], &p->w2[1], &p->w4[0], &p->w4[1], &p->w8[0], &p->w8[1], &p->tab[0], &p->tab[1], &p->misc,
                      &p->stage[0], &p->stage[1], &p->f0, &p->f1}) {
         pool.put(*q);
@@ -551,6 +555,12 @@ int ed::prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B
             return ED_EINVAL;
         }
     }
+    // (without the event, ed_release waits for the whole device instead)
+    if (hipEventCreateWithFlags(&p->ev_done, hipEventDisableTiming) != hipSuccess) p->ev_done = nullptr;
+    if (p->ev_done && hipEventRecord(p->ev_done, s) != hipSuccess) {
+        (void)hipEventDestroy(p->ev_done);
+        p->ev_done = nullptr;
+    }
     *out = p;
     return ED_OK;
 }
@@ -573,8 +583,12 @@ int ed_release(ed_pair* p) {
     ed_ctx* c = p->ctx;
     std::lock_guard<std::mutex> lk(c->mu);
     (void)hipSetDevice(c->device);
-    // buffers may still be read by queued work on a caller stream
-    (void)hipDeviceSynchronize();
+    // the prepare's kernels may still be queued on the caller's stream; every
+    // other call on a pair returns after its work
+    if (p->ev_done)
+        (void)hipEventSynchronize(p->ev_done);
+    else
+        (void)hipDeviceSynchronize();
     pair_free(p);
     delete p;
     return ED_OK;

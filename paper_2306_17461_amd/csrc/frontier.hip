@@ -546,7 +546,17 @@ __device__ __forceinline__ DumpAt dump_at(const FrontierParams& P, int32_t* dump
                                           int32_t hi) {
     DumpAt d{nullptr, lo, hi};
     if (!dump || t < P.dump_t0) return d;
-    if (P.dump_w > 0) {
+    if (P.dump_cone) {
+        if (t > P.dump_kend || cone_off(t + 1, P.dump_kend) > P.dump_cap) return d;
+        const KeepLayout L{1, P.dump_t0, 0, 0, P.dump_iend, P.dump_kend};
+        int32_t klo, khi;
+        int64_t off;
+        keep_row(L, t, klo, khi, off);
+        d.lo = imax(lo, klo);
+        d.hi = imin(hi, khi);
+        // row[i + t] = dump[off + i - klo] for i in [lo, hi]
+        d.row = dump + (off - klo - t);
+    } else if (P.dump_w > 0) {
         const int64_t r = t - P.dump_t0;
         if ((r + 1) * P.dump_w > P.dump_cap) return d;
         d.lo = imax(lo, P.dump_lo);

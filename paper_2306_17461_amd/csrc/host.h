@@ -91,6 +91,9 @@ struct ed_pair {
     double ns_prepare = 0, ns_distance = 0;
     // around the prepare kernels, and before the table kernels (ED_FLAG_TIMING)
     hipEvent_t ev_prep[3] = {nullptr, nullptr, nullptr};
+    // recorded after the prepare's kernels on the caller's stream: the only
+    // work on a pair that a call leaves queued (the others synchronise)
+    hipEvent_t ev_done = nullptr;
     bool prep_timed = false;
     double gpu_ns_frontier = 0;
     double gpu_ns_lcp = 0;  // last ed_debug_lcp with the grid tier (ED_FLAG_TIMING)

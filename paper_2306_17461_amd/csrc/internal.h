@@ -116,16 +116,18 @@ struct FrontierParams {
     unsigned int* bar;  // kMaxGrid lines of kBarStride uint32
     int32_t* gpart;     // grid rounds: 2 x kGridJobs x kMaxGrid per-workgroup first mismatches
     // optional per-round rows (device) from round dump_t0 on (a resumed launch
-    // dumps from its start round): with dump_w = 0 every diagonal, row t at
-    // t*t - dump_t0*dump_t0 and diagonal i at + t + i; with dump_w > 0 only
-    // diagonals [dump_lo, dump_lo + dump_w), row t at (t - dump_t0) * dump_w
-    // and diagonal i at + i - dump_lo.  Rows past dump_cap entries are dropped.
+    // dumps from its start round): with dump_w = 0 and no dump_rows every
+    // diagonal, row t at t*t - dump_t0*dump_t0 and diagonal i at + t + i;
+    // otherwise the rows of the KeepLayout {dump_cone, dump_t0, dump_lo,
+    // dump_w, dump_iend, dump_kend}.  Rows past dump_cap entries are dropped.
     int32_t* dump;
     int64_t dump_cap;
+    int32_t dump_cone;
     int32_t dump_t0;
     int32_t dump_lo;
     int32_t dump_w;
-    int32_t pad3_;
+    int32_t dump_iend;
+    int32_t dump_kend;
     CountersDev* counters;
 };
 
@@ -275,12 +277,47 @@ struct VerifySeg {
 };
 
 hipError_t launch_ctl_init(FrontierCtl* ctl, CountersDev* cnt, unsigned int* bar, hipStream_t s);
+// Rows kept for a traceback, from round t0 on: row u holds the diagonals
+// [lo(u), hi(u)] at dump[off(u) + j - lo(u)].
+//   window (cone = 0): lo = wlo, hi = wlo + w - 1, off = (u - t0) w;
+//   cone (cone = 1, t0 = 0): the diagonals that a path ending on diagonal
+//   iend at round kend can visit, lo(u) = max(-u, iend - (kend - u)),
+//   hi(u) = min(u, iend + (kend - u)); row u has room for min(2u + 1,
+//   2(kend - u) + 1) entries, so with h = floor(kend / 2) off(u) = u^2 for
+//   u <= h + 1, else (h + 1)^2 + (kend - h)^2 - (kend - u + 1)^2, and the
+//   rows of rounds 0 .. kend take cone_total(kend) = off(kend + 1) entries.
+struct KeepLayout {
+    int32_t cone, t0, wlo, w, iend, kend;
+};
+
+__host__ __device__ inline int64_t cone_off(int64_t u, int64_t k) {
+    const int64_t h = k / 2;
+    return u <= h + 1 ? u * u : (h + 1) * (h + 1) + (k - h) * (k - h) - (k - u + 1) * (k - u + 1);
+}
+
+__host__ __device__ inline int64_t cone_total(int64_t k) { return cone_off(k + 1, k); }
+
+__host__ __device__ inline void keep_bounds(const KeepLayout& L, int32_t u, int32_t& lo, int32_t& hi) {
+    if (L.cone) {
+        const int32_t a = L.iend - (L.kend - u), b = L.iend + (L.kend - u);
+        lo = a > -u ? a : -u;
+        hi = b < u ? b : u;
+    } else {
+        lo = L.wlo;
+        hi = L.wlo + L.w - 1;
+    }
+}
+
+__host__ __device__ inline void keep_row(const KeepLayout& L, int32_t u, int32_t& lo, int32_t& hi, int64_t& off) {
+    keep_bounds(L, u, lo, hi);
+    off = L.cone ? cone_off(u, L.kend) : static_cast<int64_t>(u - L.t0) * L.w;
+}
+
 // The steps of an optimal path for rounds te .. tb + 1 (and round 0 when tb
-// = 0) from the frontier rows of rounds tb .. te kept for diagonals [wlo, wlo
-// + w) (row u at dump[(u - tb) * w], diagonal i at + i - wlo), starting on
-// diagonal i_end of round te; state: [0] 0 ok, 1 bad start, 2 no candidate;
-// [1], [2] the path's diagonal and row value at round tb.
-hipError_t launch_traceback(const int32_t* dump, int32_t tb, int32_t te, int32_t i_end, int32_t wlo, int32_t w,
+// = 0) from the frontier rows of rounds tb .. te kept in layout L (L.t0 =
+// tb), starting on diagonal i_end of round te; state: [0] 0 ok, 1 bad start,
+// 2 no candidate; [1], [2] the path's diagonal and row value at round tb.
+hipError_t launch_traceback(const int32_t* dump, const KeepLayout& L, int32_t tb, int32_t te, int32_t i_end,
                             int32_t n, int32_t m, PathStep* out, int32_t* state, hipStream_t s);
 // Sets *bad (nonzero) when some segment's characters differ.
 hipError_t launch_verify(const PairDev& p, const VerifySeg* segs, int64_t count, uint32_t* bad, int grid,

@@ -71,5 +71,5 @@ def test_binding_constants_match_the_header():
                      ("ED_OP_INS", "OP_INS"), ("ED_ECOLLISION", "ED_ECOLLISION"), ("ED_EINVAL", "ED_EINVAL"),
                      ("ED_FLAG_NO_GRID_ROUNDS", "FLAG_NO_GRID_ROUNDS"), ("ED_FLAG_HASH_FIRST", "FLAG_HASH_FIRST"),
                      ("ED_BUF_PACKED2", "BUF_PACKED2"), ("ED_BUF_BYTES", "BUF_BYTES"), ("ED_BUF_TABLE", "BUF_TABLE"),
-                     ("ED_BUF_PACKED4", "BUF_PACKED4")]:
+                     ("ED_BUF_PACKED4", "BUF_PACKED4"), ("ED_FLAG_ALIGN_SEGMENTS", "FLAG_ALIGN_SEGMENTS")]:
         assert int(consts[name]) == getattr(ed, py), name

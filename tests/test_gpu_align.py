@@ -101,15 +101,19 @@ def test_align_script_is_optimal(ed, make_ctx, orc, engine, pack_bits, name):
     say("align", name, engine, pack_bits, len(A), len(B))
     ctx = make_ctx(engine=engine, pack_bits=pack_bits)
     want = orc.lv_omp(A, B, -1, 1)
-    p = ed.ed_prepare(ctx, A, B)
-    try:
-        k, script = ed.ed_align(ctx, p)
-    finally:
-        ed.ed_release(p)
-    assert k == want
-    assert apply_script(ed, A, B, script) == k
-    # runs are merged: no two neighbours share an operation
-    assert all(script[j][0] != script[j + 1][0] for j in range(len(script) - 1))
+    for first in ("align", "distance"):
+        # a fresh pair (segments) and one whose distance is known (the cone of rows)
+        p = ed.ed_prepare(ctx, A, B)
+        try:
+            if first == "distance":
+                assert ed.ed_distance(ctx, p) == want
+            k, script = ed.ed_align(ctx, p)
+        finally:
+            ed.ed_release(p)
+        assert k == want
+        assert apply_script(ed, A, B, script) == k
+        # runs are merged: no two neighbours share an operation
+        assert all(script[j][0] != script[j + 1][0] for j in range(len(script) - 1))
 
 
 @pytest.mark.parametrize("block", [1, 32])
@@ -127,7 +131,7 @@ def test_certified_hash_distance(ed, make_ctx, orc, block):
 
 
 def test_align_large_pair_both_engines(ed, make_ctx, orc):
-    # 10^6 characters, about 2000 edits: segments of 256 rounds between kept rows
+    # 10^6 characters, about 2000 edits: two segments of 1024 rounds between kept rows
     A, B, _ = synth.single_pair(10 ** 6, 2000, 21)
     want = orc.lv_omp(A, B)
     for engine in (0, 1):
@@ -140,16 +144,19 @@ def test_align_large_pair_both_engines(ed, make_ctx, orc):
         assert apply_script(ed, A, B, script) == k
 
 
+@pytest.mark.parametrize("form", ["auto", "segments"])
 @pytest.mark.parametrize("engine", [0, 1])
-def test_align_segments_known_and_unknown_k(ed, make_ctx, orc, engine):
-    # about 5000 edits: 20 segments of 256 rounds; the path crosses every
+def test_align_segments_known_and_unknown_k(ed, make_ctx, orc, engine, form):
+    # about 5000 edits: 5 segments of 1024 rounds; the path crosses every
     # segment boundary.  Without a distance before, the segments' launches
-    # compute k; after one, the last forward segment is skipped.
+    # compute k; after one, k is known: the rows of the cone the path can
+    # reach are kept in one launch ("auto"), or the segments run with the
+    # last forward one skipped ("segments")
     A, B, _ = synth.single_pair(300000, 5000, 23, sigma=4)
     want = orc.lv_omp(A, B)
-    ctx = make_ctx(engine=engine)
+    ctx = make_ctx(engine=engine, flags=ed.FLAG_ALIGN_SEGMENTS if form == "segments" else 0)
     for first in ("align", "distance"):
-        say("align segments", engine, first)
+        say("align segments", engine, form, first)
         p = ed.ed_prepare(ctx, A, B)
         try:
             if first == "distance":
@@ -161,6 +168,8 @@ def test_align_segments_known_and_unknown_k(ed, make_ctx, orc, engine):
         assert k == want
         assert st["rounds"] == want
         assert apply_script(ed, A, B, script) == k
+        cone = first == "distance" and form == "auto"
+        assert (st["align_segment_rounds"] == want) == cone
 
 
 def test_align_beyond_every_row_in_memory(ed, make_ctx):

@@ -164,6 +164,35 @@ def test_base_switch_after_prepare_on_side_stream(ed, make_ctx, orc):
     np.testing.assert_array_equal(TA, orc.horner_table(A, 32, orc.hash_base(501)))
 
 
+def test_release_right_after_prepare_on_side_stream(ed, make_ctx, orc):
+    # a pair released while its prepare is still queued on a stream that does
+    # not wait for the null stream: the release waits for that work, and the
+    # next pair, which reuses the pooled buffers, is exact
+    import torch
+    ctx = make_ctx(engine=ed.ENGINE_HASH, block=32, hash_seed=503)
+    side = torch.cuda.Stream()
+    A = synth.random_string(1 << 25, synth.CharDist("uniform", 4), 43)
+    B, _ = synth.plant_edits(A, 20, synth.CharDist("uniform", 4), 44)
+    tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    torch.cuda.synchronize()
+    for r in range(3):
+        say("release on side stream", r)
+        p = ed.ed_prepare(ctx, tA, tB, stream=side)
+        ed.ed_release(p)
+    C = synth.random_string(1 << 25, synth.CharDist("uniform", 4), 45)
+    D, _ = synth.plant_edits(C, 30, synth.CharDist("uniform", 4), 46)
+    tC, tD = torch.from_numpy(C).cuda(), torch.from_numpy(D).cuda()
+    torch.cuda.synchronize()
+    p = ed.ed_prepare(ctx, tC, tD, stream=side)
+    try:
+        TA = ed.ed_pair_buffer(ctx, p, 0, ed.BUF_TABLE)
+        k = ed.ed_distance(ctx, p, stream=side)
+    finally:
+        ed.ed_release(p)
+    np.testing.assert_array_equal(TA, orc.horner_table(C, 32, orc.hash_base(503)))
+    assert k == orc.lv_omp(C, D, -1, 1)
+
+
 @pytest.mark.parametrize("b,sigma", [(32, 4), (4096, 4), (32, 256), (64, 256)])
 def test_table_bit_exact_multi_chunk_scan(ed, make_ctx, orc, b, sigma):
     # more than 8192 tiles of 16384 characters: the scan of the tile hashes
@@ -499,18 +528,33 @@ def test_grid_rounds(ed, make_ctx, orc, case):
         assert st["grid_lcps"] > 0
 
 
-def test_grid_rounds_alignment(ed, make_ctx, orc):
-    # the per-round rows that the grid rounds write back are traced and checked
+@pytest.mark.parametrize("first", ["align", "distance"])
+def test_grid_rounds_alignment(ed, make_ctx, orc, first):
+    # the per-round rows that the grid rounds write back are traced and
+    # checked, in segments (a fresh pair) and in the cone of one launch (k known)
     ctx = make_ctx()
     A, B, _ = synth.single_pair(6_000_000, 7, 21)
     want = orc.lv_omp(A, B)
     p = ed.ed_prepare(ctx, A, B)
     try:
+        if first == "distance":
+            assert ed.ed_distance(ctx, p) == want
         k, script = ed.ed_align(ctx, p)
+        st = ed.ed_pair_stats(p)
     finally:
         ed.ed_release(p)
     assert k == want
+    assert st["grid_lcps"] > 0
     assert sum(ln for op, ln in script if op != ed.OP_MATCH) == k
+    x = y = 0
+    for op, ln in script:
+        if op == ed.OP_MATCH:
+            assert np.array_equal(A[x:x + ln], B[y:y + ln])
+        if op in (ed.OP_MATCH, ed.OP_SUB, ed.OP_DEL):
+            x += ln
+        if op in (ed.OP_MATCH, ed.OP_SUB, ed.OP_INS):
+            y += ln
+    assert (x, y) == (len(A), len(B))
 
 
 # ---------------------------------------------------------------------------
