@@ -63,14 +63,21 @@ __global__ __launch_bounds__(64) void traceback_kernel(const int32_t* dump, Keep
             return;
         }
         const int32_t R = amin(kTbRows, t0 - tb);
-        for (int32_t r = 0; r < R; ++r) {
+        // every row's load issued before any is stored to LDS (one memory
+        // latency per band, not one per row)
+        int32_t v[kTbRows];
+#pragma unroll
+        for (int32_t r = 0; r < kTbRows; ++r) {
             const int32_t u = t0 - 1 - r;
             const int32_t j = ic - 32 + lane;
             int32_t lo, hi;
-            int64_t off;
-            keep_row(L, u, lo, hi, off);
-            band[r][lane] = (j >= -u && j <= u && j >= lo && j <= hi) ? dump[off + (j - lo)] : kNone;
+            int64_t off = 0;
+            if (r < R) keep_row(L, u, lo, hi, off);
+            const bool in = r < R && j >= -u && j <= u && j >= lo && j <= hi;
+            v[r] = in ? dump[off + (j - lo)] : kNone;
         }
+#pragma unroll
+        for (int32_t r = 0; r < kTbRows; ++r) band[r][lane] = v[r];
         __syncthreads();
         if (lane == 0) {
             int32_t i = ic, f = sh[1];

@@ -568,6 +568,10 @@ __device__ __forceinline__ DumpAt dump_at(const FrontierParams& P, int32_t* dump
         if (static_cast<int64_t>(t + 1) * (t + 1) - base > P.dump_cap) return d;
         d.row = dump + (static_cast<int64_t>(t) * t - base);
     }
+    // the same for every lane: kept in scalar registers
+    d.row = reinterpret_cast<int32_t*>(uni(reinterpret_cast<uint64_t>(d.row)));
+    d.lo = uni(d.lo);
+    d.hi = uni(d.hi);
     return d;
 }
 
