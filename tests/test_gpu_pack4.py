@@ -219,3 +219,29 @@ def test_distances_4bit_single_batch_and_align(ed, make_ctx, orc):
         else:
             y += L; edits += L
     assert (x, y, edits) == (len(A), len(B), k)
+
+
+def test_serving_4bit_requests(ed, make_ctx, orc):
+    # requests over 16 symbols through the serving loop (the many-pair kernel
+    # reads the 4-bit words), mixed with requests over 4 symbols
+    ctx = make_ctx(engine=ed.ENGINE_DIRECT)
+    reqs = []
+    for i in range(24):
+        n = [300, 5000, 40000, 200000][i % 4]
+        d = D16 if i % 3 else D4
+        A = synth.random_string(n, d, 700 + i)
+        B, _ = synth.plant_edits(A, max(1, n // 200), d, 800 + i)
+        reqs.append((A, B))
+    say("serve 4-bit", len(reqs))
+    srv = ed.ed_serve_open(ctx, 8 << 30, 32)
+    try:
+        for tag, (A, B) in enumerate(reqs):
+            assert ed.ed_serve_submit(srv, A, B, tag) == 0, ed.ed_last_error()
+        ed.ed_serve_drain(srv)
+        res = ed.ed_serve_poll(srv, len(reqs) + 1)
+    finally:
+        ed.ed_serve_close(srv)
+    assert len(res) == len(reqs) and all(r["status"] == 0 for r in res)
+    got = {r["tag"]: r["k"] for r in res}
+    for tag, (A, B) in enumerate(reqs):
+        assert got[tag] == orc.lv_omp(A, B, -1, 1), tag
