@@ -35,8 +35,11 @@ constexpr size_t kMiscAlpha = 64;
 constexpr uint32_t kDefaultLdsRounds = 512;
 constexpr uint32_t kDefaultBlockRounds = 64;
 // many-pair kernel, when neither its own knob nor the single-pair one is set
+// (a chunk task of 128 rounds: at 32 one n = 1e7, k = 1.8e5 pair took 864 ms
+// in this kernel, at 128 500 ms; 4096 small pairs and the serving traces are
+// faster too)
 constexpr uint32_t kTaskDefaultLdsRounds = 1024;
-constexpr uint32_t kTaskDefaultBlockRounds = 32;
+constexpr uint32_t kTaskDefaultBlockRounds = 128;
 constexpr int32_t kChunkDiags = 2048;  // diagonals per chunk task
 // a wait of the frontier kernel on another workgroup or wavefront gives up
 // after 600 s of the 100 MHz real-time clock (the launch then reports an
