@@ -59,6 +59,9 @@ struct RoundShared {
     int32_t flag;
     int32_t pair;
     long long task;
+    int32_t sched;                // task kernel: this workgroup schedules a super-step
+    int32_t nsched;               // ... of this many chunk tasks
+    unsigned long long qbase;     // ... from this position of the ring
 };
 
 struct LdsState {
@@ -620,35 +623,48 @@ __device__ __forceinline__ void pair_finish(const TaskParams& P, TaskPair* S, in
     __hip_atomic_fetch_add(P.remaining, -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One thread: schedule the next super-step of pair pi (f_t in row S->cur).
-__device__ void schedule_superstep(const TaskParams& P, TaskPair* S, int32_t pi) {
-    const int32_t t = S->t;
-    int32_t H = imin(P.block_rounds, S->K - t);
-    H = imin(H, (kLdsRowLen - P.chunk_diags) / 2);  // window of a chunk must fit an LDS row
-    const int32_t kmax = S->kmax;
-    if (kmax >= 0) H = imin(H, kmax - t);
-    H = imin(H, S->t_limit - t);
-    if (H <= 0) {
-        if (kmax >= 0 && t >= kmax) pair_finish(P, S, 2, kmax + 1);
-        else if (t >= S->t_limit) pair_finish(P, S, 5, 0);
-        else pair_finish(P, S, 3, t);
-        return;
+// The next super-step of pair pi (f_t in row S->cur), or its result.  Every
+// thread of the workgroup calls it: thread 0 takes the decision and reserves
+// the ring positions, then the threads push the chunk tasks side by side (one
+// position each), so that a super-step of many chunks costs one round trip to
+// the ring rather than one per chunk.
+__device__ void schedule_superstep(const TaskParams& P, TaskPair* S, int32_t pi, RoundShared& RS) {
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        RS.nsched = 0;
+        const int32_t t = S->t;
+        int32_t H = imin(P.block_rounds, S->K - t);
+        H = imin(H, (kLdsRowLen - P.chunk_diags) / 2);  // window of a chunk must fit an LDS row
+        const int32_t kmax = S->kmax;
+        if (kmax >= 0) H = imin(H, kmax - t);
+        H = imin(H, S->t_limit - t);
+        if (H <= 0) {
+            if (kmax >= 0 && t >= kmax) pair_finish(P, S, 2, kmax + 1);
+            else if (t >= S->t_limit) pair_finish(P, S, 5, 0);
+            else pair_finish(P, S, 3, t);
+        } else {
+            const int32_t T = t + H;
+            const int32_t total = 2 * T + 5;
+            const int32_t C = P.chunk_diags;
+            const int32_t nch = (total + C - 1) / C;
+            S->H = H;
+            S->T = T;
+            S->chunk = C;
+            S->nchunks = nch;
+            S->chunks_left = nch;
+            S->found_t = INT_MAX;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            RS.qbase = atomicAdd(P.qtail, static_cast<unsigned long long>(nch));
+            RS.nsched = nch;
+        }
     }
-    const int32_t T = t + H;
-    const int32_t total = 2 * T + 5;
-    const int32_t C = P.chunk_diags;
-    const int32_t nch = (total + C - 1) / C;
-    S->H = H;
-    S->T = T;
-    S->chunk = C;
-    S->nchunks = nch;
-    S->chunks_left = nch;
-    S->found_t = INT_MAX;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const unsigned long long base = atomicAdd(P.qtail, static_cast<unsigned long long>(nch));
-    for (int32_t c = 0; c < nch; ++c)
-        q_push(P, static_cast<long long>(static_cast<uint32_t>(pi)) |
-                      (static_cast<long long>(c + 1) << 32), base + c);
+    __syncthreads();
+    const int32_t nch = RS.nsched;
+    const unsigned long long base = RS.qbase;
+    for (int32_t c = tid; c < nch; c += static_cast<int32_t>(blockDim.x))
+        q_push(P, static_cast<long long>(static_cast<uint32_t>(pi)) | (static_cast<long long>(c + 1) << 32),
+               base + static_cast<unsigned long long>(c));
+    __syncthreads();
 }
 
 template <int KIND>
@@ -697,12 +713,11 @@ __device__ void solo_task(const TaskParams& P, int32_t pi, LdsState& L, JobCurso
         }
     }
     __syncthreads();
-    if (tid == 0) {
-        S->t = t;
-        if (status != 0)
-            pair_finish(P, S, status, result);
-        else
-            schedule_superstep(P, S, pi);
+    if (tid == 0) S->t = t;
+    if (status != 0) {
+        if (tid == 0) pair_finish(P, S, status, result);
+    } else {
+        schedule_superstep(P, S, pi, RS);
     }
 }
 
@@ -743,6 +758,7 @@ __device__ void chunk_task(const TaskParams& P, int32_t pi, int32_t c, LdsState&
     for (int32_t i = a + tid; i <= b; i += nthr) gc[i + gofs] = rp[i + wofs];
     __syncthreads();
     if (tid == 0) {
+        int32_t next = 0;
         const int32_t left = __hip_atomic_fetch_add(&S->chunks_left, -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (left == 1) {
             // every chunk of the super-step is in: f_T is in row cur ^ 1
@@ -753,9 +769,12 @@ __device__ void chunk_task(const TaskParams& P, int32_t pi, int32_t c, LdsState&
             if (ft <= T)
                 pair_finish(P, S, 1, ft);
             else
-                schedule_superstep(P, S, pi);
+                next = 1;
         }
+        RS.sched = next;
     }
+    __syncthreads();
+    if (RS.sched) schedule_superstep(P, S, pi, RS);
 }
 
 __device__ __forceinline__ uint64_t clock_now() { return __builtin_amdgcn_s_memrealtime(); }
