@@ -342,12 +342,12 @@ int ed_autotune_batch(ed_ctx* c, ed_pair* const* pairs, uint64_t count, int64_t 
     double best_ms = default_ms;
     static const uint32_t kLds[] = {64, 128, 256, 512, 1024, 2048, 4096};
     static const uint32_t kBlock[] = {8, 16, 32, 64, 128, 256};
-    static const uint32_t kChunk[] = {512, 1024, 2048, 4096, 6144};
+    static const uint32_t kChunk[] = {512, 1024, 1536, 1792, 2048, 4096, 6144};
     for (uint32_t pass = 0; pass < passes; ++pass) {
         bool moved = false;
         for (int knob = 0; knob < 3; ++knob) {
             const uint32_t* vals = knob == 0 ? kLds : knob == 1 ? kBlock : kChunk;
-            const int nv = knob == 0 ? 7 : knob == 1 ? 6 : 5;
+            const int nv = knob == 0 ? 7 : knob == 1 ? 6 : 7;
             for (int v = 0; v < nv; ++v) {
                 ed_options cand = best;
                 uint32_t& field = knob == 0 ? cand.task_lds_rounds

@@ -40,7 +40,9 @@ constexpr uint32_t kDefaultBlockRounds = 64;
 // faster too)
 constexpr uint32_t kTaskDefaultLdsRounds = 1024;
 constexpr uint32_t kTaskDefaultBlockRounds = 128;
-constexpr int32_t kChunkDiags = 2048;  // diagonals per chunk task
+// diagonals per chunk task: with a halo of H = 128 per side a chunk's window
+// stays within one pass of the 1024-thread workgroup (2 diagonals per thread)
+constexpr int32_t kChunkDiags = 1536;
 // a wait of the frontier kernel on another workgroup or wavefront gives up
 // after 600 s of the 100 MHz real-time clock (the launch then reports an
 // error): far beyond any wait of a working launch, so that only a launch that
