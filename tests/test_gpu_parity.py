@@ -628,6 +628,31 @@ def test_autotune_batch(ed, make_ctx, orc, engine):
         ed.ed_release(p)
 
 
+def test_batch_superstep_wider_than_workgroup(ed, make_ctx, orc):
+    # 64-diagonal chunks: the late super-steps of the large pair hold more
+    # chunk tasks than the workgroup that schedules them has threads, so each
+    # thread pushes several; the rows the batch reserves (n / 16 rounds) hold
+    # the whole distance, so the pair stays in the many-pair kernel
+    ctx = make_ctx(engine=0)
+    A, B, _ = synth.single_pair(700000, 40000, 31)
+    want = [orc.lv_omp(A, B)]
+    assert (2 * want[0] + 5 + 63) // 64 > 1024 and want[0] <= len(A) // 16
+    pairs = [ed.ed_prepare(ctx, A, B)]
+    for n, k, ps in synth.batch_specs(40, 23, lo_exp=3.0, hi_exp=5.0, kfrac=0.05):
+        A2, B2, _ = synth.single_pair(n, k, ps)
+        pairs.append(ed.ed_prepare(ctx, A2, B2))
+        want.append(orc.lv_omp(A2, B2))
+    say("batch, 64-diagonal chunks", len(pairs))
+    ed.ed_set_options(ctx, engine=0, chunk_diags=64, task_block_rounds=16)
+    try:
+        got, st = ed.ed_batch(ctx, pairs)
+    finally:
+        for p in pairs:
+            ed.ed_release(p)
+    assert st == [0] * len(pairs)
+    assert got == want
+
+
 def test_device_inputs_and_unaligned(ed, make_ctx, orc):
     import torch
     ctx = make_ctx()
