@@ -207,6 +207,11 @@ int ed::ctx_set_hash(ed_ctx* c, uint64_t r) {
     }
     for (int l = 0; l < 64; ++l) rt[kRtabR8lane + l] = hpow(R, 8ull * (l + 1));
     for (int d = 0; d < 64; ++d) rt[kRtabRChunk + d] = hpow(R, 2048ull * d);
+    a = 1;
+    for (int j = 0; j < kScanChunkTiles; ++j) {
+        rt[kRtabRTile + j] = a;
+        a = hmul(a, R);
+    }
     const uint64_t rinv = hpow(r, kP - 2);
     a = 1;
     for (int d = 0; d < 33; ++d) {

@@ -200,7 +200,8 @@ struct PrepParams {
     int32_t fuse_table;    // block size 32: pack_kernel takes the block hashes (the first table pass)
     uint64_t r;            // hash base
     uint64_t* tile_agg;    // total_tiles entries: hash of each tile
-    uint64_t* tile_prefix; // total_tiles entries: hash of its string before each tile
+    uint64_t* tile_prefix; // total_tiles entries: hash of its string before each tile (b = 32: of
+                           // the tile's chunk of 2048 tiles before it)
     uint64_t* chunk_tot;   // per chunk of 2048 tiles of each string: its hash (prefix scan)
     uint64_t* lane_excl;   // 64 per tile: hash of the tile's characters before each lane's 256
     uint32_t* alpha;       // OR of all characters (written by after_pack_kernel)
@@ -222,7 +223,7 @@ struct PrepParams {
 //   R^(8 * 2^j), j = 0..9 | R^(8 (l + 1)), l = 0..63 | r^(-d), d = 0..32 |
 //   per lane l = 0..63 the 16 int8 of its A operand of the block-hash matrix
 //   product (two entries) | the constant term of that product |
-//   R^(2048 d), d = 0..63
+//   R^(2048 d), d = 0..63 | R^j, j = 0..2047
 constexpr int kRtabRseg = 65;
 constexpr int kRtabR = kRtabRseg + 257;
 constexpr int kRtabLut32 = kRtabR + 65;
@@ -234,7 +235,8 @@ constexpr int kRtabRinv32 = kRtabR8lane + 64;
 constexpr int kRtabMmaA = kRtabRinv32 + 34;  // 16-byte aligned
 constexpr int kRtabMmaK = kRtabMmaA + 128;
 constexpr int kRtabRChunk = kRtabMmaK + 1;
-constexpr int kRtabEntries = kRtabRChunk + 64;
+constexpr int kRtabRTile = kRtabRChunk + 64;
+constexpr int kRtabEntries = kRtabRTile + kScanChunkTiles;
 
 struct LcpQueryParams {
     PairDev p;

@@ -517,13 +517,16 @@ __device__ __forceinline__ void table_tiles(const PrepParams& P, TableShared& S,
 }
 
 // Block size 32: the emission pass from the block hashes pack_kernel stored
-// in T (the characters are not read again).  Per tile the 512 entries come
-// through the wavefront's staging slots, each lane turns the 8 of its 256
-// characters into prefix values, starting from the prefix hash at its first
-// character, and they go back to T, 64 consecutive entries per store.  The
-// next tile's entries are requested before this tile's arithmetic.  A kernel
-// of its own: few registers and little LDS, so that many wavefronts keep
-// loads in flight.
+// in T (the characters are not read again).  The hash of the string before a
+// tile is that of the string before its chunk (c chunks of 2048 tiles before
+// it: sum over them of tot(q) R^(2048 (c - 1 - q)), one term per lane) times
+// R^j (j = the tile's place in its chunk) plus the in-chunk prefix that
+// after_pack_kernel stored.  Per tile the 512 entries come through the
+// wavefront's staging slots, each lane turns the 8 of its 256 characters
+// into prefix values, starting from the prefix hash at its first character,
+// and they go back to T, 64 consecutive entries per store.  The next tile's
+// entries are requested before this tile's arithmetic.  A kernel of its own:
+// few registers and little LDS, so that many wavefronts keep loads in flight.
 __global__ __launch_bounds__(kPrepThreads) void table_emit_kernel(PrepParams P, const uint64_t* rtab) {
     __shared__ uint64_t stage[kPrepThreads / 64][64 * 9];
     const int tid = threadIdx.x;
@@ -534,23 +537,38 @@ __global__ __launch_bounds__(kPrepThreads) void table_emit_kernel(PrepParams P, 
     uint64_t* st = &stage[tid >> 6][0];
     const uint64_t r32 = rtab[32];
     const uint64_t rlane = rtab[kRtabRseg + 4 * lane];  // r^(256 lane)
+    const int32_t first1 = (P.s[1].tile0 + kScanChunkTiles - 1) / kScanChunkTiles;  // string 1's chunk 0
     uint64_t cur[8], nxt[8];
-    uint64_t pre = 0, ex = 0, npre = 0, nex = 0;
-    auto fetch = [&](int32_t g, uint64_t (&e)[8], uint64_t& tp, uint64_t& le) {
-        const StrSel str(P, g >= P.s[1].tile0);
-        const int32_t base = (g - str.tile0) * (kTileChars / 32) + 1;
+    // per tile: in-chunk prefix, this lane's term of the string before the
+    // chunk and its power, R^j, this lane's in-tile prefix
+    uint64_t loc = 0, ct = 0, cw = 0, rj = 0, ex = 0;
+    uint64_t nloc = 0, nct = 0, ncw = 0, nrj = 0, nex = 0;
+    auto fetch = [&](int32_t g, uint64_t (&e)[8], uint64_t& lo, uint64_t& t, uint64_t& w, uint64_t& r,
+                     uint64_t& le) {
+        const bool second = g >= P.s[1].tile0;
+        const StrSel str(P, second);
+        const int32_t tt = g - str.tile0;
+        const int32_t base = tt * (kTileChars / 32) + 1;
         const int32_t last = str.len >> 5;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int32_t i = k * 64 + lane;
             e[k] = base + i <= last ? str.tab[base + i] : 0;
         }
-        tp = P.tile_prefix[g];
+        const int32_t c = tt / kScanChunkTiles;
+        lo = P.tile_prefix[g];
+        t = lane < c ? P.chunk_tot[(second ? first1 : 0) + lane] : 0;
+        w = lane < c ? rtab[kRtabRChunk + (c - 1 - lane)] : 0;
+        r = rtab[kRtabRTile + (tt - c * kScanChunkTiles)];
         le = P.lane_excl[static_cast<int64_t>(g) * 64 + lane];
     };
-    if (gw < total) fetch(gw, cur, pre, ex);
+    if (gw < total) fetch(gw, cur, loc, ct, cw, rj, ex);
     for (int32_t g = gw; g < total; g += W) {
-        if (g + W < total) fetch(g + W, nxt, npre, nex);
+        if (g + W < total) fetch(g + W, nxt, nloc, nct, ncw, nrj, nex);
+        uint64_t cy = mp_mul(ct, cw);
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) cy = mp_add(cy, __shfl_xor(static_cast<unsigned long long>(cy), d));
+        const uint64_t pre = mp_add(mp_mul(cy, rj), loc);
         const StrSel str(P, g >= P.s[1].tile0);
         const int32_t t = g - str.tile0;
         const int32_t base = t * (kTileChars / 32) + 1;
@@ -577,7 +595,10 @@ __global__ __launch_bounds__(kPrepThreads) void table_emit_kernel(PrepParams P, 
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int k = 0; k < 8; ++k) cur[k] = nxt[k];
-        pre = npre;
+        loc = nloc;
+        ct = nct;
+        cw = ncw;
+        rj = nrj;
         ex = nex;
     }
 }
@@ -609,12 +630,13 @@ __global__ __launch_bounds__(kPrepThreads) void table_tiles_kernel(PrepParams P,
 
 // Pass 2: prefix[u] = h(S[0 .. 16384 u)) from the tile hashes, with
 // R = r^16384, in chunks of kScanChunk tiles, one workgroup per chunk of each
-// string (the chunks of string 0 first), in two launches: chunk_total (in
-// after_pack_kernel at b = 32, else table_total_kernel) folds each chunk to
-// its hash (Horner's rule), table_scan_kernel takes the
-// hash of the string before its chunk from those of the earlier chunks (one
-// term per lane, times R^(kScanChunk d), summed over the wavefront) and scans
-// its chunk with it.  Within a chunk each thread folds 8 consecutive tiles,
+// string (the chunks of string 0 first).  Other block sizes, two launches:
+// table_total_kernel folds each chunk to its hash (Horner's rule),
+// table_scan_kernel takes the hash of the string before its chunk from those
+// of the earlier chunks (one term per lane, times R^(kScanChunk d), summed
+// over the wavefront) and scans its chunk with it.  At b = 32
+// after_pack_kernel scans each chunk from zero and stores its hash, and the
+// emission pass adds the string before the chunk.  Within a chunk each thread folds 8 consecutive tiles,
 // the threads' values are combined by inclusive scans under
 // x(l) = x(l - d) R^(8 d) + x(l) within each wavefront and then over the
 // wavefronts.  The last chunk is zero-padded: its hash is never used and
@@ -686,7 +708,13 @@ __global__ __launch_bounds__(kScanThreads) void table_total_kernel(PrepParams P,
     chunk_total(P, rtab);
 }
 
-__global__ __launch_bounds__(kScanThreads) void table_scan_kernel(PrepParams P, const uint64_t* rtab) {
+// The scan of one chunk (the workgroup's) to the prefix hash before each of
+// its tiles (tile_prefix).  CARRY: the prefix includes the string before the
+// chunk, taken from the totals of the earlier chunks (complete before this
+// launch).  Otherwise the values start from zero at the chunk (the emission
+// pass adds the string before the chunk) and the chunk's total is stored too.
+template <bool CARRY>
+__device__ __forceinline__ void scan_chunk_tiles(const PrepParams& P, const uint64_t* rtab) {
     __shared__ uint64_t buf[kScanChunk];
     __shared__ uint64_t wtot[kScanWaves];
     __shared__ uint64_t wpre[kScanWaves];  // prefix before each wavefront's tiles
@@ -702,9 +730,12 @@ __global__ __launch_bounds__(kScanThreads) void table_scan_kernel(PrepParams P, 
     if (wave == 0) {
         // the string before the chunk: sum over earlier chunks i of
         // tot(i) R^(kScanChunk (c - 1 - i)) (at most 64 chunks per string)
-        uint64_t cy = lane < k.c ? mp_mul(P.chunk_tot[k.first + lane], rtab[kRtabRChunk + (k.c - 1 - lane)]) : 0;
+        uint64_t cy = 0;
+        if constexpr (CARRY) {
+            cy = lane < k.c ? mp_mul(P.chunk_tot[k.first + lane], rtab[kRtabRChunk + (k.c - 1 - lane)]) : 0;
 #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) cy = mp_add(cy, __shfl_xor(static_cast<unsigned long long>(cy), d));
+            for (int d = 1; d < 64; d <<= 1) cy = mp_add(cy, __shfl_xor(static_cast<unsigned long long>(cy), d));
+        }
         // over the wavefronts (512 tiles each), the carry ahead of the first
         uint64_t x = lane < kScanWaves ? wtot[lane] : 0;
         if (lane == 0) x = mp_add(mp_mul(cy, R8p[6]), x);
@@ -715,6 +746,11 @@ __global__ __launch_bounds__(kScanThreads) void table_scan_kernel(PrepParams P, 
         }
         const uint64_t xp = __shfl_up(static_cast<unsigned long long>(x), 1);
         if (lane < kScanWaves) wpre[lane] = lane == 0 ? cy : xp;
+        // without the carry the last wavefront's inclusive value is the
+        // chunk's hash (the padding of a last chunk is never used)
+        if constexpr (!CARRY) {
+            if (lane == kScanWaves - 1) P.chunk_tot[blockIdx.x] = x;
+        }
     }
     __syncthreads();
     const uint64_t pw = wpre[wave];
@@ -729,6 +765,10 @@ __global__ __launch_bounds__(kScanThreads) void table_scan_kernel(PrepParams P, 
     __syncthreads();
     uint64_t* pre = P.tile_prefix + k.tile0 + k.c * kScanChunk;
     for (int i = tid; i < k.cn; i += kScanThreads) pre[i] = buf[i];
+}
+
+__global__ __launch_bounds__(kScanThreads) void table_scan_kernel(PrepParams P, const uint64_t* rtab) {
+    scan_chunk_tiles<true>(P, rtab);
 }
 
 // Second pass, once the pair's alphabet is known: the layout it is read in
@@ -784,7 +824,8 @@ __device__ __forceinline__ void rest_pass(const PrepParams& P, uint32_t alpha, u
 // per-workgroup slots to the pair's alphabet OR and chunk classes (workgroup
 // 0 stores them for the later kernels and the host), runs the rest pass, and
 // with block hashes taken by the pack kernel the first scan_chunks workgroups
-// also fold their chunk of tile hashes (the first pass of the scan below).
+// also scan their chunk of tile hashes from zero and store its total; the
+// emission pass adds the part of the string before the chunk.
 __global__ __launch_bounds__(kPrepThreads) void after_pack_kernel(PrepParams P, const uint64_t* rtab) {
     __shared__ uint32_t red[kPrepThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63;
@@ -801,7 +842,7 @@ __global__ __launch_bounds__(kPrepThreads) void after_pack_kernel(PrepParams P, 
         *P.packed_any = classes;
     }
     rest_pass(P, alpha, classes);
-    if (P.fuse_table && static_cast<int32_t>(blockIdx.x) < P.scan_chunks) chunk_total(P, rtab);
+    if (P.fuse_table && static_cast<int32_t>(blockIdx.x) < P.scan_chunks) scan_chunk_tiles<false>(P, rtab);
 }
 
 __global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
@@ -832,9 +873,11 @@ hipError_t launch_table(const PrepParams& pp, int grid, hipStream_t s) {
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(table_scan_kernel, dim3(chunks), dim3(kScanThreads), 0, s, pp, pp.rtab);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (!pp.fuse_table) {  // else after_pack_kernel scanned each chunk from zero
+        hipLaunchKernelGGL(table_scan_kernel, dim3(chunks), dim3(kScanThreads), 0, s, pp, pp.rtab);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     if (pp.fuse_table)
         hipLaunchKernelGGL(table_emit_kernel, dim3(2 * grid), dim3(kPrepThreads), 0, s, pp, pp.rtab);
     else if (pp.log2b <= 2)
