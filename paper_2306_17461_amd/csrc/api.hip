@@ -376,11 +376,12 @@ void ed::pair_free(ed_pair* p) {
         (void)hipEventDestroy(p->ev_done);
         p->ev_done = nullptr;
     }
-    for (void** q : {&p->w2[0], &p->w2[1], &p->w4[0], &p->w4[1], &p->w8[0], &p->w8[1], &p->tab[0], &p->tab[1], &p->misc,
+    for (void** q : {&p->w2[0], &p->w2[1], &p->w4[0], &p->w4[1], &p->w8[0], &p->w8[1], &p->tab_blk[0], &p->tab_blk[1], &p->misc,
                      &p->stage[0], &p->stage[1], &p->f0, &p->f1}) {
         pool.put(*q);
         *q = nullptr;
     }
+    p->tab[0] = p->tab[1] = nullptr;
 }
 
 PairDev ed::pair_dev(const ed_pair* p) {
@@ -450,7 +451,10 @@ int ed::prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B
         p->w2[s2] = c->pool.get((static_cast<size_t>(tiles[s2]) * kTileWords2 + kPadWords) * 8);
         p->w8[s2] = c->pool.get((static_cast<size_t>(tiles[s2]) * kTileWords8 + kPadWords) * 8);
         if (nib) p->w4[s2] = c->pool.get((static_cast<size_t>(tiles[s2]) * kTileWords4 + kPadWords) * 8);
-        if (table) p->tab[s2] = c->pool.get(((len >> p->log2b) + 1) * 8);
+        if (table) {
+            p->tab_blk[s2] = c->pool.get(((len >> p->log2b) + 1) * 8 + kTabShift);
+            if (p->tab_blk[s2]) p->tab[s2] = static_cast<char*>(p->tab_blk[s2]) + kTabShift;
+        }
         if (!p->w2[s2] || !p->w8[s2] || (nib && !p->w4[s2]) || (table && !p->tab[s2])) {
             pair_free(p);
             delete p;

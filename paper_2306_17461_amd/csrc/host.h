@@ -27,6 +27,10 @@ class DevPool {
 
 // pow0 (65536) | pow1 (65536) | r^0..r^64 | r^(64k), k = 0..256 | R^d, d = 0..64
 constexpr size_t kPowEntries = 2 * 65536 + kRtabEntries;
+// a prefix table starts 248 bytes into its block, so that T[1] and with it the
+// entries of every tile's blocks (T[512 t + 1 .. 512 t + 512] at b = 32) fill
+// whole cache lines: the table passes read and write them 512 bytes at a time
+constexpr size_t kTabShift = 248;
 
 // layout of a pair's small device block
 constexpr size_t kMiscAlpha = 64;
@@ -81,7 +85,8 @@ struct ed_pair {
     void* w2[2] = {nullptr, nullptr};
     void* w4[2] = {nullptr, nullptr};  // direct engine with automatic packing only
     void* w8[2] = {nullptr, nullptr};
-    void* tab[2] = {nullptr, nullptr};
+    void* tab[2] = {nullptr, nullptr};      // prefix tables: T[0] of each string
+    void* tab_blk[2] = {nullptr, nullptr};  // their pool blocks (T[0] at kTabShift)
     void* stage[2] = {nullptr, nullptr};
     void* misc = nullptr;  // alphabet word, tile hashes and prefixes, chunk flags
     void* f0 = nullptr;    // unused (rows are per call)
