@@ -216,8 +216,9 @@ __global__ __launch_bounds__(kPrepThreads) void pack_kernel(PrepParams P) {
             uint32_t* dst = reinterpret_cast<uint32_t*>(str.w2 + static_cast<int64_t>(c) * kChunkWords2);
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                dst[k * 64 + (off >> 4)] = pack_dword(v[k].x) | (pack_dword(v[k].y) << 8) | (pack_dword(v[k].z) << 16) |
-                                           (pack_dword(v[k].w) << 24);
+                __builtin_nontemporal_store(pack_dword(v[k].x) | (pack_dword(v[k].y) << 8) |
+                                                (pack_dword(v[k].z) << 16) | (pack_dword(v[k].w) << 24),
+                                            dst + k * 64 + (off >> 4));
         } else if (nib) {
             uint64_t* dst = str.w4 + static_cast<int64_t>(c) * kChunkWords4;
 #pragma unroll
@@ -228,7 +229,7 @@ __global__ __launch_bounds__(kPrepThreads) void pack_kernel(PrepParams P) {
         if ((big && !nib) || P.force8) {
             u32x4* dst = reinterpret_cast<u32x4*>(str.w8 + static_cast<int64_t>(c) * kChunkWords8);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) dst[k * 64 + (off >> 4)] = v[k];
+            for (int k = 0; k < 4; ++k) __builtin_nontemporal_store(v[k], dst + k * 64 + (off >> 4));
         }
         const uint32_t cls = !big ? 0u : (nib ? 1u : 2u);
         if (lane == 0) P.chunk_big[str.tile0 * kTileChunks + c] = static_cast<uint8_t>(cls);
