@@ -522,6 +522,7 @@ int ed::prepare_locked(ed_ctx* c, const uint8_t* A, uint64_t n, const uint8_t* B
     pp.total_tiles = total;
     pp.log2b = p->log2b;
     pp.force8 = p->force8;
+    pp.nt_copy = p->len[0] + p->len[1] > kNtCopyBytes ? 1 : 0;
     pp.build_table = table ? 1 : 0;
     pp.fuse_table = table && p->log2b == 5 ? 1 : 0;
     pp.r = c->r;

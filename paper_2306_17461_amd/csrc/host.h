@@ -31,6 +31,14 @@ constexpr size_t kPowEntries = 2 * 65536 + kRtabEntries;
 // entries of every tile's blocks (T[512 t + 1 .. 512 t + 512] at b = 32) fill
 // whole cache lines: the table passes read and write them 512 bytes at a time
 constexpr size_t kTabShift = 248;
+// the pack kernel writes the packed words and the 8-bit copy with
+// non-temporal stores when the pair's input exceeds the 256 MiB memory-side
+// cache (MALL; a variant of the kernel of its own): packed strings
+// that fit stay there for the frontier's reads (with every packed word and
+// copy stored non-temporally the frontier of the n = 1e8 pairs at k = 1e5 took
+// 178-181 ms at 2 bits and 250 ms at 8 bits, against 168-171 and 236-239 ms,
+// measured on one device), a copy that does not fit only evicts other lines
+constexpr uint64_t kNtCopyBytes = 256ull << 20;
 
 // layout of a pair's small device block
 constexpr size_t kMiscAlpha = 64;

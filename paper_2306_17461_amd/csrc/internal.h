@@ -196,6 +196,7 @@ struct PrepParams {
     int32_t total_tiles;
     int32_t log2b;
     int32_t force8;        // write 8-bit copies of every tile
+    int32_t nt_copy;       // packed words and 8-bit copy with non-temporal stores (a pair larger than the MALL)
     int32_t build_table;
     int32_t fuse_table;    // block size 32: pack_kernel takes the block hashes (the first table pass)
     uint64_t r;            // hash base

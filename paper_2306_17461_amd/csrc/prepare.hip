@@ -157,6 +157,19 @@ __device__ __forceinline__ i32x4 as_i32x4(u32x4 v, uint32_t x) {
 // writes over it, and, as the first table pass does for other block sizes,
 // folds the 8 blocks of each lane's 256 characters and stores the in-tile
 // prefix of each lane (lane_excl) and the tile's hash (tile_agg).
+// A store of the packed words or the 8-bit copy: non-temporal for a pair
+// larger than the memory-side cache (nothing reads it again before the
+// frontier, and it would only evict other lines), else an ordinary store
+// (the lines stay for the frontier's first reads).
+template <bool NT, typename T>
+__device__ __forceinline__ void pack_store(T* p, T v) {
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
+template <bool NT>
 __global__ __launch_bounds__(kPrepThreads) void pack_kernel(PrepParams P) {
     __shared__ uint64_t stage[kPrepThreads / 64][64 * 9];
     const int lane = threadIdx.x & 63;
@@ -216,9 +229,8 @@ __global__ __launch_bounds__(kPrepThreads) void pack_kernel(PrepParams P) {
             uint32_t* dst = reinterpret_cast<uint32_t*>(str.w2 + static_cast<int64_t>(c) * kChunkWords2);
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                __builtin_nontemporal_store(pack_dword(v[k].x) | (pack_dword(v[k].y) << 8) |
-                                                (pack_dword(v[k].z) << 16) | (pack_dword(v[k].w) << 24),
-                                            dst + k * 64 + (off >> 4));
+                pack_store<NT>(dst + k * 64 + (off >> 4), pack_dword(v[k].x) | (pack_dword(v[k].y) << 8) |
+                                                              (pack_dword(v[k].z) << 16) | (pack_dword(v[k].w) << 24));
         } else if (nib) {
             uint64_t* dst = str.w4 + static_cast<int64_t>(c) * kChunkWords4;
 #pragma unroll
@@ -229,7 +241,7 @@ __global__ __launch_bounds__(kPrepThreads) void pack_kernel(PrepParams P) {
         if ((big && !nib) || P.force8) {
             u32x4* dst = reinterpret_cast<u32x4*>(str.w8 + static_cast<int64_t>(c) * kChunkWords8);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) __builtin_nontemporal_store(v[k], dst + k * 64 + (off >> 4));
+            for (int k = 0; k < 4; ++k) pack_store<NT>(dst + k * 64 + (off >> 4), v[k]);
         }
         const uint32_t cls = !big ? 0u : (nib ? 1u : 2u);
         if (lane == 0) P.chunk_big[str.tile0 * kTileChunks + c] = static_cast<uint8_t>(cls);
@@ -853,7 +865,10 @@ __global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
 }
 
 hipError_t launch_pack(const PrepParams& pp, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(pack_kernel, dim3(grid), dim3(kPrepThreads), 0, s, pp);
+    if (pp.nt_copy)
+        hipLaunchKernelGGL(pack_kernel<true>, dim3(grid), dim3(kPrepThreads), 0, s, pp);
+    else
+        hipLaunchKernelGGL(pack_kernel<false>, dim3(grid), dim3(kPrepThreads), 0, s, pp);
     return hipGetLastError();
 }
 
