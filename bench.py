@@ -735,7 +735,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: --gpus %d is not supported "
-              "(pairs shard across GPUs without communication; see the design notes)" % args.gpus,
+              "(pairs shard across GPUs without communication)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 

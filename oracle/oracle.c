@@ -8,8 +8,7 @@
  * CPU-baseline leg of the benchmark.  It shares no code with the HIP library:
  * no headers, helpers, tables or constants.
  *
- * Conventions (one reading applied throughout, listed with the others in the
- * design notes):
+ * Conventions (one reading applied throughout):
  *   - strings are 0-based byte arrays A[0..n), B[0..m);
  *   - a grid cell (x, y) means "x chars of A and y chars of B consumed";
  *   - diagonal i = x - y;
@@ -282,7 +281,7 @@ int64_t orc_lcp(const uint8_t *A, int64_t n, const uint8_t *B, int64_t m, int64_
 /*           x = f_{t-1}[j] + dx;  y = x - i;                               */
 /*           x = x + LCP(x, y);                                             */
 /*           f_t[i] = max(f_t[i], x).                                       */
-/* Readings where the listing is silent (also in the design notes):         */
+/* Readings where the listing is silent:                                    */
 /*   - a diagonal that did not exist in round t-1 starts at ORC_NONE;       */
 /*   - only diagonals with a grid cell, i in [max(-t,-m), min(t,n)], are    */
 /*     processed; the rest stay ORC_NONE;                                   */
